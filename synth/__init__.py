@@ -1,0 +1,27 @@
+"""Seeded synthetic inputs shared by the GPU path and the CPU oracle.
+
+This package builds triangulated polyhedral surfaces (the input of the
+capacity problem, Section 2.1 of the paper: conforming triangulations of a
+closed polyhedral boundary into plane triangles), refines them with newest
+vertex bisection (Fig. "nvb", Algorithm step (iv)) and draws seeded request
+streams.  It contains none of the method's arithmetic (no quadrature, no
+integral operator, no solver), so both sides can use it without sharing any
+computation.
+"""
+
+from .meshes import (  # noqa: F401
+    Mesh,
+    box,
+    convex_hull,
+    cube,
+    icosphere,
+    mesh_topology_ok,
+    voxel_union,
+)
+from .nvb import (  # noqa: F401
+    init_reference_edges,
+    refine_nvb,
+    refine_to_size,
+    refine_uniform,
+)
+from .requests import Request, request_stream  # noqa: F401
