@@ -1,0 +1,269 @@
+/*
+ * bemcap.h -- C ABI of the MI355X (gfx950) library for the P0 Galerkin
+ * boundary element computation of the electrostatic capacity of a
+ * polyhedron (Betcke, Haberl, Praetorius: "Adaptive boundary element methods
+ * for the computation of the electrostatic capacity on complex polyhedra").
+ *
+ * Problem (Section 1.4, eqs. "laplace_integral" and "cap"; Section 2.7,
+ * eq. "cap:ell"; the primal P0 Galerkin system of Appendix A,
+ * eq. "discreteform:residual"):
+ *
+ *   V[i][j] = (1/4pi) int_{T_i} int_{T_j} 1/|x - y| dy dx,
+ *   b[i]    = |T_i|,     V sigma = b,     Cap = (1/4pi) sum_i sigma_i |T_i|.
+ *
+ * Conventions shared by every call
+ *   - All functions are extern "C", reentrant, and keep no state between
+ *     calls.  The library never allocates device memory: the caller passes
+ *     device buffers (inputs, outputs and a workspace whose size the matching
+ *     *_bytes function returns) and owns all of them.
+ *   - "d_" pointers are device pointers, "h_" pointers host pointers.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Device work is
+ *     enqueued on it; calls marked ASYNC return before the work finishes and
+ *     their device outputs are valid after the stream is synchronised.
+ *   - Argument, size and workspace errors are returned synchronously as a
+ *     negative bc_status and nothing is enqueued.  Outcomes of device work
+ *     (no convergence, breakdown) are written to the device result struct.
+ *   - Meshes: vertices are M x 3 float64 row-major (x, y, z); triangles are
+ *     N x 3 int32 row-major vertex indices.  The surface must be a closed,
+ *     conforming, welded triangulation into plane triangles (Section 2.1);
+ *     bc_mesh_check verifies this on the host.
+ *   - Dense matrices are row-major N x ld with ld = bc_matrix_ld(N) (N rounded
+ *     up to a multiple of 64); columns N..ld-1 are written as zeros.
+ */
+#ifndef BEMCAP_H
+#define BEMCAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *bc_stream; /* a hipStream_t */
+
+typedef enum bc_status {
+  BC_OK = 0,
+  BC_EINVAL = -1,      /* bad argument, size or option */
+  BC_EMESH = -2,       /* mesh fails the validity check */
+  BC_ENOMEM = -3,      /* workspace smaller than required */
+  BC_EDEVICE = -4,     /* HIP runtime error (launch, copy, device query) */
+  BC_ENOCONV = -5,     /* iteration limits reached before the tolerance */
+  BC_EBREAKDOWN = -6,  /* p^T V p <= 0: the matrix is not positive definite */
+  BC_ETIMEOUT = -7,    /* a cross-workgroup barrier exceeded its spin limit */
+  BC_RUNNING = 1       /* batched solve: system not finished yet */
+} bc_status;
+
+typedef enum bc_precision {
+  BC_FP64 = 0,  /* FP64 matrix, FP64 Krylov iterations */
+  BC_MIXED = 1  /* FP32 matrix (far field computed in FP32, touching and
+                   near pairs computed in FP64 and kept as an FP64 sparse
+                   correction), FP32 CG with FP32 accumulation inside FP64
+                   iterative refinement of the residual b - V sigma */
+} bc_precision;
+
+/* ------------------------------------------------------------------------ */
+/* Version, status text, sizes                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Library ABI version (major * 10000 + minor * 100 + patch). */
+int32_t bc_version(void);
+
+/* Static text for a status code; never NULL. */
+const char *bc_status_string(int32_t status);
+
+/* Leading dimension of a dense N x N matrix: N rounded up to 64. */
+int64_t bc_matrix_ld(int64_t N);
+
+/* Bytes of the dense matrix: N * ld * (8 for BC_FP64, 4 for BC_MIXED). */
+size_t bc_matrix_bytes(int64_t N, int32_t precision);
+
+/* ------------------------------------------------------------------------ */
+/* Mesh validation (host)                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Section 2.1: a conforming triangulation of a closed polyhedral surface into
+ * plane triangles.  Rejects (BC_EMESH): N < 4 or M < 4, non-finite
+ * coordinates, indices outside [0, M), a triangle repeating a vertex, zero
+ * area, duplicate (unwelded) vertex coordinates, unused vertices, and edges
+ * not shared by exactly two triangles.  On failure *h_bad_index (if not NULL)
+ * receives the offending triangle or vertex index (-1 if none applies).
+ * Host memory only; no device work. */
+int32_t bc_mesh_check(const double *h_verts, int64_t M, const int32_t *h_tris,
+                      int64_t N, int64_t *h_bad_index);
+
+/* ------------------------------------------------------------------------ */
+/* Assembly: geometry, pair classification, dense V                        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct bc_assembly_opts {
+  int32_t far_order;  /* collapsed Gauss rule with far_order^2 points per
+                         triangle for pairs sharing no vertex; 1..4, default 4 */
+  int32_t ss_order;   /* Gauss points per coordinate of the 4-D singular
+                         rules (coincident 6, edge 4, vertex 2 subdomains);
+                         1..8, default 4 */
+  int32_t precision;  /* bc_precision */
+  int32_t reserved;   /* must be 0 */
+  double near_factor; /* BC_MIXED: pairs sharing no vertex with
+                         |c_i - c_j|^2 < near_factor^2 max(diam_i, diam_j)^2
+                         are computed in FP64 and corrected exactly; 0 = none.
+                         Must be 0 for BC_FP64. */
+} bc_assembly_opts;
+
+/* Sparse pattern produced by bc_prepare: every ordered pair (i, j) that
+ * shares a vertex with, or is near, element i.  Counts of unordered pairs
+ * (i <= j) by class are reported as well. */
+typedef struct bc_pattern_info {
+  int64_t nnz;          /* ordered entries of the pattern (both (i,j),(j,i)) */
+  int64_t n_coincident; /* = N */
+  int64_t n_edge;       /* unordered edge-adjacent pairs */
+  int64_t n_vertex;     /* unordered pairs sharing exactly one vertex */
+  int64_t n_near;       /* unordered near pairs (BC_MIXED) */
+} bc_pattern_info;
+
+/* Workspace for the mesh tables (geometry, quadrature points, row pointers
+ * of the pattern).  Depends on N only. */
+size_t bc_mesh_workspace_bytes(int64_t N);
+
+/* Workspace for the pattern itself (row pointers, and column, class and row
+ * of each entry, plus the FP64 correction values for BC_MIXED). */
+size_t bc_pattern_bytes(int64_t N, int64_t nnz, int32_t precision);
+
+/* Element geometry and pair classification (Section 2.1: pairs are told apart
+ * by shared vertex indices of the conforming mesh).  Fills d_mesh_ws and
+ * writes the pattern sizes to *h_info.  SYNCHRONOUS (waits for `stream`),
+ * because the caller needs nnz to size the pattern buffer.  d_verts, d_tris
+ * must stay unchanged until bc_assemble and bc_zz_indicators have run. */
+int32_t bc_prepare(const double *d_verts, int64_t M, const int32_t *d_tris,
+                   int64_t N, const bc_assembly_opts *opts, void *d_mesh_ws,
+                   size_t mesh_ws_bytes, bc_pattern_info *h_info,
+                   bc_stream stream);
+
+/* Dense Galerkin matrix (Appendix A, eq. "discreteform:residual"; kernel of
+ * eq. "strongform").  Pairs sharing no vertex use the collapsed Gauss rule
+ * (FP64 for BC_FP64, FP32 with FP64-formed centroid differences for
+ * BC_MIXED); touching pairs use the Sauter-Schwab-type rules in FP64; in
+ * BC_MIXED near pairs are recomputed in FP64 too and d_pattern receives the
+ * FP64 correction V64 - (double)(float)V64 of every pattern entry.  Only
+ * i <= j is integrated; V[j][i] = V[i][j] exactly.  d_V: N x ld, double
+ * (BC_FP64) or float (BC_MIXED).  opts must equal those given to bc_prepare.
+ * ASYNC. */
+int32_t bc_assemble(const double *d_verts, int64_t M, const int32_t *d_tris,
+                    int64_t N, const bc_assembly_opts *opts,
+                    const void *d_mesh_ws, size_t mesh_ws_bytes,
+                    void *d_pattern, size_t pattern_bytes, int64_t nnz,
+                    void *d_V, bc_stream stream);
+
+/* Element areas |T_i| (the load vector b) from the mesh workspace, FP64,
+ * length N.  ASYNC. */
+int32_t bc_areas(const void *d_mesh_ws, int64_t N, double *d_area,
+                 bc_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Solve and capacity                                                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct bc_solve_opts {
+  double rtol;        /* stop when ||b - A sigma||_2 <= rtol ||b||_2, with the
+                         residual formed in FP64 (A = V, plus the FP64
+                         correction in BC_MIXED); default 1e-12 (FP64) */
+  double inner_rtol;  /* each inner CG run stops at ||r_k|| <= inner_rtol
+                         ||r_0||; default 1e-13 (FP64), 1e-5 (BC_MIXED) */
+  int32_t max_iter;   /* cap on CG iterations (matrix products) in total */
+  int32_t max_outer;  /* cap on FP64 residual evaluations */
+  int32_t jacobi;     /* 1: diagonal (Jacobi) preconditioning */
+  int32_t x0_given;   /* 1: start from the caller's sigma; 0: from zero */
+} bc_solve_opts;
+
+/* Device-side result, written when a system finishes. */
+typedef struct bc_result {
+  double cap;          /* (1/4pi) sum_i sigma_i |T_i|, FP64, fixed-order sum */
+  double rel_residual; /* ||b - A sigma|| / ||b|| at the last FP64 residual */
+  int32_t iters;       /* CG iterations (matrix products with V) */
+  int32_t outer;       /* FP64 residual evaluations */
+  int32_t status;      /* BC_OK, BC_ENOCONV, BC_EBREAKDOWN, BC_ETIMEOUT, or
+                          BC_RUNNING while a chunked batch is unfinished */
+  int32_t precision;
+} bc_result;
+
+/* Workspace of one system's solver state.  Depends on N and precision. */
+size_t bc_solve_workspace_bytes(int64_t N, int32_t precision);
+
+/* Number of workgroups the solver gives a system of size N.  It depends on N
+ * only, so a system's arithmetic (row bands, reduction order) is the same
+ * alone and inside any batch. */
+int32_t bc_solve_workgroups(int64_t N);
+
+/* Krylov solve of V sigma = b (Section 2.5, Remark (ii): CG applies since V
+ * is symmetric positive definite) with b = |T| read from d_area, followed by
+ * the capacity reduction (eq. "cap:ell").  One persistent cooperative
+ * launch: CG in the Chronopoulos-Gear form (one matrix product and two
+ * cross-workgroup barriers per iteration), restarted from FP64 residuals.
+ * d_V, d_pattern as produced by bc_assemble (d_pattern may be NULL and
+ * nnz 0 for BC_FP64).  d_sigma (FP64, length N) is the initial guess if
+ * opts->x0_given and receives the solution.  d_result: one bc_result.
+ * ASYNC. */
+int32_t bc_solve(const void *d_V, int64_t N, int32_t precision,
+                 const void *d_pattern, int64_t nnz, const double *d_area,
+                 double *d_sigma, const bc_solve_opts *opts, void *d_ws,
+                 size_t ws_bytes, bc_result *d_result, bc_stream stream);
+
+/* One system of a batched solve (all pointers device pointers). */
+typedef struct bc_system {
+  const void *V;        /* N x ld matrix of `precision` */
+  const void *pattern;  /* bc_assemble pattern (NULL allowed for BC_FP64) */
+  const double *area;   /* b = |T| */
+  double *sigma;        /* initial guess / solution */
+  void *ws;             /* bc_solve_workspace_bytes(N, precision) bytes */
+  bc_result *result;    /* device result */
+  int64_t N;
+  int64_t nnz;
+  int32_t precision;
+  int32_t start;        /* 1: (re)initialise this system's state; 0: resume */
+} bc_system;
+
+/* Bytes of device scratch for the descriptors of a batch of n_sys systems. */
+size_t bc_batch_scratch_bytes(int32_t n_sys);
+
+/* Batched persistent solve: every system gets bc_solve_workgroups(N)
+ * workgroups of one cooperative launch and runs the same state machine as
+ * bc_solve.  iter_budget > 0 bounds the matrix products each system may do
+ * in this launch (continuous batching: unfinished systems report
+ * BC_RUNNING and resume, bitwise identically, in a later call with
+ * start = 0); iter_budget <= 0 runs every system to completion.  All
+ * systems must share one precision.  The total workgroup count must not
+ * exceed bc_solve_capacity().  h_sys is copied to d_scratch.  ASYNC. */
+int32_t bc_solve_batched(int32_t n_sys, const bc_system *h_sys,
+                         const bc_solve_opts *opts, int32_t iter_budget,
+                         void *d_scratch, size_t scratch_bytes,
+                         bc_stream stream);
+
+/* Workgroups one cooperative solver launch may use on the current device. */
+int32_t bc_solve_capacity(int32_t precision);
+
+/* Capacity (1/4pi) sum_i sigma_i |T_i| in FP64 with a fixed summation order
+ * (eq. "cap:ell"), written to *d_cap.  ASYNC. */
+int32_t bc_capacity(const double *d_sigma, const double *d_area, int64_t N,
+                    double *d_cap, bc_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* ZZ-type error indicators                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* eta(T)^2 = h_T ||sigma_T - I sigma||^2_{L2(T)} (eq. "zz:T", Section 2.4)
+ * for the P0 density sigma: I sigma is the S^1 function whose value at a
+ * vertex is the area-weighted mean of sigma over the elements containing it
+ * (increasing element order), and the L2 norm is evaluated in closed form.
+ * h_mode 0: h_T = diam(T) (eq. "zz:T"); 1: h_T = |T|^(1/2).  Needs the mesh
+ * workspace and pattern from bc_prepare / bc_assemble.  d_eta2: FP64,
+ * length N.  ASYNC. */
+int32_t bc_zz_indicators(const int32_t *d_tris, int64_t N,
+                         const void *d_mesh_ws, const void *d_pattern,
+                         int64_t nnz, const double *d_sigma, int32_t h_mode,
+                         double *d_eta2, bc_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BEMCAP_H */

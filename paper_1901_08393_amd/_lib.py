@@ -1,0 +1,112 @@
+"""ctypes binding of libbemcap.so: the C ABI declared in include/bemcap.h,
+function for function, with argument marshalling only.
+
+The library is built in-tree (``python -m paper_1901_08393_amd.build``).  If
+it is missing, :func:`lib` raises: there is no fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbemcap.so")
+
+BC_OK = 0
+BC_EINVAL = -1
+BC_EMESH = -2
+BC_ENOMEM = -3
+BC_EDEVICE = -4
+BC_ENOCONV = -5
+BC_EBREAKDOWN = -6
+BC_ETIMEOUT = -7
+BC_RUNNING = 1
+
+BC_FP64 = 0
+BC_MIXED = 1
+
+
+class bc_assembly_opts(C.Structure):
+    _fields_ = [("far_order", C.c_int32), ("ss_order", C.c_int32), ("precision", C.c_int32),
+                ("reserved", C.c_int32), ("near_factor", C.c_double)]
+
+
+class bc_pattern_info(C.Structure):
+    _fields_ = [("nnz", C.c_int64), ("n_coincident", C.c_int64), ("n_edge", C.c_int64),
+                ("n_vertex", C.c_int64), ("n_near", C.c_int64)]
+
+
+class bc_solve_opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("inner_rtol", C.c_double), ("max_iter", C.c_int32),
+                ("max_outer", C.c_int32), ("jacobi", C.c_int32), ("x0_given", C.c_int32)]
+
+
+class bc_result(C.Structure):
+    _fields_ = [("cap", C.c_double), ("rel_residual", C.c_double), ("iters", C.c_int32),
+                ("outer", C.c_int32), ("status", C.c_int32), ("precision", C.c_int32)]
+
+
+class bc_system(C.Structure):
+    _fields_ = [("V", C.c_void_p), ("pattern", C.c_void_p), ("area", C.c_void_p), ("sigma", C.c_void_p),
+                ("ws", C.c_void_p), ("result", C.c_void_p), ("N", C.c_int64), ("nnz", C.c_int64),
+                ("precision", C.c_int32), ("start", C.c_int32)]
+
+
+P = C.c_void_p
+I32 = C.c_int32
+I64 = C.c_int64
+SZ = C.c_size_t
+D = C.c_double
+
+# name: (restype, argtypes) -- in the order of include/bemcap.h
+SIGNATURES = {
+    "bc_version": (I32, []),
+    "bc_status_string": (C.c_char_p, [I32]),
+    "bc_matrix_ld": (I64, [I64]),
+    "bc_matrix_bytes": (SZ, [I64, I32]),
+    "bc_mesh_check": (I32, [P, I64, P, I64, C.POINTER(I64)]),
+    "bc_mesh_workspace_bytes": (SZ, [I64]),
+    "bc_pattern_bytes": (SZ, [I64, I64, I32]),
+    "bc_prepare": (I32, [P, I64, P, I64, C.POINTER(bc_assembly_opts), P, SZ, C.POINTER(bc_pattern_info), P]),
+    "bc_assemble": (I32, [P, I64, P, I64, C.POINTER(bc_assembly_opts), P, SZ, P, SZ, I64, P, P]),
+    "bc_areas": (I32, [P, I64, P, P]),
+    "bc_solve_workspace_bytes": (SZ, [I64, I32]),
+    "bc_solve_workgroups": (I32, [I64]),
+    "bc_solve": (I32, [P, I64, I32, P, I64, P, P, C.POINTER(bc_solve_opts), P, SZ, P, P]),
+    "bc_batch_scratch_bytes": (SZ, [I32]),
+    "bc_solve_batched": (I32, [I32, C.POINTER(bc_system), C.POINTER(bc_solve_opts), I32, P, SZ, P]),
+    "bc_solve_capacity": (I32, [I32]),
+    "bc_capacity": (I32, [P, P, I64, P, P]),
+    "bc_zz_indicators": (I32, [P, I64, P, P, I64, P, I32, P, P]),
+}
+
+_LIB = None
+
+
+class BemcapError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        self.status = status
+        msg = lib().bc_status_string(status).decode() if _LIB is not None else str(status)
+        super().__init__(f"{fn} failed: {msg} ({status})")
+
+
+def lib():
+    """Load libbemcap.so (once) and declare the prototypes."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1901_08393_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def check(fn: str, status: int) -> int:
+    if status < 0:
+        raise BemcapError(fn, status)
+    return status

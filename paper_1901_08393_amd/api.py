@@ -1,0 +1,238 @@
+"""Python front end of libbemcap.
+
+PyTorch provides device memory and streams; every numerical step runs in the
+library's HIP kernels.  One :class:`CapacityProblem` holds a mesh resident in
+HBM together with its geometry tables, sparse pattern, dense matrix and
+solver state:
+
+    prob = CapacityProblem(verts, tris, precision="mixed")
+    prob.assemble()
+    res = prob.solve()          # res.cap = (1/4pi) sum sigma_i |T_i|
+    eta2 = prob.zz(prob.sigma)  # ZZ-type indicators per element
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+PRECISION = {"fp64": _lib.BC_FP64, "mixed": _lib.BC_MIXED}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclasses.dataclass
+class SolveResult:
+    cap: float
+    rel_residual: float
+    iters: int
+    outer: int
+    status: int
+    precision: int
+
+    @property
+    def ok(self) -> bool:
+        return self.status == _lib.BC_OK
+
+    @staticmethod
+    def from_bytes(b: bytes) -> "SolveResult":
+        r = _lib.bc_result.from_buffer_copy(b)
+        return SolveResult(r.cap, r.rel_residual, r.iters, r.outer, r.status, r.precision)
+
+
+def default_solve_opts(precision: str, **over) -> _lib.bc_solve_opts:
+    if precision == "fp64":
+        o = dict(rtol=1e-12, inner_rtol=1e-11, max_iter=20000, max_outer=40, jacobi=1, x0_given=0)
+    else:
+        o = dict(rtol=1e-10, inner_rtol=1e-5, max_iter=20000, max_outer=60, jacobi=1, x0_given=0)
+    o.update({k: v for k, v in over.items() if v is not None})
+    return _lib.bc_solve_opts(**o)
+
+
+def mesh_check(verts: np.ndarray, tris: np.ndarray):
+    """Host validation of a closed conforming triangulation.  Returns
+    (status, bad_index)."""
+    v = np.ascontiguousarray(verts, dtype=np.float64)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    bad = C.c_int64(-1)
+    st = lib().bc_mesh_check(v.ctypes.data_as(C.c_void_p), v.shape[0], t.ctypes.data_as(C.c_void_p), t.shape[0],
+                             C.byref(bad))
+    return st, bad.value
+
+
+class CapacityProblem:
+    """A mesh on the GPU with everything the capacity computation needs."""
+
+    def __init__(self, verts, tris, precision: str = "fp64", far_order: int = 4, ss_order: int = 4,
+                 near_factor: Optional[float] = None, device: str = "cuda", validate: bool = True, stream=None):
+        if precision not in PRECISION:
+            raise ValueError(f"precision must be one of {list(PRECISION)}")
+        L = lib()
+        verts = np.ascontiguousarray(verts, dtype=np.float64)
+        tris = np.ascontiguousarray(tris, dtype=np.int32)
+        if validate:
+            st, bad = mesh_check(verts, tris)
+            if st != _lib.BC_OK:
+                raise _lib.BemcapError(f"bc_mesh_check (index {bad})", st)
+        self.precision = precision
+        self.prec = PRECISION[precision]
+        self.N = int(tris.shape[0])
+        self.M = int(verts.shape[0])
+        self.ld = int(L.bc_matrix_ld(self.N))
+        self.device = torch.device(device)
+        if near_factor is None:
+            near_factor = 1.5 if precision == "mixed" else 0.0
+        self.opts = _lib.bc_assembly_opts(far_order, ss_order, self.prec, 0, float(near_factor))
+        self.d_verts = torch.from_numpy(verts).to(self.device)
+        self.d_tris = torch.from_numpy(tris).to(self.device)
+        nb = L.bc_mesh_workspace_bytes(self.N)
+        self.mesh_ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        self.pattern = None
+        self.area = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        self.prepare(stream)
+        self.V: Optional[torch.Tensor] = None
+        self.sigma = torch.zeros(self.N, dtype=torch.float64, device=self.device)
+        self.solve_ws: Optional[torch.Tensor] = None
+        self.result_buf = torch.zeros(32, dtype=torch.uint8, device=self.device)
+
+    def prepare(self, stream=None):
+        """Geometry tables and pair classification (bc_prepare; waits for
+        the stream), then the element areas."""
+        L = lib()
+        info = _lib.bc_pattern_info()
+        check("bc_prepare", L.bc_prepare(_ptr(self.d_verts), self.M, _ptr(self.d_tris), self.N, C.byref(self.opts),
+                                         _ptr(self.mesh_ws), self.mesh_ws.numel(), C.byref(info), _stream(stream)))
+        self.info = info
+        self.nnz = int(info.nnz)
+        self.pattern_bytes = L.bc_pattern_bytes(self.N, self.nnz, self.prec)
+        if self.pattern is None or self.pattern.numel() < self.pattern_bytes:
+            self.pattern = torch.empty(self.pattern_bytes, dtype=torch.uint8, device=self.device)
+        check("bc_areas", L.bc_areas(_ptr(self.mesh_ws), self.N, _ptr(self.area), _stream(stream)))
+
+    # ------------------------------------------------------------ assembly
+    @property
+    def matrix_dtype(self):
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    def matrix_bytes(self) -> int:
+        return int(lib().bc_matrix_bytes(self.N, self.prec))
+
+    def assemble(self, stream=None) -> torch.Tensor:
+        if self.V is None:
+            self.V = torch.empty((self.N, self.ld), dtype=self.matrix_dtype, device=self.device)
+        L = lib()
+        check("bc_assemble", L.bc_assemble(_ptr(self.d_verts), self.M, _ptr(self.d_tris), self.N, C.byref(self.opts),
+                                           _ptr(self.mesh_ws), self.mesh_ws.numel(), _ptr(self.pattern),
+                                           self.pattern_bytes, self.nnz, _ptr(self.V), _stream(stream)))
+        return self.V
+
+    def dense(self) -> torch.Tensor:
+        """The N x N matrix (a view without the padding columns)."""
+        return self.V[:, : self.N]
+
+    def pattern_arrays(self):
+        """(rowptr, col, row, kind, corr) views into the pattern buffer."""
+        N, nnz = self.N, self.nnz
+
+        def off(n):
+            return (n + 255) // 256 * 256
+
+        o_rowptr = 0
+        o_col = off(4 * (N + 1))
+        o_row = o_col + off(4 * nnz)
+        o_kind = o_row + off(4 * nnz)
+        o_corr = o_kind + off(4 * nnz)
+        b = self.pattern
+        rowptr = b[o_rowptr:o_rowptr + 4 * (N + 1)].view(torch.int32)
+        col = b[o_col:o_col + 4 * nnz].view(torch.int32)
+        row = b[o_row:o_row + 4 * nnz].view(torch.int32)
+        kind = b[o_kind:o_kind + 4 * nnz].view(torch.int32)
+        corr = b[o_corr:o_corr + 8 * nnz].view(torch.float64) if self.precision == "mixed" else None
+        return rowptr, col, row, kind, corr
+
+    # --------------------------------------------------------------- solve
+    def _ensure_solve_ws(self):
+        if self.solve_ws is None:
+            nb = lib().bc_solve_workspace_bytes(self.N, self.prec)
+            self.solve_ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+
+    def solve(self, stream=None, x0: Optional[torch.Tensor] = None, sync: bool = True, **opts) -> Optional[SolveResult]:
+        if self.V is None:
+            raise RuntimeError("assemble() first")
+        self._ensure_solve_ws()
+        o = default_solve_opts(self.precision, **opts)
+        if x0 is not None:
+            self.sigma.copy_(x0)
+            o.x0_given = 1
+        L = lib()
+        check("bc_solve", L.bc_solve(_ptr(self.V), self.N, self.prec, _ptr(self.pattern), self.nnz, _ptr(self.area),
+                                     _ptr(self.sigma), C.byref(o), _ptr(self.solve_ws), self.solve_ws.numel(),
+                                     _ptr(self.result_buf), _stream(stream)))
+        if not sync:
+            return None
+        return self.result(stream)
+
+    def result(self, stream=None) -> SolveResult:
+        (stream or torch.cuda.current_stream()).synchronize()
+        return SolveResult.from_bytes(self.result_buf.cpu().numpy().tobytes())
+
+    def capacity_of(self, sigma: torch.Tensor, stream=None) -> float:
+        out = torch.empty(1, dtype=torch.float64, device=self.device)
+        check("bc_capacity", lib().bc_capacity(_ptr(sigma), _ptr(self.area), self.N, _ptr(out), _stream(stream)))
+        return float(out.item())
+
+    # ------------------------------------------------------------------ ZZ
+    def zz(self, sigma: Optional[torch.Tensor] = None, h_mode: int = 0, stream=None) -> torch.Tensor:
+        sigma = self.sigma if sigma is None else sigma
+        eta2 = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        check("bc_zz_indicators", lib().bc_zz_indicators(_ptr(self.d_tris), self.N, _ptr(self.mesh_ws),
+                                                         _ptr(self.pattern), self.nnz, _ptr(sigma), h_mode,
+                                                         _ptr(eta2), _stream(stream)))
+        return eta2
+
+    def release_matrix(self):
+        self.V = None
+        self.solve_ws = None
+
+
+def solve_batched(problems, precision: str, iter_budget: int = 0, start=None, stream=None, **opts):
+    """One persistent launch over several assembled problems (same precision).
+    start[k] = 1 (re)initialises problem k, 0 resumes it.  Asynchronous: read
+    each problem's result with problem.result() after the stream syncs."""
+    L = lib()
+    n = len(problems)
+    arr = (_lib.bc_system * n)()
+    for k, p in enumerate(problems):
+        p._ensure_solve_ws()
+        arr[k] = _lib.bc_system(p.V.data_ptr(), p.pattern.data_ptr(), p.area.data_ptr(), p.sigma.data_ptr(),
+                                p.solve_ws.data_ptr(), p.result_buf.data_ptr(), p.N, p.nnz, PRECISION[precision],
+                                1 if start is None else int(start[k]))
+    o = default_solve_opts(precision, **opts)
+    nb = L.bc_batch_scratch_bytes(n)
+    scratch = torch.empty(nb, dtype=torch.uint8, device=problems[0].device)
+    check("bc_solve_batched", L.bc_solve_batched(n, arr, C.byref(o), iter_budget, _ptr(scratch), nb,
+                                                 _stream(stream)))
+    return scratch  # keep alive until the launch completes
+
+
+def capacity(verts, tris, precision: str = "fp64", return_problem: bool = False, **kw):
+    """Assemble, solve and return the capacity of one polyhedron."""
+    solve_kw = {k: kw.pop(k) for k in list(kw) if k in ("rtol", "inner_rtol", "max_iter", "max_outer", "jacobi")}
+    p = CapacityProblem(verts, tris, precision=precision, **kw)
+    p.assemble()
+    r = p.solve(**solve_kw)
+    return (r, p) if return_problem else r

@@ -1,0 +1,376 @@
+// Dense assembly of the P0 Galerkin matrix of the single-layer operator
+// (Appendix A, eq. "discreteform:residual"; kernel 1/(4 pi |x - y|) of
+// eq. "strongform"):
+//
+//   V[i][j] = (1/4pi) int_{T_i} int_{T_j} 1/|x - y| dy dx.
+//
+// k_far64 / k_far32: every pair i <= j with the collapsed Q-point Gauss rule
+//   on both triangles (Q^2 point pairs).  One workgroup per 64 x 64 tile of
+//   the upper block triangle; lanes own columns j and keep that element's Q
+//   points in registers; the 16 rows of a wave are read with uniform
+//   (scalar) loads.  The value is stored at (i, j) and mirrored to (j, i).
+//   ALU-bound: no matrix cores (there is no dense contraction here, only
+//   a 1/r evaluation per point pair).
+// k_sparse: one wavefront per pattern entry with j >= i: touching pairs with
+//   the Sauter-Schwab-type rules, near pairs (mixed precision) with the
+//   regular rule, both in FP64; overwrites the far-field value.  In mixed
+//   precision it also stores the FP64 correction V64 - (double)(float)V64 at
+//   both (i, j) and (j, i) of the pattern.
+// k_pad: zeros in the padding columns N..ld-1.
+#include "bc_internal.h"
+
+namespace bc {
+
+// ----------------------------------------------------------------- far field
+__device__ __forceinline__ void tile_of(int t, int &I, int &J) {
+  // tiles enumerated column-block first: t = J (J + 1) / 2 + I, 0 <= I <= J
+  int j = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((j + 1) * (j + 2) / 2 <= t) ++j;
+  while (j * (j + 1) / 2 > t) --j;
+  J = j;
+  I = t - j * (j + 1) / 2;
+}
+
+template <int Q>
+__global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, const double *__restrict__ qpS,
+                                               int N, int64_t ld, double *__restrict__ V) {
+  int I, J;
+  tile_of(blockIdx.x, I, J);
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int j = J * 64 + lane;
+  const bool jv = j < N;
+  const int jj = jv ? j : N - 1;
+  double yx[Q], yy[Q], yz[Q], yw[Q];
+#pragma unroll
+  for (int b = 0; b < Q; ++b) {
+    yx[b] = qpS[(size_t)(b * 4 + 0) * N + jj];
+    yy[b] = qpS[(size_t)(b * 4 + 1) * N + jj];
+    yz[b] = qpS[(size_t)(b * 4 + 2) * N + jj];
+    yw[b] = qpS[(size_t)(b * 4 + 3) * N + jj];
+  }
+  const int i0 = I * 64 + w * 16;
+  for (int k = 0; k < 16; ++k) {
+    const int i = i0 + k;
+    if (i >= N) break;
+    const double4 *xa = qpA + (size_t)i * kQMax;
+    double acc = 0.0;
+#pragma unroll 2
+    for (int a = 0; a < Q; ++a) {
+      const double4 p = xa[a];
+      double s = 0.0;
+#pragma unroll
+      for (int b = 0; b < Q; ++b) {
+        double dx = p.x - yx[b], dy = p.y - yy[b], dz = p.z - yz[b];
+        double r2 = dx * dx + dy * dy + dz * dz;
+        s = __builtin_fma(yw[b], rsqrt64(r2), s);
+      }
+      acc = __builtin_fma(p.w, s, acc);
+    }
+    if (jv && j >= i) {
+      const double v = acc * kInv4Pi;
+      V[(size_t)i * ld + j] = v;
+      V[(size_t)j * ld + i] = v;
+    }
+  }
+}
+
+// FP32 far field.  The point offsets are relative to the element centroid
+// and the weights are those of the reference triangle; the entry is
+//   (float)( (double)S_ij * 4 |T_i| |T_j| * scale ),
+//   S_ij = sum_a w_a sum_b w_b / |x_a - y_b|   (FP32),
+// with scale = (1/4pi) (sum w / sum fl(w))^2 formed in FP64 on the host, so
+// that neither 1/(4pi) nor the weights carry an FP32 rounding that is the
+// same for every entry (such a common rounding would shift the capacity by
+// the same relative amount).
+template <int Q>
+__global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, const float *__restrict__ qpS,
+                                               const double4 *__restrict__ cen4, const double *__restrict__ area,
+                                               double scale, int N, int64_t ld, float *__restrict__ V) {
+  int I, J;
+  tile_of(blockIdx.x, I, J);
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int j = J * 64 + lane;
+  const bool jv = j < N;
+  const int jj = jv ? j : N - 1;
+  float vx[Q], vy[Q], vz[Q], vw[Q];
+#pragma unroll
+  for (int b = 0; b < Q; ++b) {
+    vx[b] = qpS[(size_t)(b * 4 + 0) * N + jj];
+    vy[b] = qpS[(size_t)(b * 4 + 1) * N + jj];
+    vz[b] = qpS[(size_t)(b * 4 + 2) * N + jj];
+    vw[b] = qpS[(size_t)(b * 4 + 3) * N + jj];
+  }
+  const double4 cj = cen4[jj];
+  const double aj = 4.0 * area[jj] * scale;
+  const int i0 = I * 64 + w * 16;
+  for (int k = 0; k < 16; ++k) {
+    const int i = i0 + k;
+    if (i >= N) break;
+    const double4 ci = cen4[i];
+    // centroid difference formed in FP64, then rounded: no cancellation of
+    // absolute coordinates on small or distant elements
+    const float Dx = (float)(ci.x - cj.x), Dy = (float)(ci.y - cj.y), Dz = (float)(ci.z - cj.z);
+    const float4 *ua = qpA + (size_t)i * kQMax;
+    float acc = 0.f;
+#pragma unroll 2
+    for (int a = 0; a < Q; ++a) {
+      const float4 p = ua[a];
+      const float ex = Dx + p.x, ey = Dy + p.y, ez = Dz + p.z;
+      float s = 0.f;
+#pragma unroll
+      for (int b = 0; b < Q; ++b) {
+        float dx = ex - vx[b], dy = ey - vy[b], dz = ez - vz[b];
+        float r2 = dx * dx + dy * dy + dz * dz;
+        s = __builtin_fmaf(vw[b], rsqrt32(r2), s);
+      }
+      acc = __builtin_fmaf(p.w, s, acc);
+    }
+    if (jv && j >= i) {
+      const float v = (float)((double)acc * (area[i] * aj));
+      V[(size_t)i * ld + j] = v;
+      V[(size_t)j * ld + i] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------- touching and near
+struct SSRule {
+  int n;
+  int pad;
+  double x[kSSMax], w[kSSMax];
+};
+
+// Region maps of the singular rules on K = {0 <= x2 <= x1 <= 1}; (xi, e1,
+// e2, e3) in [0,1]^4.  Returns the Jacobian and writes the two reference
+// points.  kind: 3 coincident (6 regions), 2 edge (4), 1 vertex (2).
+__device__ __forceinline__ double ss_map(int kind, int reg, double xi, double e1, double e2, double e3, double &x1,
+                                         double &x2, double &y1, double &y2) {
+  double a1, a2, b1, b2, J;
+  if (kind == kCoincident) {
+    J = xi * xi * xi * e1 * e1 * e2;
+    int r = reg >> 1;
+    if (r == 0) {
+      a1 = xi; a2 = xi * (1.0 - e1 + e1 * e2);
+      b1 = xi * (1.0 - e1 * e2 * e3); b2 = xi * (1.0 - e1);
+    } else if (r == 1) {
+      a1 = xi; a2 = xi * e1 * (1.0 - e2 + e2 * e3);
+      b1 = xi * (1.0 - e1 * e2); b2 = xi * e1 * (1.0 - e2);
+    } else {
+      a1 = xi * (1.0 - e1 * e2 * e3); a2 = xi * e1 * (1.0 - e2 * e3);
+      b1 = xi; b2 = xi * e1 * (1.0 - e2);
+    }
+  } else if (kind == kEdge) {
+    if ((reg & 1) == 0) {   // {p >= w + r}
+      J = xi * xi * xi * e1 * e1 * e2;
+      a1 = xi; a2 = xi * e1;
+      b1 = xi * (1.0 - e1 * e2 * e3); b2 = xi * e1 * e2 * (1.0 - e3);
+    } else {                // {p <= w + r}
+      J = xi * xi * xi * e1 * e1;
+      a1 = xi; a2 = xi * e1 * e3;
+      b1 = xi * (1.0 - e1 * e2); b2 = xi * e1 * (1.0 - e2);
+    }
+  } else {
+    J = xi * xi * xi * e2;
+    a1 = xi; a2 = xi * e1;
+    b1 = xi * e2; b2 = xi * e2 * e3;
+  }
+  // odd regions are the mirror images (the two triangles swap roles)
+  if (kind == kEdge) {
+    // edge regions are ordered A, B, mirror A, mirror B
+    if (reg >= 2) { double t1 = a1, t2 = a2; a1 = b1; a2 = b2; b1 = t1; b2 = t2; }
+  } else if (reg & 1) {
+    double t1 = a1, t2 = a2; a1 = b1; a2 = b2; b1 = t1; b2 = t2;
+  }
+  x1 = a1; x2 = a2; y1 = b1; y2 = b2;
+  return J;
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(kWG) void k_sparse(const double *__restrict__ verts, const int4 *__restrict__ tri4,
+                                                const double *__restrict__ area, const double4 *__restrict__ qpA,
+                                                int Q, SSRule ss, const int32_t *__restrict__ prowptr,
+                                                const int32_t *__restrict__ pcol, const int32_t *__restrict__ prow,
+                                                const int32_t *__restrict__ pkind, double *__restrict__ pcorr,
+                                                int64_t nnz, int64_t ld, void *__restrict__ Vout) {
+  const int lane = threadIdx.x & 63;
+  const int64_t e = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (e >= nnz) return;
+  const int i = prow[e], j = pcol[e];
+  if (j < i) return;
+  const int kind = pkind[e];
+  double acc = 0.0;
+  double scale;
+  if (kind == kNear) {
+    const double4 *xa = qpA + (size_t)i * kQMax;
+    const double4 *yb = qpA + (size_t)j * kQMax;
+    for (int p = lane; p < Q * Q; p += 64) {
+      const double4 x = xa[p / Q], y = yb[p % Q];
+      const double dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
+      acc += x.w * y.w * rsqrt64(dx * dx + dy * dy + dz * dz);
+    }
+    scale = kInv4Pi;
+  } else {
+    const int4 ti = tri4[i], tj = tri4[j];
+    int A, B, C, D0, D1, D2;
+    if (kind == kCoincident) {
+      A = ti.x; B = ti.y; C = ti.z; D0 = ti.x; D1 = ti.y; D2 = ti.z;
+    } else if (kind == kEdge) {
+      // shared edge {A, B}, A the lower index; C, D the other vertices
+      const int tv[3] = {ti.x, ti.y, ti.z}, sv[3] = {tj.x, tj.y, tj.z};
+      int sh[2], ns = 0, c = -1, d = -1;
+      for (int a = 0; a < 3; ++a) {
+        bool in = tv[a] == sv[0] || tv[a] == sv[1] || tv[a] == sv[2];
+        if (in) sh[ns++ & 1] = tv[a]; else c = tv[a];
+        bool jn = sv[a] == tv[0] || sv[a] == tv[1] || sv[a] == tv[2];
+        if (!jn) d = sv[a];
+      }
+      A = min(sh[0], sh[1]); B = max(sh[0], sh[1]); C = c;
+      D0 = A; D1 = B; D2 = d;
+    } else {
+      // shared vertex A; the others in each element's cyclic order after A
+      const int tv[3] = {ti.x, ti.y, ti.z}, sv[3] = {tj.x, tj.y, tj.z};
+      int ki = 0, kj = 0;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          if (tv[a] == sv[b]) { ki = a; kj = b; }
+      A = tv[ki]; B = tv[(ki + 1) % 3]; C = tv[(ki + 2) % 3];
+      D0 = A; D1 = sv[(kj + 1) % 3]; D2 = sv[(kj + 2) % 3];
+    }
+    const double ax = verts[3 * A], ay = verts[3 * A + 1], az = verts[3 * A + 2];
+    const double bax = verts[3 * B] - ax, bay = verts[3 * B + 1] - ay, baz = verts[3 * B + 2] - az;
+    const double cbx = verts[3 * C] - verts[3 * B], cby = verts[3 * C + 1] - verts[3 * B + 1],
+                 cbz = verts[3 * C + 2] - verts[3 * B + 2];
+    const double dx0 = verts[3 * D0], dy0 = verts[3 * D0 + 1], dz0 = verts[3 * D0 + 2];
+    const double e1x = verts[3 * D1] - dx0, e1y = verts[3 * D1 + 1] - dy0, e1z = verts[3 * D1 + 2] - dz0;
+    const double e2x = verts[3 * D2] - verts[3 * D1], e2y = verts[3 * D2 + 1] - verts[3 * D1 + 1],
+                 e2z = verts[3 * D2 + 2] - verts[3 * D1 + 2];
+    const int n = ss.n, n2 = n * n, n4 = n2 * n2;
+    const int nreg = kind == kCoincident ? 6 : (kind == kEdge ? 4 : 2);
+    for (int p = lane; p < nreg * n4; p += 64) {
+      const int reg = p / n4;
+      int q = p - reg * n4;
+      const int i3 = q % n; q /= n;
+      const int i2 = q % n; q /= n;
+      const int i1 = q % n; q /= n;
+      const int i0 = q;
+      double x1, x2, y1, y2;
+      const double Jac = ss_map(kind, reg, ss.x[i0], ss.x[i1], ss.x[i2], ss.x[i3], x1, x2, y1, y2);
+      const double wgt = ss.w[i0] * ss.w[i1] * ss.w[i2] * ss.w[i3] * Jac;
+      const double px = ax + x1 * bax + x2 * cbx, py = ay + x1 * bay + x2 * cby, pz = az + x1 * baz + x2 * cbz;
+      const double qx = dx0 + y1 * e1x + y2 * e2x, qy = dy0 + y1 * e1y + y2 * e2y, qz = dz0 + y1 * e1z + y2 * e2z;
+      const double rx = px - qx, ry = py - qy, rz = pz - qz;
+      acc += wgt * rsqrt64(rx * rx + ry * ry + rz * rz);
+    }
+    scale = (2.0 * area[i]) * (2.0 * area[j]) * kInv4Pi;
+  }
+  const double v = wave_sum(acc) * scale;
+  if (lane != 0) return;
+  if (!MIXED) {
+    double *V = static_cast<double *>(Vout);
+    V[(size_t)i * ld + j] = v;
+    V[(size_t)j * ld + i] = v;
+  } else {
+    float *V = static_cast<float *>(Vout);
+    const float f = (float)v;
+    const double corr = v - (double)f;
+    V[(size_t)i * ld + j] = f;
+    V[(size_t)j * ld + i] = f;
+    pcorr[e] = corr;
+    if (j != i) {
+      // position of (j, i) in row j (columns are sorted)
+      int lo = prowptr[j], hi = prowptr[j + 1] - 1;
+      while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (pcol[mid] < i) lo = mid + 1; else hi = mid;
+      }
+      pcorr[lo] = corr;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_pad(T *V, int N, int64_t ld) {
+  const int64_t pad = ld - N;
+  const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (idx >= (int64_t)N * pad) return;
+  const int64_t i = idx / pad, c = N + idx % pad;
+  V[i * ld + c] = T(0);
+}
+
+template <int Q>
+static void far_launch(bool mixed, const MeshView &m, int N, int64_t ld, void *V, int tiles, double scale,
+                       hipStream_t s) {
+  if (!mixed)
+    hipLaunchKernelGGL(k_far64<Q>, dim3(tiles), dim3(kWG), 0, s, m.qpA64, m.qpS64, N, ld, static_cast<double *>(V));
+  else
+    hipLaunchKernelGGL(k_far32<Q>, dim3(tiles), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, scale, N, ld,
+                       static_cast<float *>(V));
+}
+
+// (1/4pi) (sum_k w_k / sum_k fl32(w_k))^2 for the collapsed rule of order n
+static double far32_scale(int n) {
+  double x[8], w[8];
+  gauss_legendre01(n, x, w);
+  double sw = 0.0, sf = 0.0;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      const double wk = w[a] * w[b] * (1.0 - x[a]);
+      sw += wk;
+      sf += (double)(float)wk;
+    }
+  return kInv4Pi * (sw / sf) * (sw / sf);
+}
+
+int launch_assemble(const void *mesh_ws, const int32_t *tris, const double *verts, int64_t N,
+                    const bc_assembly_opts &o, void *pattern, int64_t nnz, void *V, hipStream_t s) {
+  (void)tris;
+  const bool mixed = o.precision == BC_MIXED;
+  const MeshView m = mesh_view(mesh_ws, N);
+  const int64_t ld = ld_of(N);
+  const int64_t T = (N + 63) / 64;
+  const int tiles = (int)(T * (T + 1) / 2);
+  const double scale = far32_scale(o.far_order);
+  switch (o.far_order) {
+    case 1: far_launch<1>(mixed, m, (int)N, ld, V, tiles, scale, s); break;
+    case 2: far_launch<4>(mixed, m, (int)N, ld, V, tiles, scale, s); break;
+    case 3: far_launch<9>(mixed, m, (int)N, ld, V, tiles, scale, s); break;
+    case 4: far_launch<16>(mixed, m, (int)N, ld, V, tiles, scale, s); break;
+    default: return BC_EINVAL;
+  }
+  if (hipGetLastError() != hipSuccess) return BC_EDEVICE;
+  if (nnz > 0) {
+    SSRule ss{};
+    ss.n = o.ss_order;
+    gauss_legendre01(o.ss_order, ss.x, ss.w);
+    PatternLayout P(N, nnz, o.precision);
+    char *pb = static_cast<char *>(pattern);
+    const int32_t *prowptr = reinterpret_cast<const int32_t *>(pb + P.rowptr);
+    const int32_t *pcol = reinterpret_cast<const int32_t *>(pb + P.col);
+    const int32_t *prow = reinterpret_cast<const int32_t *>(pb + P.row);
+    const int32_t *pkind = reinterpret_cast<const int32_t *>(pb + P.kind);
+    double *pcorr = mixed ? reinterpret_cast<double *>(pb + P.corr) : nullptr;
+    const int grid = (int)((nnz + 3) / 4);
+    const int Q = o.far_order * o.far_order;
+    if (!mixed)
+      hipLaunchKernelGGL(k_sparse<false>, dim3(grid), dim3(kWG), 0, s, verts, m.tri4, m.area, m.qpA64, Q, ss,
+                         prowptr, pcol, prow, pkind, pcorr, nnz, ld, V);
+    else
+      hipLaunchKernelGGL(k_sparse<true>, dim3(grid), dim3(kWG), 0, s, verts, m.tri4, m.area, m.qpA64, Q, ss, prowptr,
+                         pcol, prow, pkind, pcorr, nnz, ld, V);
+    if (hipGetLastError() != hipSuccess) return BC_EDEVICE;
+  }
+  if (ld > N) {
+    const int64_t cnt = N * (ld - N);
+    const int grid = (int)((cnt + kWG - 1) / kWG);
+    if (!mixed)
+      hipLaunchKernelGGL(k_pad<double>, dim3(grid), dim3(kWG), 0, s, static_cast<double *>(V), (int)N, ld);
+    else
+      hipLaunchKernelGGL(k_pad<float>, dim3(grid), dim3(kWG), 0, s, static_cast<float *>(V), (int)N, ld);
+    if (hipGetLastError() != hipSuccess) return BC_EDEVICE;
+  }
+  return BC_OK;
+}
+
+}  // namespace bc

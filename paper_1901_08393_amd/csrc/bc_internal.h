@@ -1,0 +1,201 @@
+// Internal declarations shared by the HIP sources of libbemcap.
+// Layouts of the caller-provided workspaces and the device helpers used by
+// several kernels.  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/bemcap.h"
+
+namespace bc {
+
+constexpr int kWG = 256;            // threads per workgroup (4 wave64)
+constexpr int kQMax = 16;           // far-field points per triangle (order <= 4)
+constexpr int kSSMax = 8;           // Gauss points per coordinate, singular rules
+constexpr int kGMax = 1024;         // workgroups per system in the solver
+constexpr double kInv4Pi = 0.079577471545947667884441881686257181;  // 1/(4 pi)
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+inline int64_t ld_of(int64_t N) { return (N + 63) / 64 * 64; }
+
+// ---------------------------------------------------------------- mesh ws
+// Offsets of the tables inside the mesh workspace (all 256-byte aligned).
+struct MeshLayout {
+  size_t tri4, cen4, area, qpA64, qpS64, qpA32, qpS32, rowcnt, rowptr, kindcnt, info, total;
+  explicit MeshLayout(int64_t N) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    tri4 = take(sizeof(int32_t) * 4 * N);
+    cen4 = take(sizeof(double) * 4 * N);
+    area = take(sizeof(double) * N);
+    qpA64 = take(sizeof(double) * 4 * kQMax * N);
+    qpS64 = take(sizeof(double) * 4 * kQMax * N);
+    qpA32 = take(sizeof(float) * 4 * kQMax * N);
+    qpS32 = take(sizeof(float) * 4 * kQMax * N);
+    rowcnt = take(sizeof(int32_t) * N);
+    rowptr = take(sizeof(int32_t) * (N + 1));
+    kindcnt = take(sizeof(int32_t) * 4 * N);
+    info = take(sizeof(int64_t) * 8);
+    total = o;
+  }
+};
+
+// Device view of the mesh workspace.
+struct MeshView {
+  const int4 *tri4;      // (v0, v1, v2, 0)
+  const double4 *cen4;   // (cx, cy, cz, diam^2)
+  const double *area;
+  const double4 *qpA64;  // [N][Q] (x, y, z, W), rows
+  const double *qpS64;   // [(b*4+c)][N], columns
+  const float4 *qpA32;   // [N][Q] (x - c, y - c, z - c, W)
+  const float *qpS32;    // [(b*4+c)][N]
+  const int32_t *rowptr; // N + 1
+};
+
+inline MeshView mesh_view(const void *ws, int64_t N) {
+  MeshLayout L(N);
+  const char *b = static_cast<const char *>(ws);
+  MeshView v;
+  v.tri4 = reinterpret_cast<const int4 *>(b + L.tri4);
+  v.cen4 = reinterpret_cast<const double4 *>(b + L.cen4);
+  v.area = reinterpret_cast<const double *>(b + L.area);
+  v.qpA64 = reinterpret_cast<const double4 *>(b + L.qpA64);
+  v.qpS64 = reinterpret_cast<const double *>(b + L.qpS64);
+  v.qpA32 = reinterpret_cast<const float4 *>(b + L.qpA32);
+  v.qpS32 = reinterpret_cast<const float *>(b + L.qpS32);
+  v.rowptr = reinterpret_cast<const int32_t *>(b + L.rowptr);
+  return v;
+}
+
+// ------------------------------------------------------------- pattern ws
+enum PairKind : int32_t { kNear = 0, kVertex = 1, kEdge = 2, kCoincident = 3 };
+
+struct PatternLayout {
+  size_t rowptr, col, row, kind, corr, total;
+  PatternLayout(int64_t N, int64_t nnz, int32_t precision) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    rowptr = take(sizeof(int32_t) * (N + 1));
+    col = take(sizeof(int32_t) * nnz);
+    row = take(sizeof(int32_t) * nnz);
+    kind = take(sizeof(int32_t) * nnz);
+    corr = precision == BC_MIXED ? take(sizeof(double) * nnz) : o;
+    total = o;
+  }
+};
+
+// ---------------------------------------------------------------- solver ws
+struct SolveLayout {
+  size_t ctl, partial, x64, r64, vec, total;
+  int64_t ld;
+  SolveLayout(int64_t N, int32_t precision) {
+    ld = ld_of(N);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    ctl = take(1024);
+    partial = take(sizeof(double) * 2 * 4 * kGMax);  // two sets, by barrier epoch parity
+    x64 = take(sizeof(double) * ld);
+    r64 = take(sizeof(double) * ld);
+    size_t es = precision == BC_FP64 ? 8 : 4;
+    vec = take(es * ld * 7);  // r u w p s d invdiag
+    total = o;
+  }
+};
+
+// Per-system control block at the start of the solver workspace.  Written
+// only by workgroup 0 of the system (state save) and by the barrier.
+struct SolveCtl {
+  unsigned bar_count;
+  unsigned bar_gen;
+  int32_t abort;       // set on barrier timeout
+  int32_t phase;
+  int32_t iters;
+  int32_t outer;
+  int32_t inner;
+  int32_t status;
+  uint32_t epoch;
+  int32_t pad;
+  double bnorm, rnorm, scale, gamma, eta, alpha, beta;
+};
+
+// Solver descriptor built by the host for each system of a launch.
+struct SysDesc {
+  const void *V;
+  const int32_t *prowptr;
+  const int32_t *pcol;
+  const double *pcorr;
+  const double *area;
+  double *sigma;
+  char *ws;
+  bc_result *result;
+  int64_t N;
+  int64_t ld;
+  int64_t nnz;
+  int32_t wg_begin;
+  int32_t wg_count;
+  int32_t start;
+  int32_t pad;
+};
+
+struct SolveParams {
+  double rtol, inner_rtol;
+  int32_t max_iter, max_outer, jacobi, x0_given;
+  int32_t iter_budget;
+  uint32_t spin_limit;
+  int32_t n_sys;
+};
+
+// --------------------------------------------------------- device helpers
+// Inverse square root in FP64: hardware estimate refined by one step of the
+// cubically convergent iteration y <- y (1 + e/2 + 3e^2/8), e = 1 - x y^2
+// (Householder's method of order 2 applied to f(y) = y^-2 - x).
+__device__ __forceinline__ double rsqrt64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double t = x * y;
+  double e = __builtin_fma(-t, y, 1.0);
+  double c = __builtin_fma(0.375, e, 0.5);
+  return __builtin_fma(y * e, c, y);
+}
+
+// Inverse square root in FP32: hardware estimate refined by one Newton step
+// y <- y + (y/2)(1 - x y^2).  The estimate alone carries a small one-sided
+// error that would bias every far-field entry the same way; after the step
+// the remaining error is rounding of either sign.
+__device__ __forceinline__ float rsqrt32(float x) {
+  float y = __builtin_amdgcn_rsqf(x);
+  float t = x * y;
+  float e = __builtin_fmaf(-t, y, 1.0f);
+  return __builtin_fmaf(0.5f * y, e, y);
+}
+
+// Sum over the 64 lanes of a wavefront with a fixed butterfly order; every
+// lane receives the total.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace bc
+
+// Host-side launchers (each returns a bc_status).
+namespace bc {
+int launch_geometry(const double *verts, int64_t M, const int32_t *tris, int64_t N,
+                    int far_order, void *mesh_ws, hipStream_t s);
+int launch_pattern(const int32_t *tris, int64_t N, double near_factor, const void *mesh_ws,
+                   void *pattern, int64_t nnz, int32_t precision, bool emit, hipStream_t s);
+int launch_assemble(const void *mesh_ws, const int32_t *tris, const double *verts, int64_t N,
+                    const bc_assembly_opts &o, void *pattern, int64_t nnz, void *V, hipStream_t s);
+int launch_zz(const int32_t *tris, int64_t N, const void *mesh_ws, const void *pattern, int64_t nnz,
+              const double *sigma, int h_mode, double *eta2, hipStream_t s);
+int launch_capacity(const double *sigma, const double *area, int64_t N, double *cap, hipStream_t s);
+int launch_solve(int32_t precision, const SysDesc *d_desc, int n_sys, int total_wg, const SolveParams &p,
+                 hipStream_t s);
+int solve_capacity(int32_t precision);
+int solve_workgroups(int64_t N);
+int launch_set_desc(const SysDesc *h, int n, SysDesc *d, hipStream_t s);
+void gauss_legendre01(int n, double *x, double *w);
+}  // namespace bc

@@ -1,0 +1,277 @@
+// Element geometry, far-field quadrature tables and pair classification.
+//
+// Geometry (Section 2.1, plane triangles): area, centroid, squared diameter,
+// and the points/weights of the collapsed Gauss rule on each triangle, in
+// two layouts: per element (rows of the far-field kernel read one element's
+// points with uniform loads) and per point (columns read one point of 64
+// consecutive elements with coalesced loads).  FP32 copies are stored
+// relative to the element centroid so that differences of nearby points do
+// not cancel in FP32, with the reference-triangle weight in place of 2|T| w.
+//
+// Classification (pairs are told apart by shared vertex indices of the
+// conforming mesh, Section 2.1): for every ordered pair (i, j) the number of
+// shared vertices decides coincident / edge / vertex; pairs sharing none are
+// "near" when |c_i - c_j|^2 < nf^2 max(diam_i^2, diam_j^2).  The pattern is
+// built in two passes (count, then emit at scanned offsets) so that entries
+// are in (row, column) order without atomics.
+#include "bc_internal.h"
+
+namespace bc {
+
+struct FarRule {
+  int Q;
+  int pad;
+  double s[kQMax], t[kQMax], w[kQMax];
+};
+
+__global__ __launch_bounds__(kWG) void k_geometry(const double *__restrict__ verts, int64_t M,
+                                                  const int32_t *__restrict__ tris, int N, FarRule rule,
+                                                  int4 *tri4, double4 *cen4, double *area, double4 *qpA64,
+                                                  double *qpS64, float4 *qpA32, float *qpS32) {
+#pragma clang fp contract(off)
+  int e = blockIdx.x * kWG + threadIdx.x;
+  if (e >= N) return;
+  int a = tris[3 * e], b = tris[3 * e + 1], c = tris[3 * e + 2];
+  double p0x = verts[3 * a], p0y = verts[3 * a + 1], p0z = verts[3 * a + 2];
+  double p1x = verts[3 * b], p1y = verts[3 * b + 1], p1z = verts[3 * b + 2];
+  double p2x = verts[3 * c], p2y = verts[3 * c + 1], p2z = verts[3 * c + 2];
+  double ux = p1x - p0x, uy = p1y - p0y, uz = p1z - p0z;
+  double vx = p2x - p0x, vy = p2y - p0y, vz = p2z - p0z;
+  double nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
+  double A = 0.5 * sqrt(nx * nx + ny * ny + nz * nz);
+  double cx = (p0x + p1x + p2x) / 3.0, cy = (p0y + p1y + p2y) / 3.0, cz = (p0z + p1z + p2z) / 3.0;
+  double d01x = p1x - p0x, d01y = p1y - p0y, d01z = p1z - p0z;
+  double d12x = p2x - p1x, d12y = p2y - p1y, d12z = p2z - p1z;
+  double d20x = p0x - p2x, d20y = p0y - p2y, d20z = p0z - p2z;
+  double l01 = d01x * d01x + d01y * d01y + d01z * d01z;
+  double l12 = d12x * d12x + d12y * d12y + d12z * d12z;
+  double l20 = d20x * d20x + d20y * d20y + d20z * d20z;
+  double diam2 = fmax(fmax(l01, l12), l20);
+  tri4[e] = make_int4(a, b, c, 0);
+  cen4[e] = make_double4(cx, cy, cz, diam2);
+  area[e] = A;
+  for (int k = 0; k < kQMax; ++k) {
+    double x = 0, y = 0, z = 0, W = 0;
+    if (k < rule.Q) {
+      x = p0x + rule.s[k] * ux + rule.t[k] * vx;
+      y = p0y + rule.s[k] * uy + rule.t[k] * vy;
+      z = p0z + rule.s[k] * uz + rule.t[k] * vz;
+      W = 2.0 * A * rule.w[k];
+    }
+    qpA64[(size_t)e * kQMax + k] = make_double4(x, y, z, W);
+    qpS64[(size_t)(k * 4 + 0) * N + e] = x;
+    qpS64[(size_t)(k * 4 + 1) * N + e] = y;
+    qpS64[(size_t)(k * 4 + 2) * N + e] = z;
+    qpS64[(size_t)(k * 4 + 3) * N + e] = W;
+    float rx = k < rule.Q ? (float)(x - cx) : 0.f;
+    float ry = k < rule.Q ? (float)(y - cy) : 0.f;
+    float rz = k < rule.Q ? (float)(z - cz) : 0.f;
+    // FP32 tables carry the reference weight only; the element areas are
+    // applied per entry in FP64 (see k_far32)
+    float rw = k < rule.Q ? (float)rule.w[k] : 0.f;
+    qpA32[(size_t)e * kQMax + k] = make_float4(rx, ry, rz, rw);
+    qpS32[(size_t)(k * 4 + 0) * N + e] = rx;
+    qpS32[(size_t)(k * 4 + 1) * N + e] = ry;
+    qpS32[(size_t)(k * 4 + 2) * N + e] = rz;
+    qpS32[(size_t)(k * 4 + 3) * N + e] = rw;
+  }
+}
+
+// Shared vertices of two triangles (0..3).
+__device__ __forceinline__ int shared_count(int a0, int a1, int a2, int b0, int b1, int b2) {
+  return (a0 == b0) + (a0 == b1) + (a0 == b2) + (a1 == b0) + (a1 == b1) + (a1 == b2) + (a2 == b0) +
+         (a2 == b1) + (a2 == b2);
+}
+
+// Pair class of (i, j): 3/2/1 = coincident/edge/vertex, 0 = near, -1 = none.
+// The distance test is written without contraction so that it rounds like
+// the plain expression ((dx dx + dy dy) + dz dz) < nf2 max(d2_i, d2_j).
+__device__ __forceinline__ int pair_class(int4 ti, double4 ci, int4 tj, double4 cj, double nf2) {
+#pragma clang fp contract(off)
+  int s = shared_count(ti.x, ti.y, ti.z, tj.x, tj.y, tj.z);
+  if (s > 0) return s;
+  if (nf2 > 0.0) {
+    double dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
+    double r2 = dx * dx + dy * dy + dz * dz;
+    double thr = nf2 * fmax(ci.w, cj.w);
+    if (r2 < thr) return kNear;
+  }
+  return -1;
+}
+
+// One workgroup per block of 64 rows (16 rows per wave); lanes sweep the
+// columns 64 at a time.  Row data are staged in LDS (broadcast reads).
+// COUNT: rowcnt[i] = |pattern row i|, kindcnt[i][k] = pairs (i, j >= i) of
+// class k.  EMIT: write (col, row, kind) at rowptr[i] in column order.
+template <bool EMIT>
+__global__ __launch_bounds__(kWG) void k_pattern(const int4 *__restrict__ tri4, const double4 *__restrict__ cen4,
+                                                 int N, double nf2, int32_t *rowcnt, int32_t *kindcnt,
+                                                 const int32_t *__restrict__ rowptr, int32_t *pcol,
+                                                 int32_t *prow, int32_t *pkind) {
+  __shared__ int4 s_tri[64];
+  __shared__ double4 s_cen[64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int I0 = blockIdx.x * 64;
+  if (threadIdx.x < 64) {
+    int i = min(I0 + (int)threadIdx.x, N - 1);
+    s_tri[threadIdx.x] = tri4[i];
+    s_cen[threadIdx.x] = cen4[i];
+  }
+  __syncthreads();
+  int cnt[16], base[16];
+  int kc[16][4];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    cnt[k] = 0;
+    kc[k][0] = kc[k][1] = kc[k][2] = kc[k][3] = 0;
+    int i = I0 + w * 16 + k;
+    base[k] = (EMIT && i < N) ? rowptr[i] : 0;
+  }
+  for (int J0 = 0; J0 < N; J0 += 64) {
+    const int j = J0 + lane;
+    const bool jv = j < N;
+    int4 tj = tri4[jv ? j : N - 1];
+    double4 cj = cen4[jv ? j : N - 1];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int i = I0 + w * 16 + k;
+      if (i < N) {  // uniform
+        int cls = jv ? pair_class(s_tri[w * 16 + k], s_cen[w * 16 + k], tj, cj, nf2) : -1;
+        uint64_t m = __ballot(cls >= 0);
+        if (!EMIT) {
+          cnt[k] += __popcll(m);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) kc[k][q] += __popcll(__ballot(cls == q && j >= i));
+        } else {
+          if (cls >= 0) {
+            int pos = base[k] + __popcll(m & ((1ull << lane) - 1ull));
+            pcol[pos] = j;
+            prow[pos] = i;
+            pkind[pos] = cls;
+          }
+          base[k] += __popcll(m);
+        }
+      }
+    }
+  }
+  if (!EMIT && lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      int i = I0 + w * 16 + k;
+      if (i < N) {
+        rowcnt[i] = cnt[k];
+        for (int q = 0; q < 4; ++q) kindcnt[4 * i + q] = kc[k][q];
+      }
+    }
+  }
+}
+
+// Exclusive scan of the row counts (one workgroup of 1024 threads, each
+// owning a contiguous chunk) and the totals by class.  info[0] = nnz,
+// info[1..4] = coincident, edge, vertex, near pairs (i <= j); info[5] = 1 if
+// nnz overflows int32.
+__global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ rowcnt,
+                                               const int32_t *__restrict__ kindcnt, int N,
+                                               int32_t *rowptr, int64_t *info) {
+  __shared__ int64_t s_sum[1024];
+  __shared__ int64_t s_kind[4][1024];
+  const int t = threadIdx.x;
+  const int chunk = (N + 1023) / 1024;
+  const int b = min(N, t * chunk), e = min(N, b + chunk);
+  int64_t s = 0, k0 = 0, k1 = 0, k2 = 0, k3 = 0;
+  for (int i = b; i < e; ++i) {
+    s += rowcnt[i];
+    k0 += kindcnt[4 * i + 0];
+    k1 += kindcnt[4 * i + 1];
+    k2 += kindcnt[4 * i + 2];
+    k3 += kindcnt[4 * i + 3];
+  }
+  s_sum[t] = s;
+  s_kind[0][t] = k0;
+  s_kind[1][t] = k1;
+  s_kind[2][t] = k2;
+  s_kind[3][t] = k3;
+  __syncthreads();
+  if (t == 0) {
+    int64_t acc = 0, q0 = 0, q1 = 0, q2 = 0, q3 = 0;
+    for (int k = 0; k < 1024; ++k) {
+      int64_t v = s_sum[k];
+      s_sum[k] = acc;
+      acc += v;
+      q0 += s_kind[0][k];
+      q1 += s_kind[1][k];
+      q2 += s_kind[2][k];
+      q3 += s_kind[3][k];
+    }
+    info[0] = acc;
+    info[1] = q3;
+    info[2] = q2;
+    info[3] = q1;
+    info[4] = q0;
+    info[5] = acc > 2147483647ll ? 1 : 0;
+  }
+  __syncthreads();
+  int64_t acc = s_sum[t];
+  for (int i = b; i < e; ++i) {
+    rowptr[i] = (int32_t)acc;
+    acc += rowcnt[i];
+  }
+  if (t == 1023) rowptr[N] = (int32_t)acc;
+}
+
+int launch_geometry(const double *verts, int64_t M, const int32_t *tris, int64_t N, int far_order,
+                    void *mesh_ws, hipStream_t s) {
+  FarRule r{};
+  double x[8], w[8];
+  gauss_legendre01(far_order, x, w);
+  r.Q = far_order * far_order;
+  for (int a = 0; a < far_order; ++a)
+    for (int b = 0; b < far_order; ++b) {
+      int k = a * far_order + b;
+      r.s[k] = x[a];
+      r.t[k] = x[b] * (1.0 - x[a]);
+      r.w[k] = w[a] * w[b] * (1.0 - x[a]);
+    }
+  MeshLayout L(N);
+  char *base = static_cast<char *>(mesh_ws);
+  int grid = (int)((N + kWG - 1) / kWG);
+  hipLaunchKernelGGL(k_geometry, dim3(grid), dim3(kWG), 0, s, verts, M, tris, (int)N, r,
+                     reinterpret_cast<int4 *>(base + L.tri4), reinterpret_cast<double4 *>(base + L.cen4),
+                     reinterpret_cast<double *>(base + L.area), reinterpret_cast<double4 *>(base + L.qpA64),
+                     reinterpret_cast<double *>(base + L.qpS64), reinterpret_cast<float4 *>(base + L.qpA32),
+                     reinterpret_cast<float *>(base + L.qpS32));
+  return hipGetLastError() == hipSuccess ? BC_OK : BC_EDEVICE;
+}
+
+int launch_pattern(const int32_t *tris, int64_t N, double near_factor, const void *mesh_ws, void *pattern,
+                   int64_t nnz, int32_t precision, bool emit, hipStream_t s) {
+  (void)tris;
+  MeshLayout L(N);
+  char *base = static_cast<char *>(const_cast<void *>(mesh_ws));
+  const int4 *tri4 = reinterpret_cast<const int4 *>(base + L.tri4);
+  const double4 *cen4 = reinterpret_cast<const double4 *>(base + L.cen4);
+  int32_t *rowcnt = reinterpret_cast<int32_t *>(base + L.rowcnt);
+  int32_t *kindcnt = reinterpret_cast<int32_t *>(base + L.kindcnt);
+  int32_t *rowptr = reinterpret_cast<int32_t *>(base + L.rowptr);
+  double nf2 = near_factor * near_factor;
+  int grid = (int)((N + 63) / 64);
+  if (!emit) {
+    hipLaunchKernelGGL(k_pattern<false>, dim3(grid), dim3(kWG), 0, s, tri4, cen4, (int)N, nf2, rowcnt, kindcnt,
+                       (const int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr);
+    if (hipGetLastError() != hipSuccess) return BC_EDEVICE;
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, rowcnt, kindcnt, (int)N, rowptr,
+                       reinterpret_cast<int64_t *>(base + L.info));
+  } else {
+    PatternLayout P(N, nnz, precision);
+    char *pb = static_cast<char *>(pattern);
+    if (hipMemcpyAsync(pb + P.rowptr, rowptr, sizeof(int32_t) * (N + 1), hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return BC_EDEVICE;
+    hipLaunchKernelGGL(k_pattern<true>, dim3(grid), dim3(kWG), 0, s, tri4, cen4, (int)N, nf2, (int32_t *)nullptr,
+                       (int32_t *)nullptr, (const int32_t *)rowptr, reinterpret_cast<int32_t *>(pb + P.col),
+                       reinterpret_cast<int32_t *>(pb + P.row), reinterpret_cast<int32_t *>(pb + P.kind));
+  }
+  return hipGetLastError() == hipSuccess ? BC_OK : BC_EDEVICE;
+}
+
+}  // namespace bc

@@ -1,0 +1,348 @@
+"""GPU path (through the C ABI) against the CPU FP64 oracle, element by
+element on the same seeded inputs.
+
+Tolerances: FP64 matrix entries and the FP64 capacity to a relative 1e-12;
+the mixed-precision capacity to a relative 1e-8 (both as stated for the
+method's GPU forms); FP32 far-field entries to 4e-6 relative (a few FP32
+roundings of a 256-term sum of positive terms plus the hardware inverse
+square root, ~1 ulp each); integer work (pair classes, pattern) bit-exact.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1901_08393_amd import api as _api
+
+    return _api
+
+
+MESHES = {
+    "cube768": lambda: synth.cube(8),
+    "voxel": lambda: synth.voxel_union(3, 0.4, 21),  # N not a multiple of 64
+    "hull": lambda: synth.convex_hull(17, 5),
+    "ico2": lambda: synth.icosphere(2, 0.8),
+}
+
+_ORACLE = {}
+
+
+def oracle_V(name, far_order=4, ss_order=4):
+    key = (name, far_order, ss_order)
+    if key not in _ORACLE:
+        m = MESHES[name]() if name in MESHES else name
+        _ORACLE[key] = oracle.assemble(m.verts, m.tris, far_order, ss_order)
+    return _ORACLE[key]
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+# --------------------------------------------------------------- pattern
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_pattern_bit_exact(api, name):
+    _flush(f"pattern {name}")
+    m = MESHES[name]()
+    p = api.CapacityProblem(m.verts, m.tris, "fp64")
+    p.assemble()
+    torch.cuda.synchronize()
+    rowptr, col, row, kind, _ = [x.cpu().numpy() if x is not None else None for x in p.pattern_arrays()]
+    ref = oracle.classify_pairs(m.tris)
+    code = {"coincident": 3, "edge": 2, "vertex": 1}
+    expect = {}
+    for (i, j, k, _a, _b) in ref:
+        expect[(i, j)] = code[k]
+        expect[(j, i)] = code[k]
+    got = {(int(r), int(c)): int(k) for r, c, k in zip(row, col, kind)}
+    assert got == expect
+    # rows sorted by column, rowptr consistent
+    assert rowptr[0] == 0 and rowptr[-1] == len(col) == p.nnz
+    for i in range(m.N):
+        seg = col[rowptr[i]:rowptr[i + 1]]
+        assert np.all(np.diff(seg) > 0) and np.all(row[rowptr[i]:rowptr[i + 1]] == i)
+    assert p.info.n_coincident == m.N
+    assert p.info.n_edge == sum(1 for c in ref if c[2] == "edge")
+    assert p.info.n_vertex == sum(1 for c in ref if c[2] == "vertex")
+
+
+@pytest.mark.parametrize("name", ["cube768", "ico2"])
+def test_near_pattern_bit_exact(api, name):
+    _flush(f"near pattern {name}")
+    m = MESHES[name]()
+    p = api.CapacityProblem(m.verts, m.tris, "mixed", near_factor=1.5)
+    p.assemble()
+    torch.cuda.synchronize()
+    _, col, row, kind, _ = [x.cpu().numpy() if x is not None else None for x in p.pattern_arrays()]
+    got = {(int(r), int(c)) for r, c, k in zip(row, col, kind) if k == 0}
+    assert got == set(oracle.near_pairs(m.verts, m.tris, 1.5))
+
+
+# -------------------------------------------------------------- matrices
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_V_fp64_entrywise(api, name):
+    _flush(f"V fp64 {name}")
+    m = MESHES[name]()
+    p = api.CapacityProblem(m.verts, m.tris, "fp64")
+    V = p.assemble()
+    torch.cuda.synchronize()
+    Vg = V.cpu().numpy()
+    ref = oracle_V(name)
+    got = Vg[:, : m.N]
+    assert np.array_equal(got, got.T)
+    assert np.all(Vg[:, m.N:] == 0.0)
+    rel = np.abs(got - ref) / np.abs(ref)
+    assert rel.max() <= 1e-12, rel.max()
+
+
+@pytest.mark.parametrize("far,ss", [(1, 1), (2, 3), (3, 6), (4, 8)])
+def test_V_fp64_other_orders(api, far, ss):
+    _flush(f"V fp64 orders far={far} ss={ss}")
+    m = MESHES["hull"]()
+    p = api.CapacityProblem(m.verts, m.tris, "fp64", far_order=far, ss_order=ss)
+    Vg = p.assemble().cpu().numpy()[:, : m.N]
+    ref = oracle.assemble(m.verts, m.tris, far, ss)
+    assert (np.abs(Vg - ref) / np.abs(ref)).max() <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["cube768", "voxel"])
+def test_V_mixed_entrywise(api, name):
+    _flush(f"V mixed {name}")
+    m = MESHES[name]()
+    p = api.CapacityProblem(m.verts, m.tris, "mixed", near_factor=1.5)
+    V32 = p.assemble()
+    torch.cuda.synchronize()
+    V32 = V32.cpu().numpy()[:, : m.N].astype(np.float64)
+    rowptr, col, row, kind, corr = [x.cpu().numpy() for x in p.pattern_arrays()]
+    ref = oracle_V(name)
+    assert np.array_equal(V32, V32.T)
+    sparse = np.zeros_like(ref, dtype=bool)
+    sparse[row, col] = True
+    # FP64 entries (touching and near): V32 + correction reproduces FP64
+    v64 = V32[row, col] + corr
+    assert (np.abs(v64 - ref[row, col]) / ref[row, col]).max() <= 1e-12
+    # the stored FP32 value is the FP64 value rounded to nearest
+    assert np.array_equal(V32[row, col], ref[row, col].astype(np.float32).astype(np.float64)) or \
+        (np.abs(V32[row, col] - ref[row, col]) / ref[row, col]).max() <= 6.0e-8
+    far = ~sparse
+    relf = np.abs(V32[far] - ref[far]) / ref[far]
+    assert relf.max() <= 4e-6, relf.max()
+    # no systematic bias: to first order the capacity moves by
+    # -x^T (A - V64) x / x^T V64 x (A = stored FP32 matrix plus the FP64
+    # correction), which must stay well below the 1e-8 target
+    bias = np.mean((V32[far] - ref[far]) / ref[far])
+    rms = np.sqrt(np.mean(((V32[far] - ref[far]) / ref[far]) ** 2))
+    A = V32.copy()
+    A[row, col] += corr
+    x = oracle.solve_direct(ref, oracle.rhs(m.verts, m.tris))
+    wbias = x @ (A - ref) @ x / (x @ ref @ x)
+    _flush(f"  FP32 far-field relative error: mean {bias:.3e} rms {rms:.3e}; x-weighted {wbias:.3e}")
+    assert abs(wbias) <= 2e-9, wbias
+
+
+# ----------------------------------------------------------------- solves
+
+def _oracle_cap(name):
+    m = MESHES[name]()
+    V = oracle_V(name)
+    b = oracle.rhs(m.verts, m.tris)
+    x = oracle.solve_direct(V, b)
+    return oracle.capacity(x, b), V, b, x
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_solve_fp64_capacity(api, name):
+    _flush(f"solve fp64 {name}")
+    m = MESHES[name]()
+    cap_ref, Vref, b, xref = _oracle_cap(name)
+    p = api.CapacityProblem(m.verts, m.tris, "fp64")
+    p.assemble()
+    r = p.solve()
+    assert r.ok, r
+    assert abs(r.cap - cap_ref) / cap_ref <= 1e-12, (r.cap, cap_ref)
+    sig = p.sigma.cpu().numpy()
+    res = np.linalg.norm(b - Vref @ sig) / np.linalg.norm(b)  # oracle-evaluated residual
+    assert res <= 1e-12, res
+    assert r.rel_residual <= 1e-12
+    # the area array the solver used is the oracle's load vector
+    assert np.allclose(p.area.cpu().numpy(), b, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_solve_mixed_capacity(api, name):
+    _flush(f"solve mixed {name}")
+    m = MESHES[name]()
+    cap_ref, *_ = _oracle_cap(name)
+    p = api.CapacityProblem(m.verts, m.tris, "mixed")
+    p.assemble()
+    r = p.solve()
+    assert r.ok, r
+    err = abs(r.cap - cap_ref) / cap_ref
+    _flush(f"  mixed cap rel err {err:.3e} iters {r.iters} outer {r.outer}")
+    assert err <= 1e-8, err
+
+
+def test_capacity_reduction(api):
+    m = MESHES["cube768"]()
+    p = api.CapacityProblem(m.verts, m.tris, "fp64")
+    rng = np.random.default_rng(3)
+    s = rng.uniform(0.1, 2.0, m.N)
+    got = p.capacity_of(torch.from_numpy(s).cuda())
+    ref = math.fsum((s * p.area.cpu().numpy()).tolist()) / (4 * math.pi)
+    assert abs(got - ref) <= 1e-14 * ref
+
+
+@pytest.mark.parametrize("name", ["cube768", "voxel", "hull"])
+def test_zz_indicators(api, name):
+    _flush(f"zz {name}")
+    m = MESHES[name]()
+    cap_ref, V, b, x = _oracle_cap(name)
+    p = api.CapacityProblem(m.verts, m.tris, "fp64")
+    p.assemble()
+    for h_mode, hname in ((0, "diam"), (1, "area")):
+        eta2 = p.zz(torch.from_numpy(x).cuda(), h_mode).cpu().numpy()
+        ref = oracle.zz_indicators(m.verts, m.tris, x, hname)
+        assert np.allclose(eta2, ref, rtol=1e-12, atol=1e-12 * ref.max())
+
+
+# ---------------------------------------------------------------- batching
+
+def test_batched_equals_alone_bitwise(api):
+    _flush("batched vs alone")
+    meshes = [MESHES["hull"](), MESHES["voxel"](), MESHES["cube768"]()]
+    for prec in ("fp64", "mixed"):
+        alone = []
+        for m in meshes:
+            p = api.CapacityProblem(m.verts, m.tris, prec)
+            p.assemble()
+            r = p.solve()
+            alone.append((r, p.sigma.cpu().numpy().copy()))
+        probs = []
+        for m in meshes:
+            p = api.CapacityProblem(m.verts, m.tris, prec)
+            p.assemble()
+            probs.append(p)
+        keep = api.solve_batched(probs, prec)
+        torch.cuda.synchronize()
+        del keep
+        for (ra, sa), p in zip(alone, probs):
+            rb = p.result()
+            assert rb.ok and rb.cap == ra.cap and rb.iters == ra.iters
+            assert np.array_equal(p.sigma.cpu().numpy(), sa)
+        # chunked continuous batching: resume until every system is done
+        for p in probs:
+            p.sigma.zero_()
+        start = [1] * len(probs)
+        for _ in range(10000):
+            keep = api.solve_batched(probs, prec, iter_budget=7, start=start)
+            torch.cuda.synchronize()
+            del keep
+            res = [p.result() for p in probs]
+            if all(r.status != 1 for r in res):
+                break
+            start = [0] * len(probs)
+        for (ra, sa), p, rb in zip(alone, probs, res):
+            assert rb.ok and rb.cap == ra.cap
+            assert np.array_equal(p.sigma.cpu().numpy(), sa)
+
+
+# -------------------------------------------------------------- edge cases
+
+def test_smallest_meshes(api):
+    _flush("smallest meshes")
+    tet = synth.Mesh(np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float),
+                     np.array([[0, 2, 1], [0, 1, 3], [0, 3, 2], [1, 2, 3]], np.int32))
+    for m in (tet, synth.icosphere(0)):
+        V = oracle.assemble(m.verts, m.tris)
+        b = oracle.rhs(m.verts, m.tris)
+        cap_ref = oracle.capacity(oracle.solve_direct(V, b), b)
+        p = api.CapacityProblem(m.verts, m.tris, "fp64")
+        Vg = p.assemble().cpu().numpy()[:, : m.N]
+        assert (np.abs(Vg - V) / V).max() <= 1e-12
+        r = p.solve()
+        assert r.ok and abs(r.cap - cap_ref) <= 1e-12 * cap_ref
+
+
+def test_invalid_inputs_rejected(api):
+    from paper_1901_08393_amd import _lib
+
+    m = synth.cube(2)
+    bad = m.tris.copy()
+    bad[0, 1] = bad[0, 0]
+    with pytest.raises(_lib.BemcapError):
+        api.CapacityProblem(m.verts, bad)
+    with pytest.raises(_lib.BemcapError):
+        api.CapacityProblem(m.verts, m.tris[:-1])  # open surface
+    with pytest.raises(_lib.BemcapError):
+        api.CapacityProblem(m.verts, m.tris, far_order=5)
+
+
+def test_no_convergence_and_breakdown_status(api):
+    from paper_1901_08393_amd import _lib
+
+    m = synth.cube(4)
+    p = api.CapacityProblem(m.verts, m.tris, "fp64")
+    p.assemble()
+    r = p.solve(max_iter=1, max_outer=1)
+    assert r.status == _lib.BC_ENOCONV
+    p.V.neg_()  # negative definite: p^T V p < 0 at the first step
+    r = p.solve(jacobi=0)
+    assert r.status == _lib.BC_EBREAKDOWN
+
+
+def test_nested_cube_capacity_monotone(api):
+    caps = []
+    for n in (2, 4, 8):
+        m = synth.cube(n)
+        caps.append(api.capacity(m.verts, m.tris, "fp64").cap)
+    assert caps[0] < caps[1] < caps[2] < 0.66067815409957
+
+
+def test_warm_start_same_answer(api):
+    m = MESHES["voxel"]()
+    p = api.CapacityProblem(m.verts, m.tris, "fp64")
+    p.assemble()
+    r0 = p.solve()
+    x0 = p.sigma.clone() * 0.9
+    r1 = p.solve(x0=x0)
+    assert r1.ok and abs(r1.cap - r0.cap) <= 1e-12 * r0.cap
+    assert r1.iters < r0.iters
+
+
+# ------------------------------------------------- full-size sampled checks
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_icosphere_L5_sampled_rows(api, prec):
+    """Full 20480-element sphere in the launch configuration the benchmark
+    times: sampled rows against the oracle, computed one row at a time."""
+    _flush(f"L5 sampled rows {prec}")
+    m = synth.icosphere(5, 1.3)
+    p = api.CapacityProblem(m.verts, m.tris, prec)
+    V = p.assemble()
+    rows = [0, 1, 777, 10240, 20479]
+    got = V[rows].cpu().numpy()[:, : m.N].astype(np.float64)
+    ref = oracle.assemble_rows(m.verts, m.tris, rows)
+    if prec == "fp64":
+        assert (np.abs(got - ref) / ref).max() <= 1e-12
+    else:
+        rel = np.abs(got - ref) / ref
+        assert rel.max() <= 4e-6
+    r = p.solve()
+    assert r.ok
+    # sphere: the discrete capacity is below r and within 0.2 % of it at L5
+    assert r.cap < 1.3 and (1.3 - r.cap) / 1.3 < 2e-3
+    del V
+    p.release_matrix()
