@@ -14,7 +14,9 @@ namespace bc {
 constexpr int kWG = 256;            // threads per workgroup (4 wave64)
 constexpr int kQMax = 16;           // far-field points per triangle (order <= 4)
 constexpr int kSSMax = 8;           // Gauss points per coordinate, singular rules
-constexpr int kGMax = 1024;         // workgroups per system in the solver
+constexpr int kGMax = 256;          // workgroups per system in the solver
+constexpr int kSolveWG = 1024;      // threads per solver workgroup (16 wave64)
+constexpr int kNRep = 16;           // copies of the solver's release record
 constexpr double kInv4Pi = 0.079577471545947667884441881686257181;  // 1/(4 pi)
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -87,29 +89,51 @@ struct PatternLayout {
 };
 
 // ---------------------------------------------------------------- solver ws
+// Barrier slot of one solver workgroup (its partial sums and arrival tag)
+// and the release record the master workgroup publishes; 64 bytes each.
+struct alignas(64) BarSlot {
+  double v[4];
+  unsigned tag;
+  unsigned pad[7];
+};
+struct alignas(64) BarRel {
+  double v[4];
+  unsigned gen;
+  int abort;
+  unsigned pad[6];
+};
+
+__host__ __device__ inline void solve_offsets(int64_t N, int32_t precision, size_t &ctl, size_t &slots,
+                                              size_t &rel, size_t &x64, size_t &r64, size_t &vec, size_t &total,
+                                              int64_t &ld) {
+  ld = (N + 63) / 64 * 64;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = (o + bytes + 255) & ~size_t(255);
+    return r;
+  };
+  ctl = take(1024);
+  slots = take(sizeof(BarSlot) * kGMax);
+  rel = take(sizeof(BarRel) * kNRep);
+  x64 = take(sizeof(double) * ld);
+  r64 = take(sizeof(double) * ld);
+  vec = take((precision == BC_FP64 ? 8 : 4) * ld * 7);  // r u w p s d invdiag
+  total = o;
+}
+
 struct SolveLayout {
-  size_t ctl, partial, x64, r64, vec, total;
+  size_t ctl, slots, rel, x64, r64, vec, total;
   int64_t ld;
-  SolveLayout(int64_t N, int32_t precision) {
-    ld = ld_of(N);
-    size_t o = 0;
-    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
-    ctl = take(1024);
-    partial = take(sizeof(double) * 2 * 4 * kGMax);  // two sets, by barrier epoch parity
-    x64 = take(sizeof(double) * ld);
-    r64 = take(sizeof(double) * ld);
-    size_t es = precision == BC_FP64 ? 8 : 4;
-    vec = take(es * ld * 7);  // r u w p s d invdiag
-    total = o;
-  }
+  SolveLayout(int64_t N, int32_t precision) { solve_offsets(N, precision, ctl, slots, rel, x64, r64, vec, total, ld); }
 };
 
 // Per-system control block at the start of the solver workspace.  Written
 // only by workgroup 0 of the system (state save) and by the barrier.
 struct SolveCtl {
-  unsigned bar_count;
-  unsigned bar_gen;
-  int32_t abort;       // set on barrier timeout
+  unsigned bar_count;  // unused (kept for layout stability)
+  unsigned bar_gen;    // unused
+  int32_t abort;       // unused
   int32_t phase;
   int32_t iters;
   int32_t outer;
@@ -148,6 +172,16 @@ struct SolveParams {
 };
 
 // --------------------------------------------------------- device helpers
+// Pointers in the global address space.  Pointers read from descriptors in
+// memory are generic to the compiler, which would then emit flat loads;
+// casting them once makes every access a global load/store.
+template <typename T>
+using gptr = T __attribute__((address_space(1))) *;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T *p) {
+  return (gptr<T>)p;
+}
+
 // Inverse square root in FP64: hardware estimate refined by one step of the
 // cubically convergent iteration y <- y (1 + e/2 + 3e^2/8), e = 1 - x y^2
 // (Householder's method of order 2 applied to f(y) = y^-2 - x).

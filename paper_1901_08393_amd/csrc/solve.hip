@@ -3,8 +3,9 @@
 // reduction Cap = (1/4pi) sum sigma_i |T_i| (eq. "cap:ell").
 //
 // One cooperative launch holds one or many systems; each system owns a fixed
-// number of workgroups (a function of N only), each workgroup a contiguous
-// band of rows.  Per system the workgroups run the same state machine:
+// number of 1024-thread workgroups (a function of N only), each workgroup a
+// contiguous band of rows and each wavefront a contiguous part of that band.
+// Per system the workgroups run the same state machine:
 //
 //   RESID  r = b - A x in FP64 (A = V, plus the FP64 sparse correction of
 //          touching/near entries in mixed precision); stop if
@@ -19,10 +20,10 @@
 //   DONE   sigma = x, Cap, result.
 //
 // The dense product streams V once from HBM (bandwidth-bound: 4 or 8 bytes
-// per entry, 2 flops): all 256 threads of a workgroup sweep 8 rows at a time
-// with 16-byte non-temporal loads, the vector comes from L2.  Every
-// reduction has a fixed order, so results are bitwise reproducible and do
-// not depend on which other systems share the launch.
+// per entry, 2 flops): the 64 lanes of a wavefront sweep up to 8 of its rows
+// at a time with 16-byte non-temporal loads; the vector comes from L2.
+// Every reduction has a fixed order, so results are bitwise reproducible and
+// do not depend on which other systems share the launch.
 #include <climits>
 
 #include "bc_internal.h"
@@ -34,184 +35,219 @@ enum Phase : int32_t { PH_INIT = 0, PH_RESID = 1, PH_CG = 2, PH_UPDATE = 3, PH_D
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 
-__host__ __device__ inline void solve_offsets(int64_t N, int32_t precision, size_t &ctl, size_t &partial,
-                                              size_t &x64, size_t &r64, size_t &vec, int64_t &ld) {
-  ld = (N + 63) / 64 * 64;
-  size_t o = 0;
-  auto take = [&](size_t bytes) {
-    size_t r = o;
-    o = (o + bytes + 255) & ~size_t(255);
-    return r;
-  };
-  ctl = take(1024);
-  partial = take(sizeof(double) * 2 * 4 * kGMax);
-  x64 = take(sizeof(double) * ld);
-  r64 = take(sizeof(double) * ld);
-  vec = take((precision == BC_FP64 ? 8 : 4) * ld * 7);
-}
+constexpr int kWaves = kSolveWG / 64;
 
 // ------------------------------------------------------------ barrier
-struct SysBarrier {
-  SolveCtl *ctl;
-  int G;
-  unsigned gen;
+// Cross-workgroup barrier of one system fused with a fixed-order reduction.
+// Every workgroup writes its partial sums and the barrier epoch into its own
+// 64-byte slot (no contended atomics); workgroup 0 of the system gathers the
+// slots in rank order, sums them and publishes the totals with the epoch in
+// kNRep copies of a release record; each workgroup waits on one copy.  Only
+// one thread per workgroup issues the agent-scope release and acquire fences
+// (an L2 write-back and an L2 invalidate), after every wavefront has waited
+// for its own stores, so a barrier costs one fence pair per workgroup.
+// Spins are bounded: on time-out the system is marked aborted and every
+// workgroup leaves its loop.
+struct SysBar {
+  gptr<BarSlot> slots;
+  gptr<BarRel> rel;
+  int G, rank;
+  unsigned epoch;
   uint32_t spin_limit;
-
-  // All workgroups of the system; returns false if the system was aborted
-  // (a barrier exceeded its spin limit somewhere).
-  __device__ bool sync(int *s_flag) {
-    if (G == 1) {
-      __syncthreads();
-      return true;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const unsigned target = gen + 1u;
-      int ok = 1;
-      unsigned prev = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (prev == (unsigned)G - 1u) {
-        __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&ctl->bar_gen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        uint32_t spins = 0;
-        while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
-          __builtin_amdgcn_s_sleep(2);
-          if (++spins > spin_limit ||
-              __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-            ok = 0;
-            break;
-          }
-        }
-      }
-      if (!ok) __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      *s_flag = ok;
-    }
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    gen += 1u;
-    return *s_flag != 0;
-  }
 };
 
-// Workgroup sum of K values; every thread receives the totals.
 template <int K>
-__device__ __forceinline__ void wg_sum(double (&v)[K], double *lds) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < K; ++k) lds[w * K + k] = v[k];
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = ((lds[k] + lds[K + k]) + lds[2 * K + k]) + lds[3 * K + k];
-  __syncthreads();
-}
-
-// Sum of slot values of the G workgroup partials of one set (fixed order).
-template <int K>
-__device__ __forceinline__ void sum_partials(const double *set, int G, const int (&slot)[K], double (&out)[K],
-                                             double *lds) {
+__device__ __noinline__ bool sys_sync(SysBar &B, const double (&v)[K], double (&tot)[K], double *lds, int *flag) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    double a = 0.0;
-    for (int g = threadIdx.x; g < G; g += kWG) a += set[4 * g + slot[k]];
-    out[k] = a;
+    const double s = wave_sum(v[k]);
+    if (lane == 0) lds[w * 4 + k] = s;
   }
-  wg_sum<K>(out, lds);
+  __builtin_amdgcn_s_waitcnt(0);  // this wavefront's global stores have reached L2
+  __syncthreads();
+  B.epoch += 1u;
+  const unsigned ep = B.epoch;
+  if (B.G == 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int q = 0; q < kWaves; ++q) s += lds[q * 4 + k];
+      tot[k] = s;
+    }
+    __syncthreads();
+    return true;
+  }
+  if (t == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int q = 0; q < kWaves; ++q) s += lds[q * 4 + k];
+      B.slots[B.rank].v[k] = s;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&B.slots[B.rank].tag, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  int ok = 1;
+  if (B.rank == 0) {
+    double a[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) a[k] = 0.0;
+    if (t < B.G) {
+      uint32_t spins = 0;
+      while (__hip_atomic_load(&B.slots[t].tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ep) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > B.spin_limit) {
+          ok = 0;
+          break;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (t < B.G) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) a[k] = B.slots[t].v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double s = wave_sum(a[k]);
+      if (lane == 0) lds[w * 4 + k] = s;
+    }
+    const int bad = __syncthreads_or(!ok);
+    if (t < kNRep) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int q = 0; q < kWaves; ++q) s += lds[q * 4 + k];
+        B.rel[t].v[k] = s;
+      }
+      B.rel[t].abort = bad;
+    }
+    if (t < 64) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (t < kNRep) __hip_atomic_store(&B.rel[t].gen, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (t == 0) {
+    gptr<BarRel> my = B.rel + (B.rank % kNRep);
+    uint32_t spins = 0;
+    while (__hip_atomic_load(&my->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ep) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > B.spin_limit) {
+        ok = 0;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (ok && my->abort) ok = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) lds[64 + k] = my->v[k];
+    *flag = ok;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) tot[k] = lds[64 + k];
+  const int r = *flag;
+  __syncthreads();
+  return r != 0;
 }
 
+// ------------------------------------------------------- matrix product
 template <typename MT, typename XT>
 struct Load16;
 template <>
 struct Load16<float, float> {  // 4 matrix entries, 4 vector entries
   static constexpr int VEC = 4;
-  __device__ static void mat(const float *p, float (&v)[4]) {
-    f4 t = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(p));
+  __device__ static void mat(gptr<const float> p, float (&v)[4]) {
+    f4 t = __builtin_nontemporal_load(reinterpret_cast<gptr<const f4>>(p));
     v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
   }
-  __device__ static void vec(const float *p, float (&v)[4]) {
-    f4 t = *reinterpret_cast<const f4 *>(p);
+  __device__ static void vec(gptr<const float> p, float (&v)[4]) {
+    f4 t = *reinterpret_cast<gptr<const f4>>(p);
     v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
   }
 };
 template <>
 struct Load16<float, double> {
   static constexpr int VEC = 4;
-  __device__ static void mat(const float *p, float (&v)[4]) { Load16<float, float>::mat(p, v); }
-  __device__ static void vec(const double *p, double (&v)[4]) {
-    d2 a = reinterpret_cast<const d2 *>(p)[0], b = reinterpret_cast<const d2 *>(p)[1];
+  __device__ static void mat(gptr<const float> p, float (&v)[4]) { Load16<float, float>::mat(p, v); }
+  __device__ static void vec(gptr<const double> p, double (&v)[4]) {
+    d2 a = reinterpret_cast<gptr<const d2>>(p)[0], b = reinterpret_cast<gptr<const d2>>(p)[1];
     v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
   }
 };
 template <>
 struct Load16<double, double> {
   static constexpr int VEC = 2;
-  __device__ static void mat(const double *p, double (&v)[2]) {
-    d2 t = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(p));
+  __device__ static void mat(gptr<const double> p, double (&v)[2]) {
+    d2 t = __builtin_nontemporal_load(reinterpret_cast<gptr<const d2>>(p));
     v[0] = t.x; v[1] = t.y;
   }
-  __device__ static void vec(const double *p, double (&v)[2]) {
-    d2 t = *reinterpret_cast<const d2 *>(p);
+  __device__ static void vec(gptr<const double> p, double (&v)[2]) {
+    d2 t = *reinterpret_cast<gptr<const d2>>(p);
     v[0] = t.x; v[1] = t.y;
   }
 };
 
-constexpr int kR = 8;  // rows per sweep of a workgroup
-
-// out(i) = sum_j V[i][j] x[j] for rows [r0, r1), accumulated in AT; the
-// epilogue is called by thread r for row g0 + r.
-template <typename MT, typename XT, typename AT, typename Epi>
-__device__ __forceinline__ void band_matvec(const MT *__restrict__ V, int64_t ld, const XT *__restrict__ x, int r0,
-                                            int r1, AT *lds, Epi epi) {
+// out(i) = sum_j V[i][j] x[j] for the R rows g0..g0+R-1: the 64 lanes of the
+// wavefront sweep the columns with 16-byte loads, R independent rows per
+// step (no branch inside the sweep, so all loads of a step are in flight
+// together); lane 0 calls epi(row, sum) after a fixed-order reduction.
+template <typename MT, typename XT, typename AT, int R, typename Epi>
+__device__ __forceinline__ void sweep_rows(gptr<const MT> V, int64_t ld, gptr<const XT> x, int g0, Epi &epi) {
   using L = Load16<MT, XT>;
   constexpr int VEC = L::VEC;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  for (int g0 = r0; g0 < r1; g0 += kR) {
-    AT acc[kR];
+  const int lane = threadIdx.x & 63;
+  AT acc[R];
 #pragma unroll
-    for (int r = 0; r < kR; ++r) acc[r] = AT(0);
-    const int nr = min(kR, r1 - g0);
-    const MT *row0 = V + (size_t)g0 * ld;
-#pragma unroll 1
-    for (int64_t c = (int64_t)t * VEC; c < ld; c += (int64_t)kWG * VEC) {
-      XT xv[VEC];
-      L::vec(x + c, xv);
+  for (int r = 0; r < R; ++r) acc[r] = AT(0);
+  gptr<const MT> row0 = V + (size_t)g0 * ld;
+#pragma unroll 2
+  for (int64_t c = (int64_t)lane * VEC; c < ld; c += 64 * VEC) {
+    XT xv[VEC];
+    L::vec(x + c, xv);
+    MT vv[R][VEC];
 #pragma unroll
-      for (int r = 0; r < kR; ++r) {
-        if (r < nr) {
-          MT vv[VEC];
-          L::mat(row0 + (size_t)r * ld + c, vv);
+    for (int r = 0; r < R; ++r) L::mat(row0 + (size_t)r * ld + c, vv[r]);
 #pragma unroll
-          for (int q = 0; q < VEC; ++q) acc[r] = __builtin_fma((AT)vv[q], (AT)xv[q], acc[r]);
-        }
-      }
-    }
+    for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int r = 0; r < kR; ++r) acc[r] = wave_sum(acc[r]);
-    if (lane == 0)
+      for (int q = 0; q < VEC; ++q) acc[r] = __builtin_fma((AT)vv[r][q], (AT)xv[q], acc[r]);
+  }
 #pragma unroll
-      for (int r = 0; r < kR; ++r) lds[w * kR + r] = acc[r];
-    __syncthreads();
-    if (t < nr) {
-      AT v = ((lds[t] + lds[kR + t]) + lds[2 * kR + t]) + lds[3 * kR + t];
-      epi(g0 + t, v);
-    }
-    __syncthreads();
+  for (int r = 0; r < R; ++r) {
+    const AT sum = wave_sum(acc[r]);
+    if (lane == 0) epi(g0 + r, sum);
   }
 }
 
-// At most 128 VGPRs, so that four workgroups fit on every CU (kGMax = 1024
-// co-resident workgroups on 256 CUs).
+// The rows [wr0, wr1) of this wavefront, at most 8 per sweep.
+template <typename MT, typename XT, typename AT, typename Epi>
+__device__ __forceinline__ void wave_matvec(gptr<const MT> V, int64_t ld, gptr<const XT> x, int wr0, int wr1,
+                                            Epi epi) {
+  int g0 = wr0;
+  while (g0 < wr1) {
+    const int n = min(8, wr1 - g0);
+    switch (n) {
+      case 8: sweep_rows<MT, XT, AT, 8>(V, ld, x, g0, epi); break;
+      case 7: sweep_rows<MT, XT, AT, 7>(V, ld, x, g0, epi); break;
+      case 6: sweep_rows<MT, XT, AT, 6>(V, ld, x, g0, epi); break;
+      case 5: sweep_rows<MT, XT, AT, 5>(V, ld, x, g0, epi); break;
+      case 4: sweep_rows<MT, XT, AT, 4>(V, ld, x, g0, epi); break;
+      case 3: sweep_rows<MT, XT, AT, 3>(V, ld, x, g0, epi); break;
+      case 2: sweep_rows<MT, XT, AT, 2>(V, ld, x, g0, epi); break;
+      default: sweep_rows<MT, XT, AT, 1>(V, ld, x, g0, epi); break;
+    }
+    g0 += n;
+  }
+}
+
+// At most 128 VGPRs, so that one 1024-thread workgroup fits on every CU.
 template <typename MT>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_solve(
+__global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) void k_solve(
     const SysDesc *__restrict__ descs, SolveParams P) {
   using VT = MT;
   constexpr bool MIXED = sizeof(MT) == 4;
-  __shared__ double s_red[4 * 4];
-  __shared__ double s_mvd[4 * kR];
-  __shared__ VT s_mv[4 * kR];
+  __shared__ double s_red[80];
   __shared__ int s_flag;
 
   // system of this workgroup: last descriptor with wg_begin <= blockIdx.x
@@ -225,31 +261,36 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
   if (rank < 0 || rank >= S.wg_count) return;
   const int G = S.wg_count;
   const int N = (int)S.N;
+  const int t = threadIdx.x, w = t >> 6;
   const int r0 = (int)((int64_t)N * rank / G), r1 = (int)((int64_t)N * (rank + 1) / G);
-  size_t o_ctl, o_part, o_x, o_r, o_vec;
+  const int nb = r1 - r0;
+  const int wr0 = r0 + nb * w / kWaves, wr1 = r0 + nb * (w + 1) / kWaves;  // this wavefront's rows
+  size_t o_ctl, o_slots, o_rel, o_x, o_r, o_vec, o_total;
   int64_t ld;
-  solve_offsets(S.N, MIXED ? BC_MIXED : BC_FP64, o_ctl, o_part, o_x, o_r, o_vec, ld);
-  SolveCtl *ctl = reinterpret_cast<SolveCtl *>(S.ws + o_ctl);
-  double *part = reinterpret_cast<double *>(S.ws + o_part);
-  double *x64 = reinterpret_cast<double *>(S.ws + o_x);
-  double *r64 = reinterpret_cast<double *>(S.ws + o_r);
-  VT *vr = reinterpret_cast<VT *>(S.ws + o_vec);
-  VT *vu = vr + ld, *vw = vu + ld, *vp = vw + ld, *vs = vp + ld, *vd = vs + ld, *idg = vd + ld;
-  const MT *V = static_cast<const MT *>(S.V);
-  const double *b = S.area;
-  const int t = threadIdx.x;
+  solve_offsets(S.N, MIXED ? BC_MIXED : BC_FP64, o_ctl, o_slots, o_rel, o_x, o_r, o_vec, o_total, ld);
+  gptr<char> ws = as_global(S.ws);
+  gptr<SolveCtl> ctl = reinterpret_cast<gptr<SolveCtl>>(ws + o_ctl);
+  gptr<double> x64 = reinterpret_cast<gptr<double>>(ws + o_x);
+  gptr<double> r64 = reinterpret_cast<gptr<double>>(ws + o_r);
+  gptr<VT> vr = reinterpret_cast<gptr<VT>>(ws + o_vec);
+  gptr<VT> vu = vr + ld, vw = vu + ld, vp = vw + ld, vs = vp + ld, vd = vs + ld, idg = vd + ld;
+  gptr<const MT> V = as_global(static_cast<const MT *>(S.V));
+  gptr<const double> b = as_global(S.area);
+  gptr<double> sigma = as_global(S.sigma);
+  gptr<bc_result> result = as_global(S.result);
+  gptr<const double> pcorr = as_global(S.pcorr);
+  gptr<const int32_t> prowptr = as_global(S.prowptr), pcol = as_global(S.pcol);
 
-  SysBarrier bar{ctl, G, __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                 P.spin_limit};
+  SysBar bar{reinterpret_cast<gptr<BarSlot>>(ws + o_slots), reinterpret_cast<gptr<BarRel>>(ws + o_rel), G, rank, 0u,
+             P.spin_limit};
 
   int32_t phase, iters, outer, inner;
-  uint32_t epoch;
   double bnorm, rnorm, scale, gamma, eta, alpha, beta;
   if (S.start) {
-    phase = PH_INIT; iters = 0; outer = 0; inner = 0; epoch = 0;
+    phase = PH_INIT; iters = 0; outer = 0; inner = 0;
     bnorm = rnorm = scale = gamma = eta = alpha = beta = 0.0;
   } else {
-    phase = ctl->phase; iters = ctl->iters; outer = ctl->outer; inner = ctl->inner; epoch = ctl->epoch;
+    phase = ctl->phase; iters = ctl->iters; outer = ctl->outer; inner = ctl->inner; bar.epoch = ctl->epoch;
     bnorm = ctl->bnorm; rnorm = ctl->rnorm; scale = ctl->scale; gamma = ctl->gamma; eta = ctl->eta;
     alpha = ctl->alpha; beta = ctl->beta;
   }
@@ -257,29 +298,22 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
   int32_t status = BC_OK;
   int budget = P.iter_budget > 0 ? P.iter_budget : INT_MAX;
   bool aborted = false;
-
-  auto my_part = [&](int k) -> double * { return part + ((size_t)(epoch & 1u) * kGMax + rank) * 4 + k; };
-  auto prev_set = [&]() -> const double * { return part + (size_t)((epoch - 1u) & 1u) * kGMax * 4; };
-  // every partial set written in epoch e is read only in epoch e + 1
-  auto sync = [&]() -> bool {
-    bool ok = bar.sync(&s_flag);
-    epoch += 1u;
-    return ok;
-  };
+  const double none[1] = {0.0};
 
   while (true) {
     if (phase == PH_INIT) {
-      for (int i = r0 + t; i < r1; i += kWG) {
-        x64[i] = P.x0_given ? S.sigma[i] : 0.0;
+      for (int i = r0 + t; i < r1; i += kSolveWG) {
+        x64[i] = P.x0_given ? sigma[i] : 0.0;
         idg[i] = P.jacobi ? VT(1) / V[(size_t)i * ld + i] : VT(1);
       }
       if (rank == G - 1)
-        for (int i = N + t; i < ld; i += kWG) {
+        for (int i = N + t; i < ld; i += kSolveWG) {
           x64[i] = 0.0; r64[i] = 0.0;
           vr[i] = vu[i] = vw[i] = vp[i] = vs[i] = vd[i] = VT(0);
           idg[i] = VT(0);
         }
-      if (!sync()) { aborted = true; break; }
+      double dummy[1];
+      if (!sys_sync<1>(bar, none, dummy, s_red, &s_flag)) { aborted = true; break; }
       phase = PH_RESID;
       continue;
     }
@@ -288,9 +322,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       budget -= 2;
       // r = b - A x in FP64
       double pr = 0.0, pb = 0.0;
-      band_matvec<MT, double, double>(V, ld, x64, r0, r1, s_mvd, [&](int i, double acc) {
+      wave_matvec<MT, double, double>(V, ld, x64, wr0, wr1, [&](int i, double acc) {
         if (MIXED && S.pcorr != nullptr) {
-          for (int e = S.prowptr[i]; e < S.prowptr[i + 1]; ++e) acc = __builtin_fma(S.pcorr[e], x64[S.pcol[e]], acc);
+          for (int e = prowptr[i]; e < prowptr[i + 1]; ++e) acc = __builtin_fma(pcorr[e], x64[pcol[e]], acc);
         }
         const double ri = b[i] - acc;
         r64[i] = ri;
@@ -298,15 +332,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
         pb = __builtin_fma(b[i], b[i], pb);
       });
       {
-        double v[2] = {pr, pb};
-        wg_sum<2>(v, s_red);
-        if (t == 0) { *my_part(0) = v[0]; *my_part(1) = v[1]; }
-      }
-      if (!sync()) { aborted = true; break; }
-      {
+        const double v[2] = {pr, pb};
         double tot[2];
-        const int sl[2] = {0, 1};
-        sum_partials<2>(prev_set(), G, sl, tot, s_red);
+        if (!sys_sync<2>(bar, v, tot, s_red, &s_flag)) { aborted = true; break; }
         if (outer == 0) bnorm = sqrt(tot[1]);
         rnorm = sqrt(tot[0]);
       }
@@ -316,39 +344,27 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       scale = 1.0 / rnorm;
       // inner start: r = r64 / ||r64||, u = M^-1 r, d = p = s = 0
       double pru = 0.0;
-      for (int i = r0 + t; i < r1; i += kWG) {
+      for (int i = r0 + t; i < r1; i += kSolveWG) {
         const VT ri = (VT)(r64[i] * scale);
         const VT ui = idg[i] * ri;
         vr[i] = ri; vu[i] = ui; vd[i] = VT(0); vp[i] = VT(0); vs[i] = VT(0);
         pru += (double)ri * (double)ui;
       }
       {
-        double v[1] = {pru};
-        wg_sum<1>(v, s_red);
-        if (t == 0) *my_part(0) = v[0];
-      }
-      if (!sync()) { aborted = true; break; }
-      {
+        const double v[1] = {pru};
         double tot[1];
-        const int sl[1] = {0};
-        sum_partials<1>(prev_set(), G, sl, tot, s_red);
+        if (!sys_sync<1>(bar, v, tot, s_red, &s_flag)) { aborted = true; break; }
         gamma = tot[0];
       }
       double pwu = 0.0;
-      band_matvec<MT, VT, VT>(V, ld, vu, r0, r1, s_mv, [&](int i, VT acc) {
+      wave_matvec<MT, VT, VT>(V, ld, vu, wr0, wr1, [&](int i, VT acc) {
         vw[i] = acc;
         pwu += (double)acc * (double)vu[i];
       });
       {
-        double v[1] = {pwu};
-        wg_sum<1>(v, s_red);
-        if (t == 0) *my_part(0) = v[0];
-      }
-      if (!sync()) { aborted = true; break; }
-      {
+        const double v[1] = {pwu};
         double tot[1];
-        const int sl[1] = {0};
-        sum_partials<1>(prev_set(), G, sl, tot, s_red);
+        if (!sys_sync<1>(bar, v, tot, s_red, &s_flag)) { aborted = true; break; }
         eta = tot[0];
       }
       iters += 1;
@@ -364,7 +380,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       budget -= 1;
       const VT a = (VT)alpha, bt = (VT)beta;
       double pru = 0.0, prr = 0.0;
-      for (int i = r0 + t; i < r1; i += kWG) {
+      for (int i = r0 + t; i < r1; i += kSolveWG) {
         const VT pi = vu[i] + bt * vp[i];
         const VT si = vw[i] + bt * vs[i];
         vp[i] = pi;
@@ -377,38 +393,26 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
         pru += (double)ri * (double)ui;
         prr += (double)ri * (double)ri;
       }
-      {
-        double v[2] = {pru, prr};
-        wg_sum<2>(v, s_red);
-        if (t == 0) { *my_part(0) = v[0]; *my_part(1) = v[1]; }
-      }
-      if (!sync()) { aborted = true; break; }
       double gnew, rr;
       {
+        const double v[2] = {pru, prr};
         double tot[2];
-        const int sl[2] = {0, 1};
-        sum_partials<2>(prev_set(), G, sl, tot, s_red);
+        if (!sys_sync<2>(bar, v, tot, s_red, &s_flag)) { aborted = true; break; }
         gnew = tot[0];
         rr = tot[1];
       }
       inner += 1;
       if (!(sqrt(rr) > P.inner_rtol) || iters >= P.max_iter) { phase = PH_UPDATE; continue; }
       double pwu = 0.0;
-      band_matvec<MT, VT, VT>(V, ld, vu, r0, r1, s_mv, [&](int i, VT acc) {
+      wave_matvec<MT, VT, VT>(V, ld, vu, wr0, wr1, [&](int i, VT acc) {
         vw[i] = acc;
         pwu += (double)acc * (double)vu[i];
       });
-      {
-        double v[1] = {pwu};
-        wg_sum<1>(v, s_red);
-        if (t == 0) *my_part(0) = v[0];
-      }
-      if (!sync()) { aborted = true; break; }
       double delta;
       {
+        const double v[1] = {pwu};
         double tot[1];
-        const int sl[1] = {0};
-        sum_partials<1>(prev_set(), G, sl, tot, s_red);
+        if (!sys_sync<1>(bar, v, tot, s_red, &s_flag)) { aborted = true; break; }
         delta = tot[0];
       }
       iters += 1;
@@ -420,76 +424,79 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       continue;
     }
     if (phase == PH_UPDATE) {
-      for (int i = r0 + t; i < r1; i += kWG) x64[i] = __builtin_fma((double)vd[i], rnorm, x64[i]);
-      if (!sync()) { aborted = true; break; }
+      for (int i = r0 + t; i < r1; i += kSolveWG) x64[i] = __builtin_fma((double)vd[i], rnorm, x64[i]);
+      double dummy[1];
+      if (!sys_sync<1>(bar, none, dummy, s_red, &s_flag)) { aborted = true; break; }
       phase = PH_RESID;
       continue;
     }
     // PH_DONE: sigma = x, Cap = (1/4pi) sum x_i |T_i|
     double pc = 0.0;
-    for (int i = r0 + t; i < r1; i += kWG) {
-      S.sigma[i] = x64[i];
+    for (int i = r0 + t; i < r1; i += kSolveWG) {
+      sigma[i] = x64[i];
       pc = __builtin_fma(x64[i], b[i], pc);
     }
-    {
-      double v[1] = {pc};
-      wg_sum<1>(v, s_red);
-      if (t == 0) *my_part(0) = v[0];
-    }
-    if (!sync()) { aborted = true; break; }
     double cap;
     {
+      const double v[1] = {pc};
       double tot[1];
-      const int sl[1] = {0};
-      sum_partials<1>(prev_set(), G, sl, tot, s_red);
+      if (!sys_sync<1>(bar, v, tot, s_red, &s_flag)) { aborted = true; break; }
       cap = tot[0] * kInv4Pi;
     }
     if (rank == 0 && t == 0) {
-      S.result->cap = cap;
-      S.result->rel_residual = bnorm > 0.0 ? rnorm / bnorm : 0.0;
-      S.result->iters = iters;
-      S.result->outer = outer;
-      S.result->status = status;
-      S.result->precision = MIXED ? BC_MIXED : BC_FP64;
+      result->cap = cap;
+      result->rel_residual = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+      result->iters = iters;
+      result->outer = outer;
+      result->status = status;
+      result->precision = MIXED ? BC_MIXED : BC_FP64;
       ctl->phase = PH_DONE;
     }
     return;
   }
   if (rank == 0 && t == 0) {
     if (aborted) {
-      S.result->iters = iters;
-      S.result->outer = outer;
-      S.result->status = BC_ETIMEOUT;
-      S.result->precision = MIXED ? BC_MIXED : BC_FP64;
+      result->iters = iters;
+      result->outer = outer;
+      result->status = BC_ETIMEOUT;
+      result->precision = MIXED ? BC_MIXED : BC_FP64;
       ctl->phase = PH_DONE;
     } else {
-      ctl->phase = phase; ctl->iters = iters; ctl->outer = outer; ctl->inner = inner; ctl->epoch = epoch;
+      ctl->phase = phase; ctl->iters = iters; ctl->outer = outer; ctl->inner = inner; ctl->epoch = bar.epoch;
       ctl->bnorm = bnorm; ctl->rnorm = rnorm; ctl->scale = scale; ctl->gamma = gamma; ctl->eta = eta;
       ctl->alpha = alpha; ctl->beta = beta;
-      S.result->iters = iters;
-      S.result->outer = outer;
-      S.result->status = BC_RUNNING;
-      S.result->precision = MIXED ? BC_MIXED : BC_FP64;
+      result->iters = iters;
+      result->outer = outer;
+      result->status = BC_RUNNING;
+      result->precision = MIXED ? BC_MIXED : BC_FP64;
     }
   }
 }
 
-// Reset the control block of systems that (re)start.
-__global__ void k_solve_init(const SysDesc *__restrict__ descs, int n_sys) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+// Reset the control block, barrier slots and release records of systems
+// that (re)start: one workgroup per system.
+__global__ __launch_bounds__(256) void k_solve_init(const SysDesc *__restrict__ descs, int n_sys) {
+  const int s = blockIdx.x;
   if (s >= n_sys) return;
   const SysDesc &S = descs[s];
   if (!S.start) return;
-  size_t o_ctl, o_part, o_x, o_r, o_vec;
+  size_t o_ctl, o_slots, o_rel, o_x, o_r, o_vec, o_total;
   int64_t ld;
-  solve_offsets(S.N, BC_FP64, o_ctl, o_part, o_x, o_r, o_vec, ld);
-  SolveCtl *ctl = reinterpret_cast<SolveCtl *>(S.ws + o_ctl);
-  ctl->bar_count = 0u;
-  ctl->bar_gen = 0u;
-  ctl->abort = 0;
-  ctl->phase = PH_INIT;
-  ctl->epoch = 0u;
-  S.result->status = BC_RUNNING;
+  solve_offsets(S.N, BC_FP64, o_ctl, o_slots, o_rel, o_x, o_r, o_vec, o_total, ld);
+  const int t = threadIdx.x;
+  BarSlot *slots = reinterpret_cast<BarSlot *>(S.ws + o_slots);
+  BarRel *rel = reinterpret_cast<BarRel *>(S.ws + o_rel);
+  if (t < kGMax) slots[t].tag = 0u;
+  if (t < kNRep) {
+    rel[t].gen = 0u;
+    rel[t].abort = 0;
+  }
+  if (t == 0) {
+    SolveCtl *ctl = reinterpret_cast<SolveCtl *>(S.ws + o_ctl);
+    ctl->phase = PH_INIT;
+    ctl->epoch = 0u;
+    S.result->status = BC_RUNNING;
+  }
 }
 
 struct DescBatch {
@@ -515,8 +522,9 @@ int launch_set_desc(const SysDesc *h, int n, SysDesc *d, hipStream_t s) {
   return BC_OK;
 }
 
+// About 80 rows (5 per wavefront) per workgroup, at most kGMax workgroups.
 int solve_workgroups(int64_t N) {
-  int64_t g = (N + 31) / 32;
+  int64_t g = (N + 79) / 80;
   if (g < 1) g = 1;
   if (g > kGMax) g = kGMax;
   return (int)g;
@@ -527,21 +535,23 @@ int solve_capacity(int32_t precision) {
   if (hipGetDevice(&dev) != hipSuccess) return -1;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
   hipError_t e = precision == BC_FP64
-                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<double>, kWG, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<float>, kWG, 0);
+                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<double>, kSolveWG, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<float>, kSolveWG, 0);
   if (e != hipSuccess) return -1;
   return nb * cus;
 }
 
 int launch_solve(int32_t precision, const SysDesc *d_desc, int n_sys, int total_wg, const SolveParams &p,
                  hipStream_t s) {
-  hipLaunchKernelGGL(k_solve_init, dim3((n_sys + 63) / 64), dim3(64), 0, s, d_desc, n_sys);
+  hipLaunchKernelGGL(k_solve_init, dim3(n_sys), dim3(256), 0, s, d_desc, n_sys);
   if (hipGetLastError() != hipSuccess) return BC_EDEVICE;
   SolveParams pp = p;
   void *args[] = {(void *)&d_desc, (void *)&pp};
   hipError_t e = precision == BC_FP64
-                     ? hipLaunchCooperativeKernel((const void *)k_solve<double>, dim3(total_wg), dim3(kWG), args, 0, s)
-                     : hipLaunchCooperativeKernel((const void *)k_solve<float>, dim3(total_wg), dim3(kWG), args, 0, s);
+                     ? hipLaunchCooperativeKernel((const void *)k_solve<double>, dim3(total_wg), dim3(kSolveWG), args,
+                                                  0, s)
+                     : hipLaunchCooperativeKernel((const void *)k_solve<float>, dim3(total_wg), dim3(kSolveWG), args,
+                                                  0, s);
   return e == hipSuccess ? BC_OK : BC_EDEVICE;
 }
 
@@ -549,10 +559,12 @@ int launch_solve(int32_t precision, const SysDesc *d_desc, int n_sys, int total_
 __global__ __launch_bounds__(kWG) void k_capacity(const double *__restrict__ sigma, const double *__restrict__ area,
                                                   int N, double *cap) {
   __shared__ double lds[4];
-  double v[1] = {0.0};
-  for (int i = threadIdx.x; i < N; i += kWG) v[0] = __builtin_fma(sigma[i], area[i], v[0]);
-  wg_sum<1>(v, lds);
-  if (threadIdx.x == 0) *cap = v[0] * kInv4Pi;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < N; i += kWG) v = __builtin_fma(sigma[i], area[i], v);
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) *cap = (((lds[0] + lds[1]) + lds[2]) + lds[3]) * kInv4Pi;
 }
 
 int launch_capacity(const double *sigma, const double *area, int64_t N, double *cap, hipStream_t s) {

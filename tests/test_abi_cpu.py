@@ -54,8 +54,8 @@ def test_sizes(L):
     assert L.bc_mesh_workspace_bytes(1000) > 1000 * (16 + 32 + 8 + 4 * 16 * (8 + 8 + 4 + 4))
     assert L.bc_pattern_bytes(100, 1000, 1) > L.bc_pattern_bytes(100, 1000, 0)
     assert L.bc_solve_workspace_bytes(1000, 0) > L.bc_solve_workspace_bytes(1000, 1)
-    assert L.bc_solve_workgroups(1) == 1 and L.bc_solve_workgroups(33) == 2
-    assert L.bc_solve_workgroups(10 ** 6) == 1024
+    assert L.bc_solve_workgroups(1) == 1 and L.bc_solve_workgroups(80) == 1 and L.bc_solve_workgroups(81) == 2
+    assert L.bc_solve_workgroups(10 ** 6) == 256
     assert L.bc_batch_scratch_bytes(3) >= 3 * 96
 
 
