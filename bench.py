@@ -140,6 +140,126 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
+def _build_request_mesh(req):
+    return req.build_mesh()
+
+
+def serve_mode(a):
+    """Serving workload: 512 seeded requests (voxel unions, convex hulls,
+    boxes; N log-uniform in [500, 30000]).  Saturated run (all at t = 0) for
+    the closed-loop rate, then Poisson arrivals at 0.8 x that rate, for the
+    mixed and the FP64 GPU forms."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    import synth
+
+    reqs = synth.request_stream(a.requests, seed=5, rate=float("inf"))
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(min(os.cpu_count() or 1, 16), mp_context=mp.get_context("fork")) as ex:
+        meshes = list(ex.map(_build_request_mesh, reqs, chunksize=4))
+    log(f"built {len(meshes)} request meshes in {time.perf_counter() - t0:.1f} s "
+        f"(N {min(m.N for m in meshes)}..{max(m.N for m in meshes)})")
+    import torch
+
+    from paper_1901_08393_amd.serve import CapacityServer, summarize
+
+    torch.cuda.set_device(0)
+    out = {"mode": "serve", "requests": len(reqs), "seed": 5}
+    caps = {}
+    for prec in ("mixed", "fp64"):
+        srv = CapacityServer(prec)
+        srv.run(reqs[:8], meshes[:8], realtime=False)  # warm-up
+        recs = srv.run(reqs, meshes, realtime=False)
+        sat = summarize(recs)
+        rate = 0.8 * sat["solves_per_s"]
+        preqs = synth.request_stream(a.requests, seed=5, rate=rate)
+        precs = srv.run(preqs, meshes, realtime=True)
+        poi = summarize(precs)
+        caps[prec] = np.array([r.cap for r in precs])
+        out[prec] = {"saturated": sat, "poisson": dict(poi, rate=rate)}
+        log(f"{prec}: saturated {sat['solves_per_s']:.1f} solves/s; poisson p50 {poi['p50_ms']:.1f} ms "
+            f"p99 {poi['p99_ms']:.1f} ms")
+        del srv
+        torch.cuda.empty_cache()
+    rel = np.abs(caps["mixed"] - caps["fp64"]) / caps["fp64"]
+    out["cap_rel_err_mixed_vs_fp64"] = {"max": float(rel.max()), "median": float(np.median(rel))}
+    print(json.dumps(out))
+
+
+def adaptive_mode(a):
+    """Adaptive workload: seeded voxel union (26 of 64 unit voxels),
+    uniform NVB refinement to about 2k triangles, then 5 steps of solve,
+    ZZ, Doerfler (theta = 0.5) and NVB (FP64 path)."""
+    import torch
+
+    import synth
+    from paper_1901_08393_amd.adaptive import adaptive_capacity
+
+    torch.cuda.set_device(0)
+    m = synth.voxel_union(4, 0.4, 3)
+    t0 = synth.init_reference_edges(m.verts, m.tris)
+    v, t = m.verts, t0
+    while len(t) * 4 <= 2600:
+        v, t, _ = synth.refine_uniform(v, t, 1)
+    prec = "fp64" if a.precision == "mixed" and not a.adaptive_mixed else a.precision
+    steps = adaptive_capacity(v, t, steps=5, theta=0.5, precision=prec)
+    rows = [dict(level=s.level, N=s.N, cap=s.cap, eta2=s.eta2, iters=s.iters, outer=s.outer, marked=s.n_marked,
+                 assemble_ms=round(s.t_assemble_ms, 3), solve_ms=round(s.t_solve_ms, 3), zz_ms=round(s.t_zz_ms, 3),
+                 refine_ms=round(s.t_refine_ms, 2)) for s in steps]
+    caps = [s.cap for s in steps]
+    print(json.dumps({"mode": "adaptive", "precision": prec, "voxels": m.meta["voxels"], "steps": rows,
+                      "monotone": all(caps[k] < caps[k + 1] for k in range(len(caps) - 1))}))
+
+
+def mixed60k_mode(a):
+    """Mixed precision at N >= 60000: a seeded voxel union adapted (ZZ +
+    Doerfler + NVB, FP64 path) until N >= 60000; then the FP64 GPU solve as
+    reference and mixed solves at several residual tolerances."""
+    import torch
+
+    import synth
+    from paper_1901_08393_amd import api
+    from paper_1901_08393_amd.adaptive import adaptive_capacity, doerfler
+
+    torch.cuda.set_device(0)
+    m = synth.voxel_union(4, 0.4, 4)
+    v, t = m.verts, synth.init_reference_edges(m.verts, m.tris)
+    while len(t) * 4 <= 2600:
+        v, t, _ = synth.refine_uniform(v, t, 1)
+    while len(t) < a.target_n:
+        steps = adaptive_capacity(v, t, steps=0, precision="mixed", keep=True)
+        mk = doerfler(steps[0].eta2_elem, 0.5)
+        v, t, _ = synth.refine_nvb(v, t, mk, "bisec3")
+        log(f"mesh N={len(t)}")
+    N = len(t)
+    p64 = api.CapacityProblem(v, t, "fp64")
+    p64.assemble()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    r64 = p64.solve()
+    e1.record()
+    torch.cuda.synchronize()
+    ref = {"cap": r64.cap, "iters": r64.iters, "solve_ms": e0.elapsed_time(e1),
+           "matrix_gb": p64.matrix_bytes() / 1e9}
+    p64.release_matrix()
+    del p64
+    torch.cuda.empty_cache()
+    p32 = api.CapacityProblem(v, t, "mixed")
+    p32.assemble()
+    rows = []
+    for rtol in (1e-5, 1e-7, 1e-9, 1e-10):
+        e0.record()
+        r = p32.solve(rtol=rtol)
+        e1.record()
+        torch.cuda.synchronize()
+        rows.append({"rtol": rtol, "cap": r.cap, "rel_err_vs_fp64": abs(r.cap - r64.cap) / r64.cap,
+                     "iters": r.iters, "outer": r.outer, "solve_ms": e0.elapsed_time(e1)})
+    print(json.dumps({"mode": "mixed60k", "N": N, "fp64": ref, "mixed": rows,
+                      "matrix_gb_fp32": p32.matrix_bytes() / 1e9}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,11 +269,23 @@ def main():
     ap.add_argument("--level", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="serving workload instead of the sphere")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--adaptive", action="store_true", help="adaptive voxel-union workload (FP64 path)")
+    ap.add_argument("--adaptive-mixed", action="store_true", help="run the adaptive workload in mixed precision")
+    ap.add_argument("--mixed60k", action="store_true", help="mixed vs FP64 at N >= 60000")
+    ap.add_argument("--target-n", type=int, default=60000)
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU design is "
                                    "described in DESIGN.md, not implemented)"}))
         sys.exit(2)
+    if a.serve:
+        return serve_mode(a)
+    if a.adaptive:
+        return adaptive_mode(a)
+    if a.mixed60k:
+        return mixed60k_mode(a)
 
     import torch
 

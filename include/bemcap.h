@@ -220,6 +220,9 @@ typedef struct bc_system {
   int64_t nnz;
   int32_t precision;
   int32_t start;        /* 1: (re)initialise this system's state; 0: resume */
+  int32_t iter_budget;  /* > 0: this system's bound on matrix products in
+                           this launch (overrides the call's iter_budget) */
+  int32_t reserved;     /* must be 0 */
 } bc_system;
 
 /* Bytes of device scratch for the descriptors of a batch of n_sys systems. */
@@ -227,10 +230,11 @@ size_t bc_batch_scratch_bytes(int32_t n_sys);
 
 /* Batched persistent solve: every system gets bc_solve_workgroups(N)
  * workgroups of one cooperative launch and runs the same state machine as
- * bc_solve.  iter_budget > 0 bounds the matrix products each system may do
- * in this launch (continuous batching: unfinished systems report
- * BC_RUNNING and resume, bitwise identically, in a later call with
- * start = 0); iter_budget <= 0 runs every system to completion.  All
+ * bc_solve.  iter_budget > 0 (or a system's own iter_budget > 0) bounds the
+ * matrix products a system may do in this launch (continuous batching:
+ * unfinished systems report BC_RUNNING and resume, bitwise identically, in
+ * a later call with start = 0); iter_budget <= 0 runs every system without
+ * a bound of its own to completion.  All
  * systems must share one precision.  The total workgroup count must not
  * exceed bc_solve_capacity().  h_sys is copied to d_scratch.  ASYNC. */
 int32_t bc_solve_batched(int32_t n_sys, const bc_system *h_sys,

@@ -50,7 +50,8 @@ class bc_result(C.Structure):
 class bc_system(C.Structure):
     _fields_ = [("V", C.c_void_p), ("pattern", C.c_void_p), ("area", C.c_void_p), ("sigma", C.c_void_p),
                 ("ws", C.c_void_p), ("result", C.c_void_p), ("N", C.c_int64), ("nnz", C.c_int64),
-                ("precision", C.c_int32), ("start", C.c_int32)]
+                ("precision", C.c_int32), ("start", C.c_int32), ("iter_budget", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 P = C.c_void_p

@@ -1,0 +1,98 @@
+"""Adaptive loop solve -> estimate -> mark -> refine (Algorithm 1, steps
+(i)-(iv)) on the primal P0 discretisation.
+
+(i)   solve: dense assembly and persistent Krylov solve on the GPU, warm
+      started from the previous mesh's solution (the P0 spaces of NVB meshes
+      are nested, so every son inherits its parent's value);
+(ii)  estimate: ZZ-type indicators eta(T)^2 on the GPU (eq. "zz:T");
+(iii) mark: Doerfler marking (eq. "doerfler") on the host;
+(iv)  refine: newest-vertex bisection of the marked elements with closure.
+
+By the corollary in Appendix A the discrete capacities of nested P0 spaces
+increase monotonically; the driver reports them per step.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+import synth
+
+from .api import CapacityProblem
+
+
+def doerfler(eta2: np.ndarray, theta: float) -> np.ndarray:
+    """Smallest set M with theta * sum eta^2 <= sum_{M} eta^2, chosen greedily
+    by decreasing eta^2 with ties to the lower index (eq. "doerfler" with
+    C_mark = 1).  Returns sorted element indices."""
+    eta2 = np.asarray(eta2, dtype=np.float64)
+    if eta2.size == 0:
+        return np.zeros(0, dtype=np.int64)
+    order = np.lexsort((np.arange(eta2.size), -eta2))
+    total = math.fsum(eta2.tolist())  # exactly rounded total
+    cum = np.cumsum(eta2[order])  # sequential, in marking order
+    k = int(np.searchsorted(cum, theta * total, side="left")) + 1
+    return np.sort(order[: min(k, eta2.size)])
+
+
+@dataclasses.dataclass
+class Step:
+    level: int
+    N: int
+    cap: float
+    eta2: float
+    iters: int
+    outer: int
+    n_marked: int
+    t_assemble_ms: float
+    t_solve_ms: float
+    t_zz_ms: float
+    t_refine_ms: float
+    verts: Optional[np.ndarray] = None
+    tris: Optional[np.ndarray] = None
+    sigma: Optional[np.ndarray] = None
+    eta2_elem: Optional[np.ndarray] = None
+
+
+def adaptive_capacity(verts, tris, steps: int = 5, theta: float = 0.5, precision: str = "fp64",
+                      h_mode: int = 0, warm_start: bool = True, keep: bool = False, **solve_opts) -> List[Step]:
+    """Run `steps` refinements (steps + 1 solves).  `tris` must be in NVB form
+    (reference edge first); use synth.init_reference_edges on a new mesh."""
+    verts = np.asarray(verts, dtype=np.float64)
+    tris = np.asarray(tris, dtype=np.int32)
+    x0 = None
+    out: List[Step] = []
+    for level in range(steps + 1):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        prob = CapacityProblem(verts, tris, precision)
+        ev[0].record()
+        prob.assemble()
+        ev[1].record()
+        res = prob.solve(x0=x0 if warm_start else None, sync=False, **solve_opts)
+        ev[2].record()
+        eta2_d = prob.zz(h_mode=h_mode)
+        ev[3].record()
+        res = prob.result()
+        if not res.ok:
+            raise RuntimeError(f"solve failed at level {level}: {res}")
+        eta2 = eta2_d.cpu().numpy()
+        sigma = prob.sigma.cpu().numpy()
+        t0 = time.perf_counter()
+        marked = doerfler(eta2, theta) if level < steps else np.zeros(0, dtype=np.int64)
+        step = Step(level, int(tris.shape[0]), res.cap, float(eta2.sum()), res.iters, res.outer, int(marked.size),
+                    ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3]), 0.0)
+        if keep:
+            step.verts, step.tris, step.sigma, step.eta2_elem = verts, tris, sigma, eta2
+        if level < steps:
+            verts, tris, parent = synth.refine_nvb(verts, tris, marked, "bisec3")
+            x0 = torch.from_numpy(sigma[parent]).to(prob.device)
+        step.t_refine_ms = (time.perf_counter() - t0) * 1e3
+        out.append(step)
+        del prob
+    return out

@@ -209,9 +209,11 @@ class CapacityProblem:
         self.solve_ws = None
 
 
-def solve_batched(problems, precision: str, iter_budget: int = 0, start=None, stream=None, **opts):
+def solve_batched(problems, precision: str, iter_budget: int = 0, start=None, budgets=None, stream=None,
+                  **opts):
     """One persistent launch over several assembled problems (same precision).
-    start[k] = 1 (re)initialises problem k, 0 resumes it.  Asynchronous: read
+    start[k] = 1 (re)initialises problem k, 0 resumes it; budgets[k] > 0
+    bounds problem k's matrix products in this launch.  Asynchronous: read
     each problem's result with problem.result() after the stream syncs."""
     L = lib()
     n = len(problems)
@@ -220,7 +222,7 @@ def solve_batched(problems, precision: str, iter_budget: int = 0, start=None, st
         p._ensure_solve_ws()
         arr[k] = _lib.bc_system(p.V.data_ptr(), p.pattern.data_ptr(), p.area.data_ptr(), p.sigma.data_ptr(),
                                 p.solve_ws.data_ptr(), p.result_buf.data_ptr(), p.N, p.nnz, PRECISION[precision],
-                                1 if start is None else int(start[k]))
+                                1 if start is None else int(start[k]), 0 if budgets is None else int(budgets[k]), 0)
     o = default_solve_opts(precision, **opts)
     nb = L.bc_batch_scratch_bytes(n)
     scratch = torch.empty(nb, dtype=torch.uint8, device=problems[0].device)

@@ -239,6 +239,7 @@ static int fill_desc(const bc_system &s, int wg_begin, SysDesc &d) {
   if (!s.V || !s.area || !s.sigma || !s.ws || !s.result || !n_ok(s.N) || s.nnz < 0) return BC_EINVAL;
   if (s.precision != BC_FP64 && s.precision != BC_MIXED) return BC_EINVAL;
   if (s.precision == BC_MIXED && s.nnz > 0 && !s.pattern) return BC_EINVAL;
+  if (s.reserved != 0 || s.iter_budget < 0) return BC_EINVAL;
   std::memset(&d, 0, sizeof(d));
   d.V = s.V;
   if (s.pattern && s.nnz > 0) {
@@ -258,6 +259,7 @@ static int fill_desc(const bc_system &s, int wg_begin, SysDesc &d) {
   d.wg_begin = wg_begin;
   d.wg_count = solve_workgroups(s.N);
   d.start = s.start;
+  d.budget = s.iter_budget;
   return BC_OK;
 }
 
@@ -271,7 +273,7 @@ int32_t bc_solve(const void *d_V, int64_t N, int32_t precision, const void *d_pa
   // the descriptor lives after the control block, inside the workspace
   const size_t desc_off = sizeof(SolveCtl);
   if (ws_bytes < L.total) return BC_ENOMEM;
-  bc_system sys{d_V, d_pattern, d_area, d_sigma, d_ws, d_result, N, nnz, precision, 1};
+  bc_system sys{d_V, d_pattern, d_area, d_sigma, d_ws, d_result, N, nnz, precision, 1, 0, 0};
   SysDesc d;
   int st = fill_desc(sys, 0, d);
   if (st != BC_OK) return st;

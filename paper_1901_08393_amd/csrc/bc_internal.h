@@ -160,7 +160,7 @@ struct SysDesc {
   int32_t wg_begin;
   int32_t wg_count;
   int32_t start;
-  int32_t pad;
+  int32_t budget;  // > 0: this system's product bound in this launch
 };
 
 struct SolveParams {

@@ -296,7 +296,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
   }
   if (phase == PH_DONE) return;
   int32_t status = BC_OK;
-  int budget = P.iter_budget > 0 ? P.iter_budget : INT_MAX;
+  int budget = S.budget > 0 ? S.budget : (P.iter_budget > 0 ? P.iter_budget : INT_MAX);
   bool aborted = false;
   const double none[1] = {0.0};
 

@@ -16,6 +16,7 @@ from .meshes import (  # noqa: F401
     cube,
     icosphere,
     mesh_topology_ok,
+    min_angle_deg,
     voxel_union,
 )
 from .nvb import (  # noqa: F401

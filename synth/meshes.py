@@ -236,14 +236,37 @@ def icosphere(level: int, r: float = 1.0, name: str | None = None) -> Mesh:
 # Convex hull of random points
 # ----------------------------------------------------------------------------
 
-def convex_hull(npts: int, seed: int, name: str | None = None) -> Mesh:
+def min_angle_deg(verts, tris) -> float:
+    """Smallest interior angle over all triangles, in degrees."""
+    P = np.asarray(verts, dtype=np.float64)[np.asarray(tris)]
+    out = []
+    for k in range(3):
+        a = P[:, (k + 1) % 3] - P[:, k]
+        b = P[:, (k + 2) % 3] - P[:, k]
+        c = np.einsum("ij,ij->i", a, b) / np.linalg.norm(a, axis=1) / np.linalg.norm(b, axis=1)
+        out.append(np.degrees(np.arccos(np.clip(c, -1.0, 1.0))))
+    return float(np.min(out))
+
+
+def convex_hull(npts: int, seed: int, name: str | None = None, min_angle: float = 10.0) -> Mesh:
     """Convex hull of `npts` uniform random points in [-1, 1]^3; hull facets
-    as triangles, outward oriented, unused (interior) points dropped."""
+    as triangles, outward oriented, unused (interior) points dropped.
+
+    Draws whose hull has a facet with an interior angle below `min_angle`
+    degrees are discarded and the same generator draws again: the method
+    assumes shape-regular triangulations (the constants of Appendix A depend
+    on gamma-shape regularity), and newest-vertex bisection keeps the initial
+    shapes, so a sliver facet would stay a sliver at every refinement."""
     from scipy.spatial import ConvexHull
 
     rng = np.random.default_rng(seed)
-    pts = rng.uniform(-1.0, 1.0, size=(npts, 3))
-    hull = ConvexHull(pts)
+    for attempt in range(10000):
+        pts = rng.uniform(-1.0, 1.0, size=(npts, 3))
+        hull = ConvexHull(pts)
+        if min_angle <= 0.0 or min_angle_deg(pts, hull.simplices) >= min_angle:
+            break
+    else:
+        raise RuntimeError("convex_hull: no draw met the angle bound")
     T = np.array(hull.simplices, dtype=np.int64)
     used = np.unique(T)
     remap = -np.ones(npts, dtype=np.int64)
@@ -255,7 +278,8 @@ def convex_hull(npts: int, seed: int, name: str | None = None) -> Mesh:
     nrm = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
     flip = np.einsum("ij,ij->i", nrm, P.mean(axis=1) - center) < 0
     T[flip] = T[flip][:, [0, 2, 1]]
-    return _finish(V, T, name or f"hull{npts}_s{seed}", {"npts": npts, "seed": seed})
+    return _finish(V, T, name or f"hull{npts}_s{seed}",
+                   {"npts": npts, "seed": seed, "attempt": attempt, "min_angle": min_angle})
 
 
 # ----------------------------------------------------------------------------
