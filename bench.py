@@ -136,6 +136,29 @@ def cpu_baseline(mesh, seconds_target: float = 15.0):
     }
 
 
+def solver_traffic(products: int):
+    """HBM bytes of one k_solve<float> launch from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE runs, scaled by a 1 GiB copy), or None
+    if the solver sources changed since the counters were taken or the launch
+    does a different number of products."""
+    import hashlib
+    import re
+
+    path = os.path.join(ROOT, "profiles", "sphere_L5_mixed_hbm_counters.md")
+    try:
+        m = re.search(r"```json\n(.*?)\n```", open(path).read(), flags=re.S)
+        data = json.loads(m.group(1))
+    except Exception:
+        return None
+    h = hashlib.sha256()
+    for f in ("paper_1901_08393_amd/csrc/solve.hip", "paper_1901_08393_amd/csrc/bc_internal.h"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    rec = data.get("k_solve_float", {})
+    if data.get("source_sha") != h.hexdigest()[:16] or rec.get("products") != products:
+        return None
+    return rec.get("hbm_bytes")
+
+
 def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
@@ -275,6 +298,7 @@ def main():
     ap.add_argument("--adaptive-mixed", action="store_true", help="run the adaptive workload in mixed precision")
     ap.add_argument("--mixed60k", action="store_true", help="mixed vs FP64 at N >= 60000")
     ap.add_argument("--target-n", type=int, default=60000)
+    ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy first (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU design is "
@@ -292,6 +316,14 @@ def main():
     from paper_1901_08393_amd import api
 
     torch.cuda.set_device(0)
+    if a.calib_copy:
+        # a plain copy of known size: 1 GiB read + 1 GiB written, used to
+        # scale hardware byte counters of the other kernels in the same run
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     mesh, radius = workload_mesh(a.level)
     N = mesh.N
     log(f"workload: icosphere L{a.level} N={N} r={radius:.6f} precision={a.precision}")
@@ -320,8 +352,9 @@ def main():
     asm_tflops = pairs * POINT_PAIRS_PER_PAIR * FLOPS_PER_POINT_PAIR / (mean("assemble_ms") * 1e-3) / 1e12
     asm_peak = FP32_VECTOR_PEAK if a.precision == "mixed" else FP64_VECTOR_PEAK
 
+    traffic = solver_traffic(streams) if a.precision == "mixed" and N == 20480 else None
     roof_solve = {"bound": "hbm", "achieved": round(solve_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(solve_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                  "frac": round(solve_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                   "kernel": f"k_solve<{'float' if elem == 4 else 'double'}>",
                   "per_launch_bytes": solve_bytes, "products_per_launch": streams,
                   "avg_launch_ms": round(mean("solve_ms"), 4)}
