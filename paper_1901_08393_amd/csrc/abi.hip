@@ -161,7 +161,7 @@ int32_t bc_prepare(const double *d_verts, int64_t M, const int32_t *d_tris, int6
   hipStream_t s = static_cast<hipStream_t>(stream);
   int st = launch_geometry(d_verts, M, d_tris, N, opts->far_order, d_mesh_ws, s);
   if (st != BC_OK) return st;
-  st = launch_pattern(d_tris, N, opts->near_factor, d_mesh_ws, nullptr, 0, opts->precision, false, s);
+  st = launch_pattern(d_verts, d_tris, N, opts->near_factor, d_mesh_ws, nullptr, 0, opts->precision, false, s);
   if (st != BC_OK) return st;
   int64_t info[8] = {0};
   if (hipMemcpyAsync(info, static_cast<char *>(d_mesh_ws) + L.info, sizeof(info), hipMemcpyDeviceToHost, s) !=
@@ -186,7 +186,7 @@ int32_t bc_assemble(const double *d_verts, int64_t M, const int32_t *d_tris, int
   if (mesh_ws_bytes < MeshLayout(N).total) return BC_ENOMEM;
   if (pattern_bytes < PatternLayout(N, nnz, opts->precision).total) return BC_ENOMEM;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  int st = launch_pattern(d_tris, N, opts->near_factor, d_mesh_ws, d_pattern, nnz, opts->precision, true, s);
+  int st = launch_pattern(d_verts, d_tris, N, opts->near_factor, d_mesh_ws, d_pattern, nnz, opts->precision, true, s);
   if (st != BC_OK) return st;
   return launch_assemble(d_mesh_ws, d_tris, d_verts, N, *opts, d_pattern, nnz, d_V, s);
 }

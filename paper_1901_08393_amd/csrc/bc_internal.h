@@ -25,7 +25,7 @@ inline int64_t ld_of(int64_t N) { return (N + 63) / 64 * 64; }
 // ---------------------------------------------------------------- mesh ws
 // Offsets of the tables inside the mesh workspace (all 256-byte aligned).
 struct MeshLayout {
-  size_t tri4, cen4, area, qpA64, qpS64, qpA32, qpS32, rowcnt, rowptr, kindcnt, info, total;
+  size_t tri4, cen4, area, qpA64, qpS64, qpA32, qpS32, rowcnt, rowptr, kindcnt, info, blockbox, total;
   explicit MeshLayout(int64_t N) {
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
@@ -40,6 +40,7 @@ struct MeshLayout {
     rowptr = take(sizeof(int32_t) * (N + 1));
     kindcnt = take(sizeof(int32_t) * 4 * N);
     info = take(sizeof(int64_t) * 8);
+    blockbox = take(sizeof(double) * 8 * ((N + 63) / 64));  // per 64 elements: min xyz, max xyz, max diam^2
     total = o;
   }
 };
@@ -141,7 +142,7 @@ struct SolveCtl {
   int32_t status;
   uint32_t epoch;
   int32_t pad;
-  double bnorm, rnorm, scale, gamma, eta, alpha, beta;
+  double bnorm, rnorm, scale, gamma, eta, alpha, beta, itol;
 };
 
 // Solver descriptor built by the host for each system of a launch.
@@ -219,7 +220,7 @@ __device__ __forceinline__ T wave_sum(T v) {
 namespace bc {
 int launch_geometry(const double *verts, int64_t M, const int32_t *tris, int64_t N,
                     int far_order, void *mesh_ws, hipStream_t s);
-int launch_pattern(const int32_t *tris, int64_t N, double near_factor, const void *mesh_ws,
+int launch_pattern(const double *verts, const int32_t *tris, int64_t N, double near_factor, const void *mesh_ws,
                    void *pattern, int64_t nnz, int32_t precision, bool emit, hipStream_t s);
 int launch_assemble(const void *mesh_ws, const int32_t *tris, const double *verts, int64_t N,
                     const bc_assembly_opts &o, void *pattern, int64_t nnz, void *V, hipStream_t s);

@@ -99,14 +99,57 @@ __device__ __forceinline__ int pair_class(int4 ti, double4 ci, int4 tj, double4 
   return -1;
 }
 
+// Axis-aligned box of the vertices of each block of 64 consecutive elements
+// and the largest squared diameter in the block: one wavefront per block.
+__global__ __launch_bounds__(64) void k_blockbox(const double *__restrict__ verts, const int4 *__restrict__ tri4,
+                                                 const double4 *__restrict__ cen4, int N, double *box) {
+  const int B = blockIdx.x, lane = threadIdx.x;
+  const int e = min(B * 64 + lane, N - 1);
+  const int4 t = tri4[e];
+  double lo[3], hi[3];
+  for (int c = 0; c < 3; ++c) {
+    const double a = verts[3 * t.x + c], b = verts[3 * t.y + c], d = verts[3 * t.z + c];
+    lo[c] = fmin(fmin(a, b), d);
+    hi[c] = fmax(fmax(a, b), d);
+  }
+  double d2 = cen4[e].w;
+  for (int off = 32; off >= 1; off >>= 1) {
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = fmin(lo[c], __shfl_xor(lo[c], off, 64));
+      hi[c] = fmax(hi[c], __shfl_xor(hi[c], off, 64));
+    }
+    d2 = fmax(d2, __shfl_xor(d2, off, 64));
+  }
+  if (lane == 0) {
+    double *o = box + 8 * B;
+    o[0] = lo[0]; o[1] = lo[1]; o[2] = lo[2];
+    o[3] = hi[0]; o[4] = hi[1]; o[5] = hi[2];
+    o[6] = d2; o[7] = 0.0;
+  }
+}
+
+// Squared distance between two boxes (0 if they touch or overlap).
+__device__ __forceinline__ double box_dist2(const double *a, const double *b) {
+  double s = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const double g = fmax(0.0, fmax(a[c] - b[3 + c], b[c] - a[3 + c]));
+    s += g * g;
+  }
+  return s;
+}
+
 // One workgroup per block of 64 rows (16 rows per wave); lanes sweep the
 // columns 64 at a time.  Row data are staged in LDS (broadcast reads).
 // COUNT: rowcnt[i] = |pattern row i|, kindcnt[i][k] = pairs (i, j >= i) of
 // class k.  EMIT: write (col, row, kind) at rowptr[i] in column order.
+// Column blocks whose vertex box is farther from the row block's box than
+// nf * (largest diameter in either block) can hold neither a touching pair
+// (touching triangles share a point) nor a near pair (centroids lie in the
+// boxes), so they are skipped without looking at their elements.
 template <bool EMIT>
 __global__ __launch_bounds__(kWG) void k_pattern(const int4 *__restrict__ tri4, const double4 *__restrict__ cen4,
-                                                 int N, double nf2, int32_t *rowcnt, int32_t *kindcnt,
-                                                 const int32_t *__restrict__ rowptr, int32_t *pcol,
+                                                 const double *__restrict__ bbox, int N, double nf2, int32_t *rowcnt,
+                                                 int32_t *kindcnt, const int32_t *__restrict__ rowptr, int32_t *pcol,
                                                  int32_t *prow, int32_t *pkind) {
   __shared__ int4 s_tri[64];
   __shared__ double4 s_cen[64];
@@ -128,7 +171,13 @@ __global__ __launch_bounds__(kWG) void k_pattern(const int4 *__restrict__ tri4, 
     int i = I0 + w * 16 + k;
     base[k] = (EMIT && i < N) ? rowptr[i] : 0;
   }
+  const double *rb = bbox + 8 * blockIdx.x;
   for (int J0 = 0; J0 < N; J0 += 64) {
+    {
+      const double *cb = bbox + 8 * (J0 / 64);
+      const double thr = nf2 * fmax(rb[6], cb[6]);
+      if (box_dist2(rb, cb) > thr * (1.0 + 1e-9)) continue;  // uniform over the workgroup
+    }
     const int j = J0 + lane;
     const bool jv = j < N;
     int4 tj = tri4[jv ? j : N - 1];
@@ -244,8 +293,8 @@ int launch_geometry(const double *verts, int64_t M, const int32_t *tris, int64_t
   return hipGetLastError() == hipSuccess ? BC_OK : BC_EDEVICE;
 }
 
-int launch_pattern(const int32_t *tris, int64_t N, double near_factor, const void *mesh_ws, void *pattern,
-                   int64_t nnz, int32_t precision, bool emit, hipStream_t s) {
+int launch_pattern(const double *verts, const int32_t *tris, int64_t N, double near_factor, const void *mesh_ws,
+                   void *pattern, int64_t nnz, int32_t precision, bool emit, hipStream_t s) {
   (void)tris;
   MeshLayout L(N);
   char *base = static_cast<char *>(const_cast<void *>(mesh_ws));
@@ -256,8 +305,11 @@ int launch_pattern(const int32_t *tris, int64_t N, double near_factor, const voi
   int32_t *rowptr = reinterpret_cast<int32_t *>(base + L.rowptr);
   double nf2 = near_factor * near_factor;
   int grid = (int)((N + 63) / 64);
+  const double *bbox = reinterpret_cast<const double *>(base + L.blockbox);
   if (!emit) {
-    hipLaunchKernelGGL(k_pattern<false>, dim3(grid), dim3(kWG), 0, s, tri4, cen4, (int)N, nf2, rowcnt, kindcnt,
+    hipLaunchKernelGGL(k_blockbox, dim3(grid), dim3(64), 0, s, verts, tri4, cen4, (int)N, const_cast<double *>(bbox));
+    if (hipGetLastError() != hipSuccess) return BC_EDEVICE;
+    hipLaunchKernelGGL(k_pattern<false>, dim3(grid), dim3(kWG), 0, s, tri4, cen4, bbox, (int)N, nf2, rowcnt, kindcnt,
                        (const int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr);
     if (hipGetLastError() != hipSuccess) return BC_EDEVICE;
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, rowcnt, kindcnt, (int)N, rowptr,
@@ -267,7 +319,7 @@ int launch_pattern(const int32_t *tris, int64_t N, double near_factor, const voi
     char *pb = static_cast<char *>(pattern);
     if (hipMemcpyAsync(pb + P.rowptr, rowptr, sizeof(int32_t) * (N + 1), hipMemcpyDeviceToDevice, s) != hipSuccess)
       return BC_EDEVICE;
-    hipLaunchKernelGGL(k_pattern<true>, dim3(grid), dim3(kWG), 0, s, tri4, cen4, (int)N, nf2, (int32_t *)nullptr,
+    hipLaunchKernelGGL(k_pattern<true>, dim3(grid), dim3(kWG), 0, s, tri4, cen4, bbox, (int)N, nf2, (int32_t *)nullptr,
                        (int32_t *)nullptr, (const int32_t *)rowptr, reinterpret_cast<int32_t *>(pb + P.col),
                        reinterpret_cast<int32_t *>(pb + P.row), reinterpret_cast<int32_t *>(pb + P.kind));
   }

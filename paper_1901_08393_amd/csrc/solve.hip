@@ -285,14 +285,14 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
              P.spin_limit};
 
   int32_t phase, iters, outer, inner;
-  double bnorm, rnorm, scale, gamma, eta, alpha, beta;
+  double bnorm, rnorm, scale, gamma, eta, alpha, beta, itol;
   if (S.start) {
     phase = PH_INIT; iters = 0; outer = 0; inner = 0;
-    bnorm = rnorm = scale = gamma = eta = alpha = beta = 0.0;
+    bnorm = rnorm = scale = gamma = eta = alpha = beta = itol = 0.0;
   } else {
     phase = ctl->phase; iters = ctl->iters; outer = ctl->outer; inner = ctl->inner; bar.epoch = ctl->epoch;
     bnorm = ctl->bnorm; rnorm = ctl->rnorm; scale = ctl->scale; gamma = ctl->gamma; eta = ctl->eta;
-    alpha = ctl->alpha; beta = ctl->beta;
+    alpha = ctl->alpha; beta = ctl->beta; itol = ctl->itol;
   }
   if (phase == PH_DONE) return;
   int32_t status = BC_OK;
@@ -342,6 +342,8 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       if (!(rnorm > P.rtol * bnorm)) { status = BC_OK; phase = PH_DONE; continue; }
       if (outer > P.max_outer || iters >= P.max_iter) { status = BC_ENOCONV; phase = PH_DONE; continue; }
       scale = 1.0 / rnorm;
+      // the inner solve need not go further than the outer tolerance asks
+      itol = fmax(P.inner_rtol, 0.3 * P.rtol * bnorm / rnorm);
       // inner start: r = r64 / ||r64||, u = M^-1 r, d = p = s = 0
       double pru = 0.0;
       for (int i = r0 + t; i < r1; i += kSolveWG) {
@@ -402,7 +404,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
         rr = tot[1];
       }
       inner += 1;
-      if (!(sqrt(rr) > P.inner_rtol) || iters >= P.max_iter) { phase = PH_UPDATE; continue; }
+      if (!(sqrt(rr) > itol) || iters >= P.max_iter) { phase = PH_UPDATE; continue; }
       double pwu = 0.0;
       wave_matvec<MT, VT, VT>(V, ld, vu, wr0, wr1, [&](int i, VT acc) {
         vw[i] = acc;
@@ -464,7 +466,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
     } else {
       ctl->phase = phase; ctl->iters = iters; ctl->outer = outer; ctl->inner = inner; ctl->epoch = bar.epoch;
       ctl->bnorm = bnorm; ctl->rnorm = rnorm; ctl->scale = scale; ctl->gamma = gamma; ctl->eta = eta;
-      ctl->alpha = alpha; ctl->beta = beta;
+      ctl->alpha = alpha; ctl->beta = beta; ctl->itol = itol;
       result->iters = iters;
       result->outer = outer;
       result->status = BC_RUNNING;
