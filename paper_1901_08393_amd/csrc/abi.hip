@@ -240,6 +240,7 @@ static int fill_desc(const bc_system &s, int wg_begin, SysDesc &d) {
   if (s.precision != BC_FP64 && s.precision != BC_MIXED) return BC_EINVAL;
   if (s.precision == BC_MIXED && s.nnz > 0 && !s.pattern) return BC_EINVAL;
   if (s.reserved != 0 || s.iter_budget < 0) return BC_EINVAL;
+  if (s.N > (int64_t)kMaxBand * solve_workgroups(s.N)) return BC_EINVAL;  // rows per workgroup
   std::memset(&d, 0, sizeof(d));
   d.V = s.V;
   if (s.pattern && s.nnz > 0) {

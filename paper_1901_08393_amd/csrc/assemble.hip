@@ -17,6 +17,8 @@
 //   precision it also stores the FP64 correction V64 - (double)(float)V64 at
 //   both (i, j) and (j, i) of the pattern.
 // k_pad: zeros in the padding columns N..ld-1.
+#include <type_traits>
+
 #include "bc_internal.h"
 
 namespace bc {
@@ -82,11 +84,24 @@ __global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, 
 // with scale = (1/4pi) (sum w / sum fl(w))^2 formed in FP64 on the host, so
 // that neither 1/(4pi) nor the weights carry an FP32 rounding that is the
 // same for every entry (such a common rounding would shift the capacity by
-// the same relative amount).
+// the same relative amount).  The inverse distance is the hardware estimate
+// refined by one Newton step whose small correction e = 1 - r^2 y0^2 is
+// formed on its own (a step folded into a value near 2 would round the
+// correction away and leave the estimate's one-sided error in place).
+//
+// The kernel forms c = -r^2.  For tiles whose bounding boxes are at least
+// kSepFar block diameters apart it expands c = -|e|^2 - |y|^2 + 2 e.y with
+// e = c_i - c_j + x_a and y the offset of y_b from c_j, so that a point pair
+// costs one add and three FMAs; closer tiles form the differences.  At that
+// separation the expansion loses at most a few roundings of |e|^2 over
+// r^2 <= (1 + 1/kSepFar)^2 + 1/kSepFar^2.
+constexpr double kSepFar = 4.0;
+
 template <int Q>
 __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, const float *__restrict__ qpS,
                                                const double4 *__restrict__ cen4, const double *__restrict__ area,
-                                               double scale, int N, int64_t ld, float *__restrict__ V) {
+                                               const double *__restrict__ bbox, double scale, int N, int64_t ld,
+                                               float *__restrict__ V) {
   int I, J;
   tile_of(blockIdx.x, I, J);
   const int lane = threadIdx.x & 63;
@@ -94,20 +109,24 @@ __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, c
   const int j = J * 64 + lane;
   const bool jv = j < N;
   const int jj = jv ? j : N - 1;
-  float vx[Q], vy[Q], vz[Q], vw[Q];
+  float vx[Q], vy[Q], vz[Q], vw[Q], vn[Q];
 #pragma unroll
   for (int b = 0; b < Q; ++b) {
     vx[b] = qpS[(size_t)(b * 4 + 0) * N + jj];
     vy[b] = qpS[(size_t)(b * 4 + 1) * N + jj];
     vz[b] = qpS[(size_t)(b * 4 + 2) * N + jj];
     vw[b] = qpS[(size_t)(b * 4 + 3) * N + jj];
+    vn[b] = -(vx[b] * vx[b] + vy[b] * vy[b] + vz[b] * vz[b]);
+  }
+  bool sep;
+  {
+    const double *bi = bbox + 8 * I, *bj = bbox + 8 * J;
+    sep = box_dist2(bi, bj) >= kSepFar * kSepFar * fmax(bi[6], bj[6]);
   }
   const double4 cj = cen4[jj];
   const double aj = 4.0 * area[jj] * scale;
   const int i0 = I * 64 + w * 16;
-  for (int k = 0; k < 16; ++k) {
-    const int i = i0 + k;
-    if (i >= N) break;
+  auto row = [&](auto SEP, int i) {
     const double4 ci = cen4[i];
     // centroid difference formed in FP64, then rounded: no cancellation of
     // absolute coordinates on small or distant elements
@@ -118,12 +137,21 @@ __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, c
     for (int a = 0; a < Q; ++a) {
       const float4 p = ua[a];
       const float ex = Dx + p.x, ey = Dy + p.y, ez = Dz + p.z;
+      const float ne = -(ex * ex + ey * ey + ez * ez);
+      const float tx = 2.0f * ex, ty = 2.0f * ey, tz = 2.0f * ez;
       float s = 0.f;
 #pragma unroll
       for (int b = 0; b < Q; ++b) {
-        float dx = ex - vx[b], dy = ey - vy[b], dz = ez - vz[b];
-        float r2 = dx * dx + dy * dy + dz * dz;
-        s = __builtin_fmaf(vw[b], rsqrt32(r2), s);
+        float c;  // -r^2
+        if constexpr (decltype(SEP)::value) {
+          c = __builtin_fmaf(tz, vz[b], __builtin_fmaf(ty, vy[b], __builtin_fmaf(tx, vx[b], ne + vn[b])));
+        } else {
+          const float dx = ex - vx[b], dy = ey - vy[b], dz = ez - vz[b];
+          c = -(dx * dx + dy * dy + dz * dz);
+        }
+        const float y0 = __builtin_amdgcn_rsqf(-c);
+        const float e = __builtin_fmaf(c, y0 * y0, 1.0f);  // 1 - r^2 y0^2
+        s = __builtin_fmaf(vw[b], __builtin_fmaf(0.5f * y0, e, y0), s);
       }
       acc = __builtin_fmaf(p.w, s, acc);
     }
@@ -132,6 +160,11 @@ __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, c
       V[(size_t)i * ld + j] = v;
       V[(size_t)j * ld + i] = v;
     }
+  };
+  for (int k = 0; k < 16; ++k) {
+    const int i = i0 + k;
+    if (i >= N) break;
+    if (sep) row(std::true_type{}, i); else row(std::false_type{}, i);
   }
 }
 
@@ -305,8 +338,8 @@ static void far_launch(bool mixed, const MeshView &m, int N, int64_t ld, void *V
   if (!mixed)
     hipLaunchKernelGGL(k_far64<Q>, dim3(tiles), dim3(kWG), 0, s, m.qpA64, m.qpS64, N, ld, static_cast<double *>(V));
   else
-    hipLaunchKernelGGL(k_far32<Q>, dim3(tiles), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, scale, N, ld,
-                       static_cast<float *>(V));
+    hipLaunchKernelGGL(k_far32<Q>, dim3(tiles), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox, scale, N,
+                       ld, static_cast<float *>(V));
 }
 
 // (1/4pi) (sum_k w_k / sum_k fl32(w_k))^2 for the collapsed rule of order n

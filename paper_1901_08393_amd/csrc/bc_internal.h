@@ -55,6 +55,7 @@ struct MeshView {
   const float4 *qpA32;   // [N][Q] (x - c, y - c, z - c, W)
   const float *qpS32;    // [(b*4+c)][N]
   const int32_t *rowptr; // N + 1
+  const double *bbox;    // per 64 elements: min xyz, max xyz, max diam^2, 0
 };
 
 inline MeshView mesh_view(const void *ws, int64_t N) {
@@ -69,6 +70,7 @@ inline MeshView mesh_view(const void *ws, int64_t N) {
   v.qpA32 = reinterpret_cast<const float4 *>(b + L.qpA32);
   v.qpS32 = reinterpret_cast<const float *>(b + L.qpS32);
   v.rowptr = reinterpret_cast<const int32_t *>(b + L.rowptr);
+  v.bbox = reinterpret_cast<const double *>(b + L.blockbox);
   return v;
 }
 
@@ -104,29 +106,57 @@ struct alignas(64) BarRel {
   unsigned pad[6];
 };
 
-__host__ __device__ inline void solve_offsets(int64_t N, int32_t precision, size_t &ctl, size_t &slots,
-                                              size_t &rel, size_t &x64, size_t &r64, size_t &vec, size_t &total,
-                                              int64_t &ld) {
-  ld = (N + 63) / 64 * 64;
-  size_t o = 0;
-  auto take = [&](size_t bytes) {
-    size_t r = o;
-    o = (o + bytes + 255) & ~size_t(255);
-    return r;
-  };
-  ctl = take(1024);
-  slots = take(sizeof(BarSlot) * kGMax);
-  rel = take(sizeof(BarRel) * kNRep);
-  x64 = take(sizeof(double) * ld);
-  r64 = take(sizeof(double) * ld);
-  vec = take((precision == BC_FP64 ? 8 : 4) * ld * 7);  // r u w p s d invdiag
-  total = o;
+// Symmetric product.  V is read only on its diagonal blocks and above them:
+// rows are grouped in blocks of kRB, and block b is swept from column kRB*b to
+// ld in chunks of 64*k columns (16 bytes per lane: k = 4 FP32 or 2 FP64
+// entries).  A unit is one (block, chunk) pair; units are numbered block by
+// block and the workgroups of a system take equal contiguous ranges of them.
+constexpr int kRB = 128;        // rows per block of the symmetric product
+constexpr int kMaxBand = 1536;  // rows of the vectors owned by one solver workgroup
+
+// Units of the blocks 0..B-1, m64 = ld / 64.  Block b has
+// ceil((m64 - 2b) / k) units; the sum is written out for k = 2 and k = 4
+// (pairs of blocks for k = 4).
+__host__ __device__ inline int64_t half_units_before(int64_t B, int64_t m64, int k) {
+  if (k == 2) return B * ((m64 + 1) / 2) - B * (B - 1) / 2;
+  const int64_t n = m64 + 3, f0 = n / 4, f2 = (n - 2) / 4, A = B / 2;
+  int64_t s = A * (f0 + f2) - A * (A - 1);
+  if (B & 1) s += f0 - A;
+  return s;
 }
 
+// Offsets inside one system's solver workspace (256-byte aligned).
+//   ctl    control block, then the solver descriptor of bc_solve
+//   slots  barrier slots, one per workgroup;  rel  release records
+//   x64 r64   FP64 iterate and residual
+//   vec    r u w p s d invdiag in the matrix precision
+//   rpart  row partial sums of the symmetric product, kRB per unit
+//   cpart  column partial sums, ld per row block
 struct SolveLayout {
-  size_t ctl, slots, rel, x64, r64, vec, total;
-  int64_t ld;
-  SolveLayout(int64_t N, int32_t precision) { solve_offsets(N, precision, ctl, slots, rel, x64, r64, vec, total, ld); }
+  size_t ctl, slots, rel, x64, r64, vec, rpart, cpart, total;
+  int64_t ld, nB, T;
+  int k;
+  __host__ __device__ SolveLayout(int64_t N, int32_t precision) {
+    ld = (N + 63) / 64 * 64;
+    k = precision == BC_FP64 ? 2 : 4;
+    nB = (N + kRB - 1) / kRB;
+    T = half_units_before(nB, ld / 64, k);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+      size_t r = o;
+      o = (o + bytes + 255) & ~size_t(255);
+      return r;
+    };
+    ctl = take(1024);
+    slots = take(sizeof(BarSlot) * kGMax);
+    rel = take(sizeof(BarRel) * kNRep);
+    x64 = take(sizeof(double) * ld);
+    r64 = take(sizeof(double) * ld);
+    vec = take((precision == BC_FP64 ? 8 : 4) * ld * 7);
+    rpart = take(sizeof(double) * kRB * (size_t)T);
+    cpart = take(sizeof(double) * (size_t)ld * (size_t)nB);
+    total = o;
+  }
 };
 
 // Per-system control block at the start of the solver workspace.  Written
@@ -205,6 +235,22 @@ __device__ __forceinline__ float rsqrt32(float x) {
   return __builtin_fmaf(0.5f * y, e, y);
 }
 
+// Squared distance between two axis-aligned boxes given as (min xyz, max
+// xyz); 0 if they touch or overlap.
+__device__ __forceinline__ double box_dist2(const double *a, const double *b) {
+  double s = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const double g = fmax(0.0, fmax(a[c] - b[3 + c], b[c] - a[3 + c]));
+    s += g * g;
+  }
+  return s;
+}
+
+// Fused multiply-add in the type of the operands (__builtin_fma alone would
+// promote float operands to double).
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Sum over the 64 lanes of a wavefront with a fixed butterfly order; every
 // lane receives the total.
 template <typename T>
@@ -212,6 +258,39 @@ __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
+}
+
+// Sum over the 64 lanes of a wavefront whose lanes are all active, with
+// DPP lane exchanges (fixed order): pairs and quads by quad permutations,
+// eight and sixteen lanes by the half-row and row mirrors, then the four
+// rows of sixteen read out in order, ((r0 + r1) + (r2 + r3)).  Needs no lane
+// index and no LDS; every lane receives the total.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ float lane_f(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double lane_f(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <typename T>
+__device__ __forceinline__ T wave_sum_full(T v) {
+  v += dpp_f<0xB1>(v);   // quad_perm(1,0,3,2): lane ^ 1
+  v += dpp_f<0x4E>(v);   // quad_perm(2,3,0,1): lane ^ 2
+  v += dpp_f<0x141>(v);  // row_half_mirror: the other quad of eight
+  v += dpp_f<0x140>(v);  // row_mirror: the other eight of sixteen
+  return (lane_f(v, 0) + lane_f(v, 16)) + (lane_f(v, 32) + lane_f(v, 48));
 }
 
 }  // namespace bc

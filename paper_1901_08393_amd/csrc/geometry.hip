@@ -128,15 +128,6 @@ __global__ __launch_bounds__(64) void k_blockbox(const double *__restrict__ vert
   }
 }
 
-// Squared distance between two boxes (0 if they touch or overlap).
-__device__ __forceinline__ double box_dist2(const double *a, const double *b) {
-  double s = 0.0;
-  for (int c = 0; c < 3; ++c) {
-    const double g = fmax(0.0, fmax(a[c] - b[3 + c], b[c] - a[3 + c]));
-    s += g * g;
-  }
-  return s;
-}
 
 // One workgroup per block of 64 rows (16 rows per wave); lanes sweep the
 // columns 64 at a time.  Row data are staged in LDS (broadcast reads).

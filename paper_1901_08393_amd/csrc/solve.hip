@@ -188,56 +188,201 @@ struct Load16<double, double> {
   }
 };
 
-// out(i) = sum_j V[i][j] x[j] for the R rows g0..g0+R-1: the 64 lanes of the
-// wavefront sweep the columns with 16-byte loads, R independent rows per
-// step (no branch inside the sweep, so all loads of a step are in flight
-// together); lane 0 calls epi(row, sum) after a fixed-order reduction.
-template <typename MT, typename XT, typename AT, int R, typename Epi>
-__device__ __forceinline__ void sweep_rows(gptr<const MT> V, int64_t ld, gptr<const XT> x, int g0, Epi &epi) {
+// ------------------------------------------------ symmetric half product
+// y = V x reading V only on its diagonal blocks and above them.  A unit
+// (block B, chunk c) covers the rows [kRB B, kRB B + kRB) and CW = 64 VEC
+// columns; wavefront w of the workgroup owns 8 of the block's rows and lane l
+// VEC consecutive columns of the chunk.  For its rows a unit adds
+// V[i][j] x[j] to the row sums (kept in registers across the chunks of a
+// segment: the units of one block that one workgroup holds), and for the
+// columns right of the diagonal block it forms the column sums
+// sum_i V[i][j] x[i], which stand for the lower triangle by symmetry.  The
+// sixteen wavefronts' column sums are added in LDS in wavefront order and
+// stored per row block (cpart); the row sums are stored per segment (rpart).
+// half_gather then forms y_i = (row sums of i's segments) + (column sums of
+// the row blocks above i), each in a fixed order, so the result depends on
+// N and the workgroup count only.  With DELTA the kernel also returns this
+// workgroup's share of x^T V x, summed from the same column sums (weight 1 on
+// the diagonal block, 2 right of it), so that an inner product of the CG
+// iteration needs no pass over y.
+struct HalfPlan {
+  int64_t ld, m64, T;
+  int N, nB, k, G;
+  int64_t u0, u1;  // this workgroup's units
+};
+
+template <typename MT, typename XT, typename AT, bool DELTA, bool LDS2>
+__device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x, const HalfPlan &H, gptr<AT> rpart,
+                                             gptr<AT> cpart, AT *lbuf, double &delta) {
   using L = Load16<MT, XT>;
   constexpr int VEC = L::VEC;
-  const int lane = threadIdx.x & 63;
-  AT acc[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = AT(0);
-  gptr<const MT> row0 = V + (size_t)g0 * ld;
-#pragma unroll 2
-  for (int64_t c = (int64_t)lane * VEC; c < ld; c += 64 * VEC) {
-    XT xv[VEC];
-    L::vec(x + c, xv);
-    MT vv[R][VEC];
-#pragma unroll
-    for (int r = 0; r < R; ++r) L::mat(row0 + (size_t)r * ld + c, vv[r]);
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-      for (int q = 0; q < VEC; ++q) acc[r] = __builtin_fma((AT)vv[r][q], (AT)xv[q], acc[r]);
+  constexpr int CW = 64 * VEC;
+  int64_t u = H.u0;
+  if (u >= H.u1) return;
+  // lane from mbcnt and the wavefront index as a scalar: both can be
+  // recomputed where needed instead of being kept in registers
+  const int lane = (int)__lane_id();
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int tid = 64 * w + lane;
+  const int N = H.N;
+  const int ld = (int)H.ld;
+  // block of the first unit
+  int B;
+  {
+    int lo = 0, hi = H.nB - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (half_units_before(mid, H.m64, H.k) <= u) lo = mid; else hi = mid - 1;
+    }
+    B = lo;
   }
+  int64_t SE = half_units_before(B + 1, H.m64, H.k);  // first unit of the next block
+  int c = (int)(u - half_units_before(B, H.m64, H.k));
+  int64_t useg = u;  // first unit of the current segment (its row sums are stored there)
+
+  AT xr[8], acc[8];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const AT sum = wave_sum(acc[r]);
-    if (lane == 0) epi(g0 + r, sum);
+  for (int r = 0; r < 8; ++r) {
+    const int row = kRB * B + 8 * w + r;
+    xr[r] = (c > 0 && row < N) ? (AT)x[row] : AT(0);  // chunk 0 brings them itself
+    acc[r] = AT(0);
   }
+  MT va[8][VEC];
+  XT xa[VEC];
+  // loads of unit (Bl, cl): the wavefront's 8 rows of block Bl (their bases
+  // are the same for the whole wavefront) and the lane's VEC columns
+  auto load = [&](int Bl, int cl) {
+    const int c0 = kRB * Bl + CW * cl + lane * VEC;
+    const int cc = c0 < ld ? c0 : ld - VEC;  // lanes past the end read the last columns, weighted 0
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int row = min(kRB * Bl + 8 * w + r, N - 1);
+      L::mat(V + (size_t)row * (size_t)ld + cc, va[r]);
+    }
+    L::vec(x + cc, xa);
+  };
+  load(B, c);
+  // Units are swept as one stream: the loads of the next unit (of this block
+  // or the next) are issued as soon as this unit's registers are free, so
+  // they are in flight across the workgroup barrier and across block ends.
+  while (true) {
+    const int col = kRB * B + CW * c + lane * VEC;
+    const bool act = col < ld;
+    if (c == 0) {
+      // chunk 0 starts at column kRB B: lane l holds x[kRB B + VEC l + q],
+      // among them the x values of this wavefront's rows
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const XT v = __shfl(xa[r % VEC], (8 * w + r) / VEC, 64);
+        xr[r] = kRB * B + 8 * w + r < N ? (AT)v : AT(0);
+      }
+    }
+    AT xq[VEC], cs[VEC];
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+      xq[q] = act ? (AT)xa[q] : AT(0);
+      cs[q] = AT(0);
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) {
+        acc[r] = fma_t((AT)va[r][q], xq[q], acc[r]);
+        cs[q] = fma_t((AT)va[r][q], xr[r], cs[q]);
+      }
+    const int diag_end = kRB * B + kRB;
+    if (DELTA) {
+      double d = 0.0;
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) d = __builtin_fma((double)xq[q], (double)cs[q], d);
+      delta = __builtin_fma(col < diag_end ? 1.0 : 2.0, d, delta);
+    }
+    AT *lb = lbuf + (LDS2 ? (int)(u & 1) * (16 * CW) : 0);
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) lb[w * CW + lane * VEC + q] = cs[q];
+    const bool more = u + 1 < H.u1;
+    const bool same = u + 1 < SE;
+    if (more) load(same ? B : B + 1, same ? c + 1 : 0);
+    __syncthreads();
+    if (tid < CW) {
+      const int ct = kRB * B + CW * c + tid;
+      if (ct >= diag_end && ct < ld) {
+        AT sum = AT(0);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) sum += lb[q * CW + tid];
+        cpart[(size_t)B * (size_t)ld + ct] = sum;
+      }
+    }
+    // with two buffers the next unit writes the other one; the barrier of
+    // that unit orders these reads before the writes of the unit after
+    if (!LDS2) __syncthreads();
+    if (!more || !same) {
+      // end of a segment: the row sums of this block's units
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const AT sum = wave_sum_full(acc[r]);
+        if (lane == r && kRB * B + 8 * w + r < N) rpart[(size_t)useg * kRB + 8 * w + r] = sum;
+        acc[r] = AT(0);
+      }
+      useg = u + 1;
+    }
+    if (!more) break;
+    ++u;
+    if (same) {
+      ++c;
+    } else {
+      ++B;
+      c = 0;
+      SE = half_units_before(B + 1, H.m64, H.k);
+    }
+  }
+  if (LDS2) __syncthreads();  // the last column sums are read before lbuf is reused
 }
 
-// The rows [wr0, wr1) of this wavefront, at most 8 per sweep.
-template <typename MT, typename XT, typename AT, typename Epi>
-__device__ __forceinline__ void wave_matvec(gptr<const MT> V, int64_t ld, gptr<const XT> x, int wr0, int wr1,
-                                            Epi epi) {
-  int g0 = wr0;
-  while (g0 < wr1) {
-    const int n = min(8, wr1 - g0);
-    switch (n) {
-      case 8: sweep_rows<MT, XT, AT, 8>(V, ld, x, g0, epi); break;
-      case 7: sweep_rows<MT, XT, AT, 7>(V, ld, x, g0, epi); break;
-      case 6: sweep_rows<MT, XT, AT, 6>(V, ld, x, g0, epi); break;
-      case 5: sweep_rows<MT, XT, AT, 5>(V, ld, x, g0, epi); break;
-      case 4: sweep_rows<MT, XT, AT, 4>(V, ld, x, g0, epi); break;
-      case 3: sweep_rows<MT, XT, AT, 3>(V, ld, x, g0, epi); break;
-      case 2: sweep_rows<MT, XT, AT, 2>(V, ld, x, g0, epi); break;
-      default: sweep_rows<MT, XT, AT, 1>(V, ld, x, g0, epi); break;
+// y_i for the rows [r0, r1) of this workgroup into band[i - r0]: the row
+// sums of the segments of i's block (one per workgroup that holds units of
+// it, in workgroup order) and then the column sums of the row blocks
+// 0 .. B(i)-1.  Lanes take rows, the sixteen wavefronts take every
+// sixteenth term, and the wavefronts' sums are added in wavefront order.
+template <typename AT>
+__device__ __noinline__ void half_gather(const HalfPlan &H, int r0, int r1, gptr<const AT> rpart,
+                                         gptr<const AT> cpart, AT *lpart, AT *band) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int t0 = r0; t0 < r1; t0 += 64) {
+    const int i = t0 + lane;
+    AT s = AT(0);
+    if (i < r1) {
+      const int B = i / kRB;
+      const int64_t SB = half_units_before(B, H.m64, H.k), SE = half_units_before(B + 1, H.m64, H.k);
+      // workgroups holding the units SB and SE - 1 (ranges [T g / G, T (g+1) / G))
+      const int glo = (int)(((SB + 1) * H.G + H.T - 1) / H.T) - 1;
+      const int ghi = (int)((SE * H.G + H.T - 1) / H.T) - 1;
+      const int nseg = ghi - glo + 1;
+      const int nterm = nseg + B;
+      const int ii = i - kRB * B;
+      for (int q = w; q < nterm; q += 16) {
+        if (q < nseg) {
+          int64_t us = SB;
+          if (q > 0) {
+            const int g = glo + q;
+            us = H.T * g / H.G;
+            if (H.T * (g + 1) / H.G == us) continue;  // workgroup without units
+          }
+          s += rpart[(size_t)us * kRB + ii];
+        } else {
+          s += cpart[(size_t)(q - nseg) * (size_t)H.ld + i];
+        }
+      }
     }
-    g0 += n;
+    lpart[w * 64 + lane] = s;
+    __syncthreads();
+    if (w == 0 && i < r1) {
+      AT tot = AT(0);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) tot += lpart[q * 64 + lane];
+      band[i - r0] = tot;
+    }
+    __syncthreads();
   }
 }
 
@@ -249,6 +394,9 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
   constexpr bool MIXED = sizeof(MT) == 4;
   __shared__ double s_red[80];
   __shared__ int s_flag;
+  __shared__ double s_buf[4096];       // column sums of the symmetric product (32 KB)
+  __shared__ double s_part[16 * 64];   // per-wavefront sums of half_gather
+  __shared__ double s_band[kMaxBand];  // V x on this workgroup's rows
 
   // system of this workgroup: last descriptor with wg_begin <= blockIdx.x
   int lo = 0, hi = P.n_sys - 1;
@@ -263,17 +411,22 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
   const int N = (int)S.N;
   const int t = threadIdx.x, w = t >> 6;
   const int r0 = (int)((int64_t)N * rank / G), r1 = (int)((int64_t)N * (rank + 1) / G);
-  const int nb = r1 - r0;
-  const int wr0 = r0 + nb * w / kWaves, wr1 = r0 + nb * (w + 1) / kWaves;  // this wavefront's rows
-  size_t o_ctl, o_slots, o_rel, o_x, o_r, o_vec, o_total;
-  int64_t ld;
-  solve_offsets(S.N, MIXED ? BC_MIXED : BC_FP64, o_ctl, o_slots, o_rel, o_x, o_r, o_vec, o_total, ld);
+  const SolveLayout Lay(S.N, MIXED ? BC_MIXED : BC_FP64);
+  const int64_t ld = Lay.ld;
+  HalfPlan H;
+  H.ld = ld; H.m64 = ld / 64; H.T = Lay.T; H.N = N; H.nB = (int)Lay.nB; H.k = Lay.k; H.G = G;
+  H.u0 = Lay.T * rank / G; H.u1 = Lay.T * (rank + 1) / G;
   gptr<char> ws = as_global(S.ws);
-  gptr<SolveCtl> ctl = reinterpret_cast<gptr<SolveCtl>>(ws + o_ctl);
-  gptr<double> x64 = reinterpret_cast<gptr<double>>(ws + o_x);
-  gptr<double> r64 = reinterpret_cast<gptr<double>>(ws + o_r);
-  gptr<VT> vr = reinterpret_cast<gptr<VT>>(ws + o_vec);
+  gptr<SolveCtl> ctl = reinterpret_cast<gptr<SolveCtl>>(ws + Lay.ctl);
+  gptr<double> x64 = reinterpret_cast<gptr<double>>(ws + Lay.x64);
+  gptr<double> r64 = reinterpret_cast<gptr<double>>(ws + Lay.r64);
+  gptr<VT> vr = reinterpret_cast<gptr<VT>>(ws + Lay.vec);
   gptr<VT> vu = vr + ld, vw = vu + ld, vp = vw + ld, vs = vp + ld, vd = vs + ld, idg = vd + ld;
+  gptr<double> rpD = reinterpret_cast<gptr<double>>(ws + Lay.rpart);
+  gptr<double> cpD = reinterpret_cast<gptr<double>>(ws + Lay.cpart);
+  gptr<VT> rpV = reinterpret_cast<gptr<VT>>(ws + Lay.rpart);
+  gptr<VT> cpV = reinterpret_cast<gptr<VT>>(ws + Lay.cpart);
+  VT *bandV = reinterpret_cast<VT *>(s_band);
   gptr<const MT> V = as_global(static_cast<const MT *>(S.V));
   gptr<const double> b = as_global(S.area);
   gptr<double> sigma = as_global(S.sigma);
@@ -281,7 +434,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
   gptr<const double> pcorr = as_global(S.pcorr);
   gptr<const int32_t> prowptr = as_global(S.prowptr), pcol = as_global(S.pcol);
 
-  SysBar bar{reinterpret_cast<gptr<BarSlot>>(ws + o_slots), reinterpret_cast<gptr<BarRel>>(ws + o_rel), G, rank, 0u,
+  SysBar bar{reinterpret_cast<gptr<BarSlot>>(ws + Lay.slots), reinterpret_cast<gptr<BarRel>>(ws + Lay.rel), G, rank, 0u,
              P.spin_limit};
 
   int32_t phase, iters, outer, inner;
@@ -321,8 +474,15 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       if (budget <= 0) break;
       budget -= 2;
       // r = b - A x in FP64
+      {
+        double unused = 0.0, dummy[1];
+        half_product<MT, double, double, false, false>(V, x64, H, rpD, cpD, s_buf, unused);
+        if (!sys_sync<1>(bar, none, dummy, s_red, &s_flag)) { aborted = true; break; }
+        half_gather<double>(H, r0, r1, rpD, cpD, s_part, s_band);
+      }
       double pr = 0.0, pb = 0.0;
-      wave_matvec<MT, double, double>(V, ld, x64, wr0, wr1, [&](int i, double acc) {
+      for (int i = r0 + t; i < r1; i += kSolveWG) {
+        double acc = s_band[i - r0];
         if (MIXED && S.pcorr != nullptr) {
           for (int e = prowptr[i]; e < prowptr[i + 1]; ++e) acc = __builtin_fma(pcorr[e], x64[pcol[e]], acc);
         }
@@ -330,7 +490,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
         r64[i] = ri;
         pr = __builtin_fma(ri, ri, pr);
         pb = __builtin_fma(b[i], b[i], pb);
-      });
+      }
       {
         const double v[2] = {pr, pb};
         double tot[2];
@@ -359,10 +519,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
         gamma = tot[0];
       }
       double pwu = 0.0;
-      wave_matvec<MT, VT, VT>(V, ld, vu, wr0, wr1, [&](int i, VT acc) {
-        vw[i] = acc;
-        pwu += (double)acc * (double)vu[i];
-      });
+      half_product<MT, VT, VT, true, true>(V, vu, H, rpV, cpV, reinterpret_cast<VT *>(s_buf), pwu);
       {
         const double v[1] = {pwu};
         double tot[1];
@@ -380,11 +537,13 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
     if (phase == PH_CG) {
       if (budget <= 0) break;
       budget -= 1;
+      // w = V u of the last product
+      half_gather<VT>(H, r0, r1, rpV, cpV, reinterpret_cast<VT *>(s_part), bandV);
       const VT a = (VT)alpha, bt = (VT)beta;
       double pru = 0.0, prr = 0.0;
       for (int i = r0 + t; i < r1; i += kSolveWG) {
         const VT pi = vu[i] + bt * vp[i];
-        const VT si = vw[i] + bt * vs[i];
+        const VT si = bandV[i - r0] + bt * vs[i];
         vp[i] = pi;
         vs[i] = si;
         vd[i] = vd[i] + a * pi;
@@ -406,10 +565,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       inner += 1;
       if (!(sqrt(rr) > itol) || iters >= P.max_iter) { phase = PH_UPDATE; continue; }
       double pwu = 0.0;
-      wave_matvec<MT, VT, VT>(V, ld, vu, wr0, wr1, [&](int i, VT acc) {
-        vw[i] = acc;
-        pwu += (double)acc * (double)vu[i];
-      });
+      half_product<MT, VT, VT, true, true>(V, vu, H, rpV, cpV, reinterpret_cast<VT *>(s_buf), pwu);
       double delta;
       {
         const double v[1] = {pwu};
@@ -482,19 +638,17 @@ __global__ __launch_bounds__(256) void k_solve_init(const SysDesc *__restrict__ 
   if (s >= n_sys) return;
   const SysDesc &S = descs[s];
   if (!S.start) return;
-  size_t o_ctl, o_slots, o_rel, o_x, o_r, o_vec, o_total;
-  int64_t ld;
-  solve_offsets(S.N, BC_FP64, o_ctl, o_slots, o_rel, o_x, o_r, o_vec, o_total, ld);
+  const SolveLayout Lay(S.N, BC_FP64);  // the control block, slots and records do not depend on precision
   const int t = threadIdx.x;
-  BarSlot *slots = reinterpret_cast<BarSlot *>(S.ws + o_slots);
-  BarRel *rel = reinterpret_cast<BarRel *>(S.ws + o_rel);
+  BarSlot *slots = reinterpret_cast<BarSlot *>(S.ws + Lay.slots);
+  BarRel *rel = reinterpret_cast<BarRel *>(S.ws + Lay.rel);
   if (t < kGMax) slots[t].tag = 0u;
   if (t < kNRep) {
     rel[t].gen = 0u;
     rel[t].abort = 0;
   }
   if (t == 0) {
-    SolveCtl *ctl = reinterpret_cast<SolveCtl *>(S.ws + o_ctl);
+    SolveCtl *ctl = reinterpret_cast<SolveCtl *>(S.ws + Lay.ctl);
     ctl->phase = PH_INIT;
     ctl->epoch = 0u;
     S.result->status = BC_RUNNING;

@@ -142,15 +142,20 @@ def test_V_mixed_entrywise(api, name):
     assert relf.max() <= 4e-6, relf.max()
     # no systematic bias: to first order the capacity moves by
     # -x^T (A - V64) x / x^T V64 x (A = stored FP32 matrix plus the FP64
-    # correction), which must stay well below the 1e-8 target
+    # correction), which must stay well below the 1e-8 target.  The entries'
+    # rounding errors (rms `rms`) alone give this weighted mean a spread of
+    # about rms / sqrt(n_far), so the bound is 2e-9 or four such standard
+    # errors, whichever is larger (the latter only binds on meshes with few
+    # far entries).
     bias = np.mean((V32[far] - ref[far]) / ref[far])
     rms = np.sqrt(np.mean(((V32[far] - ref[far]) / ref[far]) ** 2))
     A = V32.copy()
     A[row, col] += corr
     x = oracle.solve_direct(ref, oracle.rhs(m.verts, m.tris))
     wbias = x @ (A - ref) @ x / (x @ ref @ x)
-    _flush(f"  FP32 far-field relative error: mean {bias:.3e} rms {rms:.3e}; x-weighted {wbias:.3e}")
-    assert abs(wbias) <= 2e-9, wbias
+    bound = max(2e-9, 4.0 * rms / math.sqrt(far.sum()))
+    _flush(f"  FP32 far-field relative error: mean {bias:.3e} rms {rms:.3e}; x-weighted {wbias:.3e} (bound {bound:.2e})")
+    assert abs(wbias) <= bound, (wbias, bound)
 
 
 # ----------------------------------------------------------------- solves
