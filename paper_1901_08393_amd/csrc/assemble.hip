@@ -17,6 +17,7 @@
 //   precision it also stores the FP64 correction V64 - (double)(float)V64 at
 //   both (i, j) and (j, i) of the pattern.
 // k_pad: zeros in the padding columns N..ld-1.
+#include <mutex>
 #include <type_traits>
 
 #include "bc_internal.h"
@@ -79,15 +80,15 @@ __global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, 
 
 // FP32 far field.  The point offsets are relative to the element centroid
 // and the weights are those of the reference triangle; the entry is
-//   (float)( (double)S_ij * 4 |T_i| |T_j| * scale ),
-//   S_ij = sum_a w_a sum_b w_b / |x_a - y_b|   (FP32),
-// with scale = (1/4pi) (sum w / sum fl(w))^2 formed in FP64 on the host, so
-// that neither 1/(4pi) nor the weights carry an FP32 rounding that is the
-// same for every entry (such a common rounding would shift the capacity by
-// the same relative amount).  The inverse distance is the hardware estimate
-// refined by one Newton step whose small correction e = 1 - r^2 y0^2 is
-// formed on its own (a step folded into a value near 2 would round the
-// correction away and leave the estimate's one-sided error in place).
+//   (float)( (double)S_ij * 4 |T_i| |T_j| * scale / (1 + beta) ),
+//   S_ij = sum_a w_a sum_b w_b rsq(r_ab^2)   (FP32),
+// with scale = (1/4pi) (sum w / sum fl(w))^2 formed in FP64 on the host and
+// beta the mean relative error of the hardware inverse square root, measured
+// on the device (k_rsq_bias), so that neither 1/(4pi), the weights nor the
+// inverse square root carry an FP32 error that is the same for every entry
+// (such a common error would shift the capacity by the same relative
+// amount).  What remains per point pair is rounding of either sign, about one
+// FP32 ulp, which the 256-term sums and the FP32 storage of V dominate.
 //
 // The kernel forms c = -r^2.  For tiles whose bounding boxes are at least
 // kSepFar block diameters apart it expands c = -|e|^2 - |y|^2 + 2 e.y with
@@ -96,6 +97,46 @@ __global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, 
 // separation the expansion loses at most a few roundings of |e|^2 over
 // r^2 <= (1 + 1/kSepFar)^2 + 1/kSepFar^2.
 constexpr double kSepFar = 4.0;
+
+// Mean relative error of v_rsq_f32 over inputs spread log-uniformly over
+// [1, 4) (the error depends only on the mantissa and the exponent's parity,
+// as scaling x by 4 scales rsq(x) by exactly 1/2): 2^16 inputs
+// x_k = 2^(2 (k + 1/2) / 2^16), errors y sqrt(x) - 1 formed in FP64, summed
+// in a fixed order by one workgroup.  Written once per device.
+__device__ double g_rsq_bias;
+constexpr int kRsqSamples = 1 << 16;
+
+__global__ __launch_bounds__(kWG) void k_rsq_bias() {
+  __shared__ double part[kWG];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < kRsqSamples; k += kWG) {
+    const float x = (float)exp2(2.0 * (k + 0.5) / kRsqSamples);
+    const double y = (double)__builtin_amdgcn_rsqf(x);
+    s += y * sqrt((double)x) - 1.0;
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kWG; ++q) t += part[q];
+    g_rsq_bias = t / kRsqSamples;
+  }
+}
+
+// Runs k_rsq_bias once per device, on the first FP32 assembly, and waits for
+// it so that assemblies on any stream see the value.
+static int rsq_bias_ready(hipStream_t s) {
+  static std::mutex mu;
+  static bool done[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return BC_EDEVICE;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done[dev]) return BC_OK;
+  hipLaunchKernelGGL(k_rsq_bias, dim3(1), dim3(kWG), 0, s);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return BC_EDEVICE;
+  done[dev] = true;
+  return BC_OK;
+}
 
 template <int Q>
 __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, const float *__restrict__ qpS,
@@ -124,7 +165,7 @@ __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, c
     sep = box_dist2(bi, bj) >= kSepFar * kSepFar * fmax(bi[6], bj[6]);
   }
   const double4 cj = cen4[jj];
-  const double aj = 4.0 * area[jj] * scale;
+  const double aj = 4.0 * area[jj] * (scale / (1.0 + g_rsq_bias));
   const int i0 = I * 64 + w * 16;
   auto row = [&](auto SEP, int i) {
     const double4 ci = cen4[i];
@@ -149,9 +190,7 @@ __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, c
           const float dx = ex - vx[b], dy = ey - vy[b], dz = ez - vz[b];
           c = -(dx * dx + dy * dy + dz * dz);
         }
-        const float y0 = __builtin_amdgcn_rsqf(-c);
-        const float e = __builtin_fmaf(c, y0 * y0, 1.0f);  // 1 - r^2 y0^2
-        s = __builtin_fmaf(vw[b], __builtin_fmaf(0.5f * y0, e, y0), s);
+        s = __builtin_fmaf(vw[b], __builtin_amdgcn_rsqf(-c), s);
       }
       acc = __builtin_fmaf(p.w, s, acc);
     }
@@ -365,6 +404,10 @@ int launch_assemble(const void *mesh_ws, const int32_t *tris, const double *vert
   const int64_t T = (N + 63) / 64;
   const int tiles = (int)(T * (T + 1) / 2);
   const double scale = far32_scale(o.far_order);
+  if (mixed) {
+    const int st = rsq_bias_ready(s);
+    if (st != BC_OK) return st;
+  }
   switch (o.far_order) {
     case 1: far_launch<1>(mixed, m, (int)N, ld, V, tiles, scale, s); break;
     case 2: far_launch<4>(mixed, m, (int)N, ld, V, tiles, scale, s); break;

@@ -273,7 +273,7 @@ __device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x,
       // among them the x values of this wavefront's rows
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        const XT v = __shfl(xa[r % VEC], (8 * w + r) / VEC, 64);
+        const XT v = lane_f(xa[r % VEC], (8 * w + r) / VEC);  // the source lane is the same for the wavefront
         xr[r] = kRB * B + 8 * w + r < N ? (AT)v : AT(0);
       }
     }
@@ -342,15 +342,18 @@ __device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x,
 // y_i for the rows [r0, r1) of this workgroup into band[i - r0]: the row
 // sums of the segments of i's block (one per workgroup that holds units of
 // it, in workgroup order) and then the column sums of the row blocks
-// 0 .. B(i)-1.  Lanes take rows, the sixteen wavefronts take every
-// sixteenth term, and the wavefronts' sums are added in wavefront order.
+// 0 .. B(i)-1.  Lanes take rows and the sixteen wavefronts take every
+// sixteenth term; a wavefront keeps four partial sums (terms 16k + w with k
+// mod 4 fixed) so that four loads are in flight, adds them as
+// (s0 + s1) + (s2 + s3), and the wavefronts' sums are added in wavefront
+// order.  The order depends on N and the workgroup count only.
 template <typename AT>
 __device__ __noinline__ void half_gather(const HalfPlan &H, int r0, int r1, gptr<const AT> rpart,
                                          gptr<const AT> cpart, AT *lpart, AT *band) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int t0 = r0; t0 < r1; t0 += 64) {
     const int i = t0 + lane;
-    AT s = AT(0);
+    AT s[4] = {AT(0), AT(0), AT(0), AT(0)};
     if (i < r1) {
       const int B = i / kRB;
       const int64_t SB = half_units_before(B, H.m64, H.k), SE = half_units_before(B + 1, H.m64, H.k);
@@ -360,21 +363,31 @@ __device__ __noinline__ void half_gather(const HalfPlan &H, int r0, int r1, gptr
       const int nseg = ghi - glo + 1;
       const int nterm = nseg + B;
       const int ii = i - kRB * B;
-      for (int q = w; q < nterm; q += 16) {
-        if (q < nseg) {
-          int64_t us = SB;
-          if (q > 0) {
-            const int g = glo + q;
-            us = H.T * g / H.G;
-            if (H.T * (g + 1) / H.G == us) continue;  // workgroup without units
-          }
-          s += rpart[(size_t)us * kRB + ii];
-        } else {
-          s += cpart[(size_t)(q - nseg) * (size_t)H.ld + i];
+      int q = w;
+      for (; q < nseg && q < nterm; q += 16) {  // segment row sums (few)
+        int64_t us = SB;
+        bool ok = true;
+        if (q > 0) {
+          const int g = glo + q;
+          us = H.T * g / H.G;
+          ok = H.T * (g + 1) / H.G != us;  // a workgroup without units has no segment
         }
+        if (ok) s[(q >> 4) & 3] += rpart[(size_t)us * kRB + ii];
       }
+      // column sums of the blocks above: four independent loads per step
+      for (; q + 48 < nterm; q += 64) {
+        const AT v0 = cpart[(size_t)(q - nseg) * (size_t)H.ld + i];
+        const AT v1 = cpart[(size_t)(q + 16 - nseg) * (size_t)H.ld + i];
+        const AT v2 = cpart[(size_t)(q + 32 - nseg) * (size_t)H.ld + i];
+        const AT v3 = cpart[(size_t)(q + 48 - nseg) * (size_t)H.ld + i];
+        s[(q >> 4) & 3] += v0;
+        s[((q >> 4) + 1) & 3] += v1;
+        s[((q >> 4) + 2) & 3] += v2;
+        s[((q >> 4) + 3) & 3] += v3;
+      }
+      for (; q < nterm; q += 16) s[(q >> 4) & 3] += cpart[(size_t)(q - nseg) * (size_t)H.ld + i];
     }
-    lpart[w * 64 + lane] = s;
+    lpart[w * 64 + lane] = (s[0] + s[1]) + (s[2] + s[3]);
     __syncthreads();
     if (w == 0 && i < r1) {
       AT tot = AT(0);
