@@ -356,7 +356,7 @@ def main():
     mean = lambda k: float(np.mean([r[k] for r in recs]))  # noqa: E731
     ld = prob.ld
     elem = 4 if a.precision == "mixed" else 8
-    streams = res.iters + res.outer  # products with V per solve
+    streams = res.iters + res.outer - 1  # products with V per solve (the first residual, with x = 0, needs none)
     # algorithmic bytes: each product reads the diagonal blocks and the blocks
     # above them once (the symmetric half of the stored matrix)
     solve_bytes = streams * half_matrix_bytes(N, elem)

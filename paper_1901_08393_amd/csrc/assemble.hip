@@ -34,8 +34,18 @@ __device__ __forceinline__ void tile_of(int t, int &I, int &J) {
   I = t - j * (j + 1) / 2;
 }
 
+// Tiles whose 64-element blocks' bounding boxes are at least this many block
+// diameters apart use the expanded distance form in the far-field kernels.
+constexpr double kSepFar = 4.0;
+
+// FP64 far field: V_ij = (1/4pi) sum_a sum_b W_a W_b / |x_a - y_b| over the
+// tensor rule's points (absolute coordinates, FP64), the inverse square root
+// refined to full FP64 accuracy (rsqrt64).  Tiles at least kSepFar block
+// diameters apart expand -r^2 = -|x|^2 - |y|^2 + 2 x.y about the column
+// element's centroid (as in the FP32 kernel); closer tiles form differences.
 template <int Q>
 __global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, const double *__restrict__ qpS,
+                                               const double4 *__restrict__ cen4, const double *__restrict__ bbox,
                                                int N, int64_t ld, double *__restrict__ V) {
   int I, J;
   tile_of(blockIdx.x, I, J);
@@ -44,29 +54,45 @@ __global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, 
   const int j = J * 64 + lane;
   const bool jv = j < N;
   const int jj = jv ? j : N - 1;
-  double yx[Q], yy[Q], yz[Q], yw[Q];
+  bool sep;
+  {
+    const double *bi = bbox + 8 * I, *bj = bbox + 8 * J;
+    sep = box_dist2(bi, bj) >= kSepFar * kSepFar * fmax(bi[6], bj[6]);
+  }
+  // column element's points relative to its centroid (separated tiles) or
+  // absolute (close tiles)
+  const double4 cj = cen4[jj];
+  const double ox = sep ? cj.x : 0.0, oy = sep ? cj.y : 0.0, oz = sep ? cj.z : 0.0;
+  double yx[Q], yy[Q], yz[Q], yw[Q], yn[Q];
 #pragma unroll
   for (int b = 0; b < Q; ++b) {
-    yx[b] = qpS[(size_t)(b * 4 + 0) * N + jj];
-    yy[b] = qpS[(size_t)(b * 4 + 1) * N + jj];
-    yz[b] = qpS[(size_t)(b * 4 + 2) * N + jj];
+    yx[b] = qpS[(size_t)(b * 4 + 0) * N + jj] - ox;
+    yy[b] = qpS[(size_t)(b * 4 + 1) * N + jj] - oy;
+    yz[b] = qpS[(size_t)(b * 4 + 2) * N + jj] - oz;
     yw[b] = qpS[(size_t)(b * 4 + 3) * N + jj];
+    yn[b] = -(yx[b] * yx[b] + yy[b] * yy[b] + yz[b] * yz[b]);
   }
   const int i0 = I * 64 + w * 16;
-  for (int k = 0; k < 16; ++k) {
-    const int i = i0 + k;
-    if (i >= N) break;
+  auto row = [&](auto SEP, int i) {
     const double4 *xa = qpA + (size_t)i * kQMax;
     double acc = 0.0;
 #pragma unroll 2
     for (int a = 0; a < Q; ++a) {
       const double4 p = xa[a];
+      const double ex = p.x - ox, ey = p.y - oy, ez = p.z - oz;
+      const double ne = -(ex * ex + ey * ey + ez * ez);
+      const double tx = 2.0 * ex, ty = 2.0 * ey, tz = 2.0 * ez;
       double s = 0.0;
 #pragma unroll
       for (int b = 0; b < Q; ++b) {
-        double dx = p.x - yx[b], dy = p.y - yy[b], dz = p.z - yz[b];
-        double r2 = dx * dx + dy * dy + dz * dz;
-        s = __builtin_fma(yw[b], rsqrt64(r2), s);
+        double c;  // -r^2
+        if constexpr (decltype(SEP)::value) {
+          c = __builtin_fma(tz, yz[b], __builtin_fma(ty, yy[b], __builtin_fma(tx, yx[b], ne + yn[b])));
+        } else {
+          const double dx = ex - yx[b], dy = ey - yy[b], dz = ez - yz[b];
+          c = -(dx * dx + dy * dy + dz * dz);
+        }
+        s = __builtin_fma(yw[b], rsqrt64(-c), s);
       }
       acc = __builtin_fma(p.w, s, acc);
     }
@@ -75,6 +101,11 @@ __global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, 
       V[(size_t)i * ld + j] = v;
       V[(size_t)j * ld + i] = v;
     }
+  };
+  for (int k = 0; k < 16; ++k) {
+    const int i = i0 + k;
+    if (i >= N) break;
+    if (sep) row(std::true_type{}, i); else row(std::false_type{}, i);
   }
 }
 
@@ -96,7 +127,6 @@ __global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, 
 // costs one add and three FMAs; closer tiles form the differences.  At that
 // separation the expansion loses at most a few roundings of |e|^2 over
 // r^2 <= (1 + 1/kSepFar)^2 + 1/kSepFar^2.
-constexpr double kSepFar = 4.0;
 
 // Mean relative error of v_rsq_f32 over inputs spread log-uniformly over
 // [1, 4) (the error depends only on the mantissa and the exponent's parity,
@@ -375,7 +405,8 @@ template <int Q>
 static void far_launch(bool mixed, const MeshView &m, int N, int64_t ld, void *V, int tiles, double scale,
                        hipStream_t s) {
   if (!mixed)
-    hipLaunchKernelGGL(k_far64<Q>, dim3(tiles), dim3(kWG), 0, s, m.qpA64, m.qpS64, N, ld, static_cast<double *>(V));
+    hipLaunchKernelGGL(k_far64<Q>, dim3(tiles), dim3(kWG), 0, s, m.qpA64, m.qpS64, m.cen4, m.bbox, N, ld,
+                       static_cast<double *>(V));
   else
     hipLaunchKernelGGL(k_far32<Q>, dim3(tiles), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox, scale, N,
                        ld, static_cast<float *>(V));

@@ -19,11 +19,13 @@
 //   UPDATE x += ||r|| d in FP64, back to RESID.
 //   DONE   sigma = x, Cap, result.
 //
-// The dense product streams V once from HBM (bandwidth-bound: 4 or 8 bytes
-// per entry, 2 flops): the 64 lanes of a wavefront sweep up to 8 of its rows
-// at a time with 16-byte non-temporal loads; the vector comes from L2.
-// Every reduction has a fixed order, so results are bitwise reproducible and
-// do not depend on which other systems share the launch.
+// The product streams the diagonal blocks of V and the blocks above them once
+// from HBM (bandwidth-bound: 4 or 8 bytes per entry read, 4 flops) and uses
+// each off-diagonal block for both of its triangles (half_product,
+// half_gather).  At the first step without an initial guess x = 0 and r = b
+// needs no product.  Every reduction has a fixed order, so results are
+// bitwise reproducible and do not depend on which other systems share the
+// launch.
 #include <climits>
 
 #include "bc_internal.h"
@@ -486,8 +488,9 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
     if (phase == PH_RESID) {
       if (budget <= 0) break;
       budget -= 2;
-      // r = b - A x in FP64
-      {
+      // r = b - A x in FP64 (x = 0 at the first step without an initial guess)
+      const bool zero_x = outer == 0 && !P.x0_given;
+      if (!zero_x) {
         double unused = 0.0, dummy[1];
         half_product<MT, double, double, false, false>(V, x64, H, rpD, cpD, s_buf, unused);
         if (!sys_sync<1>(bar, none, dummy, s_red, &s_flag)) { aborted = true; break; }
@@ -495,8 +498,8 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       }
       double pr = 0.0, pb = 0.0;
       for (int i = r0 + t; i < r1; i += kSolveWG) {
-        double acc = s_band[i - r0];
-        if (MIXED && S.pcorr != nullptr) {
+        double acc = zero_x ? 0.0 : s_band[i - r0];
+        if (MIXED && S.pcorr != nullptr && !zero_x) {
           for (int e = prowptr[i]; e < prowptr[i + 1]; ++e) acc = __builtin_fma(pcorr[e], x64[pcol[e]], acc);
         }
         const double ri = b[i] - acc;
