@@ -281,6 +281,32 @@ def test_smallest_meshes(api):
         assert r.ok and abs(r.cap - cap_ref) <= 1e-12 * cap_ref
 
 
+def test_workgroups_without_product_units(api):
+    """A box refined to N = 192: the solver runs 3 workgroups, but the mixed
+    (FP32) symmetric product has only 2 units (128-row blocks x 256-column
+    chunks), so one workgroup holds none and only joins the barriers and the
+    gathers.  Both precisions must still match the oracle."""
+    _flush("workgroups without product units (box N=192)")
+    m = synth.box(1.0, 5.0)
+    v, t, _ = synth.refine_uniform(m.verts, synth.init_reference_edges(m.verts, m.tris), 2)
+    from paper_1901_08393_amd import _lib
+
+    assert t.shape[0] == 192 and _lib.lib().bc_solve_workgroups(192) == 3
+    V = oracle.assemble(v, t)
+    b = oracle.rhs(v, t)
+    x = oracle.solve_direct(V, b)
+    cap_ref = oracle.capacity(x, b)
+    p64 = api.CapacityProblem(v, t, "fp64")
+    p64.assemble()
+    r = p64.solve()
+    assert r.ok and abs(r.cap - cap_ref) <= 1e-12 * cap_ref, (r.cap, cap_ref)
+    assert np.abs(p64.sigma.cpu().numpy() - x).max() <= 1e-10 * np.abs(x).max()
+    p32 = api.CapacityProblem(v, t, "mixed")
+    p32.assemble()
+    r = p32.solve()
+    assert r.ok and abs(r.cap - cap_ref) <= 1e-8 * cap_ref, (r.cap, cap_ref)
+
+
 def test_invalid_inputs_rejected(api):
     from paper_1901_08393_amd import _lib
 
