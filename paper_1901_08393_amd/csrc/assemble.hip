@@ -199,15 +199,20 @@ __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, c
   const int i0 = I * 64 + w * 16;
   auto row = [&](auto SEP, int i) {
     const double4 ci = cen4[i];
-    // centroid difference formed in FP64, then rounded: no cancellation of
-    // absolute coordinates on small or distant elements
-    const float Dx = (float)(ci.x - cj.x), Dy = (float)(ci.y - cj.y), Dz = (float)(ci.z - cj.z);
+    // centroid difference formed in FP64 and kept as hi + lo floats, so that
+    // each point offset e = D_hi + (x_a + D_lo) is one rounding of D + x_a.
+    // Rounding D alone would give every pair with the same D the same error;
+    // on lattice-like meshes (boxes) such errors share their sign and would
+    // shift the capacity by up to 1e-8.
+    const double dX = ci.x - cj.x, dY = ci.y - cj.y, dZ = ci.z - cj.z;
+    const float Dx = (float)dX, Dy = (float)dY, Dz = (float)dZ;
+    const float Lx = (float)(dX - (double)Dx), Ly = (float)(dY - (double)Dy), Lz = (float)(dZ - (double)Dz);
     const float4 *ua = qpA + (size_t)i * kQMax;
     float acc = 0.f;
 #pragma unroll 2
     for (int a = 0; a < Q; ++a) {
       const float4 p = ua[a];
-      const float ex = Dx + p.x, ey = Dy + p.y, ez = Dz + p.z;
+      const float ex = Dx + (p.x + Lx), ey = Dy + (p.y + Ly), ez = Dz + (p.z + Lz);
       const float ne = -(ex * ex + ey * ey + ez * ez);
       const float tx = 2.0f * ex, ty = 2.0f * ey, tz = 2.0f * ez;
       float s = 0.f;
