@@ -21,7 +21,10 @@ path computes:
 * the discrete capacity Cap = (1/4 pi) sum_i x_i |T_i| (eq. "cap:ell" and
   the proof of the capacity proposition);
 * ZZ-type indicators for the primal P0 solution (eq. "zz:T", Section 2.4)
-  and Doerfler marking (eq. "doerfler").
+  and Doerfler marking (eq. "doerfler");
+* the dual-mesh system of the paper's Algorithm 1 (``dual``): barycentric
+  V, the projections P and Q_m, the hypersingular matrix, the mass matrix,
+  the direct dual solve, its capacity and ZZ indicators (Section 2.6).
 
 Parity pins are in tests/test_oracle_*.py.  Functions without an independent
 pin say "parity unpinned" in their docstring.
@@ -47,3 +50,4 @@ from .capacity import (  # noqa: F401
     doerfler,
     mesh_check,
 )
+from . import dual  # noqa: F401

@@ -4,7 +4,8 @@ This package builds triangulated polyhedral surfaces (the input of the
 capacity problem, Section 2.1 of the paper: conforming triangulations of a
 closed polyhedral boundary into plane triangles), refines them with newest
 vertex bisection (Fig. "nvb", Algorithm step (iv)) and draws seeded request
-streams.  It contains none of the method's arithmetic (no quadrature, no
+streams, and builds the barycentric refinement of a mesh (the common
+refinement of the mesh and its dual, Section 2.1).  It contains none of the method's arithmetic (no quadrature, no
 integral operator, no solver), so both sides can use it without sharing any
 computation.
 """
@@ -26,3 +27,4 @@ from .nvb import (  # noqa: F401
     refine_uniform,
 )
 from .requests import Request, request_stream  # noqa: F401
+from .dual import SON_VERTEX, barycentric, vertex_incidence  # noqa: F401
