@@ -266,6 +266,90 @@ int32_t bc_zz_indicators(const int32_t *d_tris, int64_t N,
                          int64_t nnz, const double *d_sigma, int32_t h_mode,
                          double *d_eta2, bc_stream stream);
 
+/* ------------------------------------------------------------------------ */
+/* Standalone product with a stored matrix                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Device scratch for bc_matvec (x padded to the leading dimension, partial
+ * sums of the symmetric product, about 2% of the FP32 matrix). */
+size_t bc_matvec_workspace_bytes(int64_t N, int32_t precision);
+
+/* y = V x for a matrix from bc_assemble (row-major N x bc_matrix_ld(N); only
+ * the diagonal 128 x 128 blocks and the entries right of them are read,
+ * V being symmetric).  BC_FP64: V, x, y are FP64; BC_MIXED: FP32 (products
+ * accumulated in FP32).  Fixed summation order: the result depends on N
+ * only.  d_x and d_y have N entries and must not overlap.  ASYNC. */
+int32_t bc_matvec(const void *d_V, int64_t N, int32_t precision,
+                  const void *d_x, void *d_y, void *d_ws, size_t ws_bytes,
+                  bc_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Dual-mesh system with operator preconditioning (Algorithm 1, step (i);   */
+/* Section 2.6, eq. "laplace_precond_discrete")                             */
+/* ------------------------------------------------------------------------ */
+
+/* The unknowns are the coefficients x_j of the dual-cell indicators, one per
+ * vertex of the primal mesh (N triangles, M vertices).  The caller assembles
+ * V_bary (FP64, bc_prepare + bc_assemble) on the barycentric refinement whose
+ * son 6t + s of triangle t = (v0, v1, v2) is, in this order,
+ * (v0, m01, c), (m01, v1, c), (v1, m12, c), (m12, v2, c), (v2, m20, c),
+ * (m20, v0, c)   (c the centre of gravity, m the edge midpoints),
+ * and passes the vertex-to-triangle incidence of the primal mesh as CSR:
+ * d_iptr[M + 1], and for each entry the triangle d_itri[] and the vertex's
+ * corner 0..2 in it d_icor[], triangles in increasing order per vertex. */
+typedef struct {
+  double rtol;           /* stop when the preconditioned residual of GMRES
+                            has dropped by rtol, e.g. 1e-12 */
+  int32_t max_iter;      /* GMRES steps, <= restart */
+  int32_t restart;       /* Krylov basis size the workspace was sized for */
+  int32_t jacobi_sweeps; /* sweeps approximating M^{-1} (a fixed linear
+                            operator; the solution does not depend on it) */
+  int32_t reserved;      /* must be 0 */
+} bc_dual_opts;
+
+typedef struct {
+  double cap;            /* (1/4pi) sum_j x_j |T_j^dual|   (eq. "cap:ell") */
+  double rel_residual;   /* last preconditioned relative residual */
+  int32_t iters;         /* GMRES steps (four products with V_bary each) */
+  int32_t status;        /* BC_OK or BC_ENOCONV */
+} bc_dual_result;
+
+/* Device scratch for the dual system: per-triangle geometry and curls,
+ * dual areas, mass matrix diagonal, the Krylov basis (restart + 1 vectors of
+ * length M), four vectors on the barycentric mesh and the product's
+ * scratch. */
+size_t bc_dual_workspace_bytes(int64_t N, int64_t M, int32_t restart);
+
+/* Per triangle: area, diameter, surface curls of the hat functions
+ * curl_G phi_a = (P_{a+1} - P_{a+2}) / (2|T|); per vertex: the dual area
+ * |T_j^dual| = <phi_j, 1> = sum |T|/3 and the mass matrix diagonal
+ * sum 11|T|/54.  d_verts: M x 3 FP64; d_tris: N x 3 int32.  ASYNC. */
+int32_t bc_dual_setup(const double *d_verts, int64_t M, const int32_t *d_tris,
+                      int64_t N, const int32_t *d_iptr, const int32_t *d_itri,
+                      void *d_ws, size_t ws_bytes, int32_t restart,
+                      bc_stream stream);
+
+/* Preconditioned GMRES for V_dual x = f (V_dual = P^T V_bary P, f_j =
+ * |T_j^dual|) with the hypersingular operator D_reg = sum_m Q_m^T V_bary Q_m
+ * + a a^T as right and the inverse mass matrix as left preconditioner
+ * (Section 2.6).  Writes x (M entries, FP64) to d_x and the capacity,
+ * iteration count and status to *h_result.  Host-driven: SYNCHRONOUS (waits
+ * for `stream` once per Gram-Schmidt pass).  Errors: BC_EINVAL for bad
+ * options or sizes, BC_ENOMEM for a short workspace. */
+int32_t bc_dual_solve(const double *d_Vbary, const int32_t *d_tris, int64_t N,
+                      int64_t M, const int32_t *d_iptr, const int32_t *d_itri,
+                      const int32_t *d_icor, void *d_ws, size_t ws_bytes,
+                      const bc_dual_opts *opts, double *d_x,
+                      bc_dual_result *h_result, bc_stream stream);
+
+/* eta(T)^2 = h_T ||Phi - I Phi||^2_{L2(T)} (eq. "zz:T") for the dual
+ * solution Phi = sum_j x_j chi_j^dual, I Phi = sum_j x_j phi_j, in closed
+ * form on the six barycentric sons of each triangle.  h_mode 0: diam(T);
+ * 1: |T|^(1/2).  Needs bc_dual_setup's workspace.  d_eta2: N FP64.  ASYNC. */
+int32_t bc_dual_zz(const void *d_ws, size_t ws_bytes, const int32_t *d_tris,
+                   int64_t N, int64_t M, int32_t restart, const double *d_x,
+                   int32_t h_mode, double *d_eta2, bc_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

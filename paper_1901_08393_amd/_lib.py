@@ -54,6 +54,15 @@ class bc_system(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class bc_dual_opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("restart", C.c_int32),
+                ("jacobi_sweeps", C.c_int32), ("reserved", C.c_int32)]
+
+
+class bc_dual_result(C.Structure):
+    _fields_ = [("cap", C.c_double), ("rel_residual", C.c_double), ("iters", C.c_int32), ("status", C.c_int32)]
+
+
 P = C.c_void_p
 I32 = C.c_int32
 I64 = C.c_int64
@@ -80,6 +89,12 @@ SIGNATURES = {
     "bc_solve_capacity": (I32, [I32]),
     "bc_capacity": (I32, [P, P, I64, P, P]),
     "bc_zz_indicators": (I32, [P, I64, P, P, I64, P, I32, P, P]),
+    "bc_matvec_workspace_bytes": (SZ, [I64, I32]),
+    "bc_matvec": (I32, [P, I64, I32, P, P, P, SZ, P]),
+    "bc_dual_workspace_bytes": (SZ, [I64, I64, I32]),
+    "bc_dual_setup": (I32, [P, I64, P, I64, P, P, P, SZ, I32, P]),
+    "bc_dual_solve": (I32, [P, P, I64, I64, P, P, P, P, SZ, C.POINTER(bc_dual_opts), P, C.POINTER(bc_dual_result), P]),
+    "bc_dual_zz": (I32, [P, SZ, P, I64, I64, I32, P, I32, P, P]),
 }
 
 _LIB = None

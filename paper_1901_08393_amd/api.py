@@ -209,6 +209,90 @@ class CapacityProblem:
         self.solve_ws = None
 
 
+def matvec(problem: "CapacityProblem", x: torch.Tensor, stream=None) -> torch.Tensor:
+    """y = V x with the problem's assembled matrix (bc_matvec): the symmetric
+    product of the solver as a standalone call.  x has N entries in the
+    matrix precision."""
+    L = lib()
+    ws = torch.empty(L.bc_matvec_workspace_bytes(problem.N, problem.prec), dtype=torch.uint8, device=problem.device)
+    y = torch.empty(problem.N, dtype=problem.matrix_dtype, device=problem.device)
+    check("bc_matvec", L.bc_matvec(_ptr(problem.V), problem.N, problem.prec, _ptr(x), _ptr(y), _ptr(ws), ws.numel(),
+                                   _stream(stream)))
+    return y
+
+
+@dataclasses.dataclass
+class DualResult:
+    cap: float
+    rel_residual: float
+    iters: int
+    status: int
+
+    @property
+    def ok(self) -> bool:
+        return self.status == _lib.BC_OK
+
+
+class DualProblem:
+    """The paper's dual-mesh Galerkin system (Algorithm 1, step (i)): V on
+    the barycentric refinement (FP64, assembled by the library like any
+    mesh), the unknowns on the dual cells of the vertices, solved by GMRES
+    with the hypersingular operator as preconditioner (Section 2.6)."""
+
+    def __init__(self, verts, tris, far_order: int = 4, ss_order: int = 4, restart: int = 200, device: str = "cuda",
+                 stream=None):
+        import synth
+
+        L = lib()
+        verts = np.ascontiguousarray(verts, dtype=np.float64)
+        tris = np.ascontiguousarray(tris, dtype=np.int32)
+        st, bad = mesh_check(verts, tris)
+        if st != _lib.BC_OK:
+            raise _lib.BemcapError(f"bc_mesh_check (index {bad})", st)
+        self.N, self.M = int(tris.shape[0]), int(verts.shape[0])
+        self.restart = int(restart)
+        self.device = torch.device(device)
+        bary, _, _ = synth.barycentric(verts, tris)
+        self.bary = CapacityProblem(bary.verts, bary.tris, "fp64", far_order, ss_order, device=device, validate=False,
+                                    stream=stream)
+        iptr, itri, icor = synth.vertex_incidence(tris, self.M)
+        self.d_verts = torch.from_numpy(verts).to(self.device)
+        self.d_tris = torch.from_numpy(tris).to(self.device)
+        self.d_iptr = torch.from_numpy(iptr).to(self.device)
+        self.d_itri = torch.from_numpy(itri).to(self.device)
+        self.d_icor = torch.from_numpy(icor).to(self.device)
+        nb = L.bc_dual_workspace_bytes(self.N, self.M, self.restart)
+        if nb == 0:
+            raise ValueError("mesh too large or too small for the dual system")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        check("bc_dual_setup", L.bc_dual_setup(_ptr(self.d_verts), self.M, _ptr(self.d_tris), self.N,
+                                               _ptr(self.d_iptr), _ptr(self.d_itri), _ptr(self.ws), self.ws.numel(),
+                                               self.restart, _stream(stream)))
+        self.x = torch.zeros(self.M, dtype=torch.float64, device=self.device)
+
+    def assemble(self, stream=None) -> torch.Tensor:
+        """V_bary (6N x 6N, FP64)."""
+        return self.bary.assemble(stream)
+
+    def solve(self, rtol: float = 1e-12, max_iter: Optional[int] = None, jacobi_sweeps: int = 30,
+              stream=None) -> DualResult:
+        if self.bary.V is None:
+            raise RuntimeError("assemble() first")
+        o = _lib.bc_dual_opts(rtol, int(max_iter or self.restart), self.restart, jacobi_sweeps, 0)
+        r = _lib.bc_dual_result()
+        check("bc_dual_solve", lib().bc_dual_solve(_ptr(self.bary.V), _ptr(self.d_tris), self.N, self.M,
+                                                   _ptr(self.d_iptr), _ptr(self.d_itri), _ptr(self.d_icor),
+                                                   _ptr(self.ws), self.ws.numel(), C.byref(o), _ptr(self.x),
+                                                   C.byref(r), _stream(stream)))
+        return DualResult(r.cap, r.rel_residual, r.iters, r.status)
+
+    def zz(self, h_mode: int = 0, stream=None) -> torch.Tensor:
+        eta2 = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        check("bc_dual_zz", lib().bc_dual_zz(_ptr(self.ws), self.ws.numel(), _ptr(self.d_tris), self.N, self.M,
+                                             self.restart, _ptr(self.x), h_mode, _ptr(eta2), _stream(stream)))
+        return eta2
+
+
 def solve_batched(problems, precision: str, iter_budget: int = 0, start=None, budgets=None, stream=None,
                   **opts):
     """One persistent launch over several assembled problems (same precision).

@@ -319,4 +319,55 @@ int32_t bc_zz_indicators(const int32_t *d_tris, int64_t N, const void *d_mesh_ws
   return launch_zz(d_tris, N, d_mesh_ws, d_pattern, nnz, d_sigma, h_mode, d_eta2, static_cast<hipStream_t>(stream));
 }
 
+size_t bc_matvec_workspace_bytes(int64_t N, int32_t precision) {
+  if (!n_ok(N) || (precision != BC_FP64 && precision != BC_MIXED)) return 0;
+  return MatvecLayout(N, precision).total;
+}
+
+int32_t bc_matvec(const void *d_V, int64_t N, int32_t precision, const void *d_x, void *d_y, void *d_ws,
+                  size_t ws_bytes, bc_stream stream) {
+  if (!d_V || !d_x || !d_y || !d_ws || !n_ok(N) || (precision != BC_FP64 && precision != BC_MIXED)) return BC_EINVAL;
+  if (N > (int64_t)kMaxBand * solve_workgroups(N)) return BC_EINVAL;
+  if (ws_bytes < MatvecLayout(N, precision).total) return BC_ENOMEM;
+  return launch_matvec(precision, d_V, N, d_x, d_y, d_ws, static_cast<hipStream_t>(stream));
+}
+
+static bool dual_sizes_ok(int64_t N, int64_t M, int32_t restart) {
+  return n_ok(N) && M >= 4 && M <= 3 * N && restart >= 1 && restart <= 1000 && 6 * N <= (int64_t)1 << 20 &&
+         6 * N <= (int64_t)kMaxBand * solve_workgroups(6 * N);
+}
+
+size_t bc_dual_workspace_bytes(int64_t N, int64_t M, int32_t restart) {
+  if (!dual_sizes_ok(N, M, restart)) return 0;
+  return DualLayout(N, M, restart).total;
+}
+
+int32_t bc_dual_setup(const double *d_verts, int64_t M, const int32_t *d_tris, int64_t N, const int32_t *d_iptr,
+                      const int32_t *d_itri, void *d_ws, size_t ws_bytes, int32_t restart, bc_stream stream) {
+  if (!d_verts || !d_tris || !d_iptr || !d_itri || !d_ws || !dual_sizes_ok(N, M, restart)) return BC_EINVAL;
+  if (ws_bytes < DualLayout(N, M, restart).total) return BC_ENOMEM;
+  return launch_dual_setup(d_verts, d_tris, N, M, d_iptr, d_itri, d_ws, restart, static_cast<hipStream_t>(stream));
+}
+
+int32_t bc_dual_solve(const double *d_Vbary, const int32_t *d_tris, int64_t N, int64_t M, const int32_t *d_iptr,
+                      const int32_t *d_itri, const int32_t *d_icor, void *d_ws, size_t ws_bytes,
+                      const bc_dual_opts *opts, double *d_x, bc_dual_result *h_result, bc_stream stream) {
+  if (!d_Vbary || !d_tris || !d_iptr || !d_itri || !d_icor || !d_ws || !opts || !d_x || !h_result) return BC_EINVAL;
+  if (!dual_sizes_ok(N, M, opts->restart)) return BC_EINVAL;
+  if (!(opts->rtol > 0.0) || !std::isfinite(opts->rtol) || opts->max_iter < 1 || opts->max_iter > opts->restart ||
+      opts->jacobi_sweeps < 0 || opts->jacobi_sweeps > 1000 || opts->reserved != 0)
+    return BC_EINVAL;
+  if (ws_bytes < DualLayout(N, M, opts->restart).total) return BC_ENOMEM;
+  return run_dual_solve(d_Vbary, d_tris, N, M, d_iptr, d_itri, d_icor, d_ws, *opts, d_x, h_result,
+                        static_cast<hipStream_t>(stream));
+}
+
+int32_t bc_dual_zz(const void *d_ws, size_t ws_bytes, const int32_t *d_tris, int64_t N, int64_t M, int32_t restart,
+                   const double *d_x, int32_t h_mode, double *d_eta2, bc_stream stream) {
+  if (!d_ws || !d_tris || !d_x || !d_eta2 || !dual_sizes_ok(N, M, restart) || (h_mode != 0 && h_mode != 1))
+    return BC_EINVAL;
+  if (ws_bytes < DualLayout(N, M, restart).total) return BC_ENOMEM;
+  return launch_dual_zz(d_ws, d_tris, N, M, restart, d_x, h_mode, d_eta2, static_cast<hipStream_t>(stream));
+}
+
 }  // extern "C"

@@ -159,6 +159,37 @@ struct SolveLayout {
   }
 };
 
+// Workspace of a standalone product y = V x (bc_matvec): x padded to ld
+// with zeros, then the partial sums of the symmetric product.
+struct MatvecLayout {
+  size_t xpad, rpart, cpart, total;
+  int64_t ld, nB, T;
+  int k;
+  __host__ __device__ MatvecLayout(int64_t N, int32_t precision) {
+    ld = (N + 63) / 64 * 64;
+    k = precision == BC_FP64 ? 2 : 4;
+    nB = (N + kRB - 1) / kRB;
+    T = half_units_before(nB, ld / 64, k);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+      size_t r = o;
+      o = (o + bytes + 255) & ~size_t(255);
+      return r;
+    };
+    xpad = take(sizeof(double) * (size_t)ld);
+    rpart = take(sizeof(double) * kRB * (size_t)T);
+    cpart = take(sizeof(double) * (size_t)ld * (size_t)nB);
+    total = o;
+  }
+};
+
+// Workspace of the dual-mesh system (bc_dual_*).
+struct DualLayout {
+  size_t area, diam, curl, f, mdiag, basis, w, t1, t2, t3, xt, bvec, yvec, dots, mv, total;
+  int64_t nb;
+  DualLayout(int64_t N, int64_t M, int32_t restart);
+};
+
 // Per-system control block at the start of the solver workspace.  Written
 // only by workgroup 0 of the system (state save) and by the barrier.
 struct SolveCtl {
@@ -309,6 +340,13 @@ int launch_capacity(const double *sigma, const double *area, int64_t N, double *
 int launch_solve(int32_t precision, const SysDesc *d_desc, int n_sys, int total_wg, const SolveParams &p,
                  hipStream_t s);
 int solve_capacity(int32_t precision);
+int launch_matvec(int32_t precision, const void *V, int64_t N, const void *x, void *y, void *ws, hipStream_t s);
+int launch_dual_setup(const double *verts, const int32_t *tris, int64_t N, int64_t M, const int32_t *iptr,
+                      const int32_t *itri, void *ws, int32_t restart, hipStream_t s);
+int run_dual_solve(const void *Vb, const int32_t *tris, int64_t N, int64_t M, const int32_t *iptr, const int32_t *itri,
+                   const int32_t *icor, void *ws, const bc_dual_opts &o, double *x, bc_dual_result *res, hipStream_t s);
+int launch_dual_zz(const void *ws, const int32_t *tris, int64_t N, int64_t M, int32_t restart, const double *x,
+                   int h_mode, double *eta2, hipStream_t s);
 int solve_workgroups(int64_t N);
 int launch_set_desc(const SysDesc *h, int n, SysDesc *d, hipStream_t s);
 void gauss_legendre01(int n, double *x, double *w);

@@ -1,0 +1,430 @@
+// Dual-mesh Galerkin system with operator preconditioning (the paper's
+// Algorithm 1, step (i); Section 2.6, eq. "laplace_precond_discrete").
+//
+// The unknowns are the coefficients x_j of the dual-cell indicators
+// chi_j^dual, one per vertex of the primal mesh (N triangles, M vertices).
+// Everything is expressed through V_bary, the P0 Galerkin matrix of the
+// single-layer operator on the barycentric refinement (6N triangles; son
+// 6t + s of triangle t lies in the dual cell of its vertex SON_VERTEX[s]):
+//
+//   V_dual = P^T V_bary P,                    (P x)_k = x_{owner(k)}
+//   D      = sum_m Q_m^T V_bary Q_m,          (Q_m x)_k = (curl_G sum_j x_j phi_j)_m on son k
+//   D_reg  = D + a a^T,                       a_j = <phi_j, 1>
+//   M[i][j] = <phi_j, chi_i^dual>             (11|T|/54 on the diagonal, 7|T|/108 off it, per triangle)
+//
+// GMRES solves  M^{-1} V_dual M^{-1} D_reg  x~ = M^{-1} f  (M is symmetric),
+// and x = M^{-1} D_reg x~ solves V_dual x = f, f_j = |T_j^dual|.  M^{-1} is
+// applied as a fixed number of Jacobi sweeps: a fixed linear operator, used
+// the same way on both sides, so the solution is exact whatever the sweep
+// count; the count only sets the quality of the preconditioner.  Each GMRES
+// step makes four products with V_bary (three curl components, one dual
+// indicator).  Every reduction has a fixed order.
+#include <cmath>
+#include <vector>
+
+#include "bc_internal.h"
+
+namespace bc {
+
+namespace {
+
+constexpr int kSonVertex[6] = {0, 1, 1, 2, 2, 0};
+
+// per corner a of a triangle, its two sons (the dual cell of that vertex)
+__device__ __forceinline__ void sons_of_corner(int a, int &s1, int &s2) {
+  s1 = a == 0 ? 0 : (a == 1 ? 1 : 3);
+  s2 = a == 0 ? 5 : (a == 1 ? 2 : 4);
+}
+
+// Per triangle: area, diameter and the surface curls of its three hat
+// functions, curl_G phi_a = (P_{a+1} - P_{a+2}) / (2 |T|).
+__global__ void k_dual_geometry(const double *__restrict__ verts, const int32_t *__restrict__ tris, int N,
+                                double *__restrict__ area, double *__restrict__ diam, double *__restrict__ curl) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  double P[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) P[a][c] = verts[3 * tris[3 * t + a] + c];
+  const double e1[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
+  const double e2[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
+  const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+  const double A2 = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  area[t] = 0.5 * A2;
+  double d2 = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    double l2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      curl[9 * t + 3 * a + k] = (P[b][k] - P[c][k]) / A2;
+      l2 += (P[b][k] - P[a][k]) * (P[b][k] - P[a][k]);
+    }
+    d2 = fmax(d2, l2);
+  }
+  diam[t] = sqrt(d2);
+}
+
+// Per vertex: f_j = |T_j^dual| = sum_{T ni j} |T|/3 (also a_j = <phi_j, 1>)
+// and the mass matrix diagonal sum_{T ni j} 11|T|/54, in incidence order.
+__global__ void k_dual_vertex(const int32_t *__restrict__ iptr, const int32_t *__restrict__ itri, int M,
+                              const double *__restrict__ area, double *__restrict__ f, double *__restrict__ mdiag) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  double s = 0.0;
+  for (int e = iptr[j]; e < iptr[j + 1]; ++e) s += area[itri[e]];
+  f[j] = s / 3.0;
+  mdiag[j] = s * (11.0 / 54.0);
+}
+
+// out_k = x_{owner(k)} for the 6N sons
+__global__ void k_dual_P(const double *__restrict__ x, const int32_t *__restrict__ tris, int N,
+                         double *__restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 6 * N) return;
+  const int t = k / 6, s = k - 6 * t;
+  const int sv = s == 0 || s == 5 ? 0 : (s <= 2 ? 1 : 2);
+  out[k] = x[tris[3 * t + sv]];
+}
+
+// out[m][k] = sum_a curl[t][a][m] x_{tris[t][a]} for the sons k of t
+__global__ void k_dual_Q(const double *__restrict__ x, const int32_t *__restrict__ tris,
+                         const double *__restrict__ curl, int N, int64_t nb, double *__restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 6 * N) return;
+  const int t = k / 6;
+  const double x0 = x[tris[3 * t]], x1 = x[tris[3 * t + 1]], x2 = x[tris[3 * t + 2]];
+  for (int m = 0; m < 3; ++m) {
+    const double v = curl[9 * t + m] * x0 + curl[9 * t + 3 + m] * x1 + curl[9 * t + 6 + m] * x2;
+    out[m * nb + k] = v;
+  }
+}
+
+// out_j = sum over the triangles around j (incidence order) of the two sons
+// in j's dual cell: (P^T y)_j
+__global__ void k_dual_PT(const double *__restrict__ y, const int32_t *__restrict__ iptr,
+                          const int32_t *__restrict__ itri, const int32_t *__restrict__ icor, int M,
+                          double *__restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  double s = 0.0;
+  for (int e = iptr[j]; e < iptr[j + 1]; ++e) {
+    int s1, s2;
+    sons_of_corner(icor[e], s1, s2);
+    const int t = itri[e];
+    s += y[6 * t + s1] + y[6 * t + s2];
+  }
+  out[j] = s;
+}
+
+// out_j = sum_m (Q_m^T y_m)_j + a_j (a^T u), with (a^T u) read from *au
+__global__ void k_dual_QT(const double *__restrict__ y, int64_t nb, const int32_t *__restrict__ iptr,
+                          const int32_t *__restrict__ itri, const int32_t *__restrict__ icor,
+                          const double *__restrict__ curl, const double *__restrict__ a, const double *__restrict__ au,
+                          int M, double *__restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  double s = 0.0;
+  for (int e = iptr[j]; e < iptr[j + 1]; ++e) {
+    const int t = itri[e], c = icor[e];
+    for (int m = 0; m < 3; ++m) {
+      const double *ym = y + m * nb + 6 * t;
+      const double sum6 = ((ym[0] + ym[1]) + (ym[2] + ym[3])) + (ym[4] + ym[5]);
+      s = fma(curl[9 * t + 3 * c + m], sum6, s);
+    }
+  }
+  out[j] = fma(a[j], *au, s);
+}
+
+// One Jacobi sweep for M z = r: zout = zin + (r - M zin) / diag(M), with
+// (M z)_i = sum_{T ni i} |T| (11/54 z_i + 7/108 (z_b + z_c)).
+__global__ void k_dual_jacobi(const double *__restrict__ r, const double *__restrict__ zin,
+                              const int32_t *__restrict__ iptr, const int32_t *__restrict__ itri,
+                              const int32_t *__restrict__ icor, const int32_t *__restrict__ tris,
+                              const double *__restrict__ area, const double *__restrict__ mdiag, int M,
+                              double *__restrict__ zout) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const double zi = zin[i];
+  double mz = 0.0;
+  for (int e = iptr[i]; e < iptr[i + 1]; ++e) {
+    const int t = itri[e], c = icor[e];
+    const double zb = zin[tris[3 * t + (c + 1) % 3]], zc = zin[tris[3 * t + (c + 2) % 3]];
+    mz = fma(area[t], (11.0 / 54.0) * zi + (7.0 / 108.0) * (zb + zc), mz);
+  }
+  zout[i] = zi + (r[i] - mz) / mdiag[i];
+}
+
+__global__ void k_dual_div(const double *__restrict__ r, const double *__restrict__ d, int M, double *__restrict__ z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < M) z[i] = r[i] / d[i];
+}
+
+// out[q] = sum_i A[q][i] w_i for q < nq (rows of A at stride lda): one
+// workgroup per q, fixed order (strided per thread, then a tree in LDS).
+__global__ __launch_bounds__(kWG) void k_multidot(const double *__restrict__ A, int64_t lda, const double *__restrict__ w,
+                                                  int M, double *__restrict__ out) {
+  __shared__ double part[kWG];
+  const int q = blockIdx.x;
+  const double *aq = A + q * lda;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < M; i += kWG) s = fma(aq[i], w[i], s);
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = kWG / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[q] = part[0];
+}
+
+// w_i -= sum_{q < nq} h_q A[q][i] (q ascending)
+__global__ void k_gs_update(const double *__restrict__ A, int64_t lda, const double *__restrict__ h, int nq, int M,
+                            double *__restrict__ w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  double s = w[i];
+  for (int q = 0; q < nq; ++q) s = fma(-h[q], A[q * lda + i], s);
+  w[i] = s;
+}
+
+// out_i = alpha * in_i
+__global__ void k_scale(const double *__restrict__ in, double alpha, int M, double *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < M) out[i] = alpha * in[i];
+}
+
+// out_i = sum_q c_q A[q][i] (q ascending)
+__global__ void k_combine(const double *__restrict__ A, int64_t lda, const double *__restrict__ c, int nq, int M,
+                          double *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  double s = 0.0;
+  for (int q = 0; q < nq; ++q) s = fma(c[q], A[q * lda + i], s);
+  out[i] = s;
+}
+
+// eta_T^2 = h_T || Phi - I Phi ||^2_{L2(T)} (eq. "zz:T"): on each son the
+// difference is affine with values g at the son's vertices, and
+// int g^2 = |son| / 12 ((sum g)^2 + sum g^2).  Son (v_a, m_ab, c) of the
+// cell of a: g = (0, (x_a - x_b)/2, x_a - mean); son (m_ca, v_a, c):
+// g = ((x_a - x_c)/2, 0, x_a - mean); |son| = |T| / 6.
+__global__ void k_dual_zz(const double *__restrict__ x, const int32_t *__restrict__ tris,
+                          const double *__restrict__ area, const double *__restrict__ diam, int N, int h_mode,
+                          double *__restrict__ eta2) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const double v[3] = {x[tris[3 * t]], x[tris[3 * t + 1]], x[tris[3 * t + 2]]};
+  const double mean = (v[0] + v[1] + v[2]) / 3.0;
+  double s = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    const double gc = v[a] - mean;
+    const double g1 = 0.5 * (v[a] - v[b]), g2 = 0.5 * (v[a] - v[c]);
+    // son towards b: (0, g1, gc); son towards c: (g2, 0, gc)
+    const double s1 = g1 + gc, s2 = g2 + gc;
+    s += (s1 * s1 + g1 * g1 + gc * gc) + (s2 * s2 + g2 * g2 + gc * gc);
+  }
+  const double h = h_mode == 0 ? diam[t] : sqrt(area[t]);
+  eta2[t] = h * (area[t] / 6.0) / 12.0 * s;
+}
+
+inline int blocks(int64_t n) { return (int)((n + kWG - 1) / kWG); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- layout
+DualLayout::DualLayout(int64_t N, int64_t M, int32_t restart) {
+  nb = 6 * N;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = (o + bytes + 255) & ~size_t(255);
+    return r;
+  };
+  area = take(8 * N);
+  diam = take(8 * N);
+  curl = take(8 * 9 * N);
+  f = take(8 * M);
+  mdiag = take(8 * M);
+  basis = take(8 * (size_t)(restart + 1) * M);
+  w = take(8 * M);
+  t1 = take(8 * M);
+  t2 = take(8 * M);
+  t3 = take(8 * M);
+  xt = take(8 * M);
+  bvec = take(8 * 4 * (size_t)nb);  // three curl components and the dual indicator
+  yvec = take(8 * 4 * (size_t)nb);
+  dots = take(8 * (size_t)(restart + 8));
+  mv = take(MatvecLayout(nb, BC_FP64).total);
+  total = o;
+}
+
+int launch_dual_setup(const double *verts, const int32_t *tris, int64_t N, int64_t M, const int32_t *iptr,
+                      const int32_t *itri, void *ws, int32_t restart, hipStream_t s) {
+  const DualLayout L(N, M, restart);
+  char *b = static_cast<char *>(ws);
+  double *area = reinterpret_cast<double *>(b + L.area), *diam = reinterpret_cast<double *>(b + L.diam);
+  hipLaunchKernelGGL(k_dual_geometry, dim3(blocks(N)), dim3(kWG), 0, s, verts, tris, (int)N, area, diam,
+                     reinterpret_cast<double *>(b + L.curl));
+  hipLaunchKernelGGL(k_dual_vertex, dim3(blocks(M)), dim3(kWG), 0, s, iptr, itri, (int)M, (const double *)area,
+                     reinterpret_cast<double *>(b + L.f), reinterpret_cast<double *>(b + L.mdiag));
+  return hipGetLastError() == hipSuccess ? BC_OK : BC_EDEVICE;
+}
+
+// Host-driven GMRES (no restart within max_iter <= restart): Arnoldi with
+// classical Gram-Schmidt applied twice (all inner products of a pass in one
+// launch), Givens rotations on the host.
+int run_dual_solve(const void *Vb, const int32_t *tris, int64_t N, int64_t M, const int32_t *iptr, const int32_t *itri,
+                   const int32_t *icor, void *ws, const bc_dual_opts &o, double *x, bc_dual_result *res, hipStream_t s) {
+  const DualLayout L(N, M, o.restart);
+  char *b = static_cast<char *>(ws);
+  auto D = [&](size_t off) { return reinterpret_cast<double *>(b + off); };
+  const double *area = D(L.area), *diam = D(L.diam), *curl = D(L.curl), *f = D(L.f), *mdiag = D(L.mdiag);
+  (void)diam;
+  double *basis = D(L.basis), *w = D(L.w), *t1 = D(L.t1), *t2 = D(L.t2), *t3 = D(L.t3), *xt = D(L.xt);
+  double *bvec = D(L.bvec), *yvec = D(L.yvec), *dots = D(L.dots);
+  void *mvws = b + L.mv;
+  const int64_t nb = L.nb;
+  const int gM = blocks(M), gB = blocks(nb);
+  bool err = false;
+  auto chk = [&]() { err = err || hipGetLastError() != hipSuccess; };
+  // z = M^{-1} r by o.jacobi_sweeps Jacobi sweeps from z0 = r / diag (ping-pong t2/t3)
+  auto minv = [&](const double *r, double *z) {
+    hipLaunchKernelGGL(k_dual_div, dim3(gM), dim3(kWG), 0, s, r, mdiag, (int)M, t2);
+    double *cur = t2, *nxt = t3;
+    for (int k = 0; k < o.jacobi_sweeps; ++k) {
+      hipLaunchKernelGGL(k_dual_jacobi, dim3(gM), dim3(kWG), 0, s, r, (const double *)cur, iptr, itri, icor, tris,
+                         area, mdiag, (int)M, nxt);
+      double *tmp = cur; cur = nxt; nxt = tmp;
+    }
+    hipLaunchKernelGGL(k_scale, dim3(gM), dim3(kWG), 0, s, (const double *)cur, 1.0, (int)M, z);
+    chk();
+  };
+  // out = D_reg u
+  auto dreg = [&](const double *u, double *out) {
+    hipLaunchKernelGGL(k_dual_Q, dim3(gB), dim3(kWG), 0, s, u, tris, curl, (int)N, nb, bvec);
+    for (int m = 0; m < 3; ++m) {
+      if (launch_matvec(BC_FP64, Vb, nb, bvec + m * nb, yvec + m * nb, mvws, s) != BC_OK) err = true;
+    }
+    hipLaunchKernelGGL(k_multidot, dim3(1), dim3(kWG), 0, s, f, (int64_t)0, u, (int)M, dots + o.restart + 4);
+    hipLaunchKernelGGL(k_dual_QT, dim3(gM), dim3(kWG), 0, s, (const double *)yvec, nb, iptr, itri, icor, curl, f,
+                       (const double *)(dots + o.restart + 4), (int)M, out);
+    chk();
+  };
+  // out = M^{-1} P^T V P u  (u already M^{-1}-applied by the caller)
+  auto vdual = [&](const double *u, double *out) {
+    hipLaunchKernelGGL(k_dual_P, dim3(gB), dim3(kWG), 0, s, u, tris, (int)N, bvec + 3 * nb);
+    if (launch_matvec(BC_FP64, Vb, nb, bvec + 3 * nb, yvec + 3 * nb, mvws, s) != BC_OK) err = true;
+    hipLaunchKernelGGL(k_dual_PT, dim3(gM), dim3(kWG), 0, s, (const double *)(yvec + 3 * nb), iptr, itri, icor,
+                       (int)M, t1);
+    minv(t1, out);
+  };
+  // out = M^{-1} V_dual M^{-1} D_reg u
+  auto op = [&](const double *u, double *out) {
+    dreg(u, t1);
+    minv(t1, w);
+    vdual(w, out);
+  };
+  auto host_dots = [&](int n, std::vector<double> &h) {
+    h.resize(n);
+    if (hipMemcpyAsync(h.data(), dots, 8 * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      err = true;
+  };
+  auto put_dots = [&](const std::vector<double> &h) {
+    if (hipMemcpyAsync(dots, h.data(), 8 * h.size(), hipMemcpyHostToDevice, s) != hipSuccess) err = true;
+  };
+
+  const int m = o.max_iter;
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), h;
+  // rhs = M^{-1} f, v0 = rhs / |rhs|
+  minv(f, w);
+  hipLaunchKernelGGL(k_multidot, dim3(1), dim3(kWG), 0, s, (const double *)w, (int64_t)0, (const double *)w, (int)M, dots);
+  host_dots(1, h);
+  if (err) return BC_EDEVICE;
+  const double beta = sqrt(h[0]);
+  if (!(beta > 0.0)) return BC_EINVAL;
+  hipLaunchKernelGGL(k_scale, dim3(gM), dim3(kWG), 0, s, (const double *)w, 1.0 / beta, (int)M, basis);
+  g[0] = beta;
+  int k = 0;
+  double rel = 1.0;
+  int status = BC_ENOCONV;
+  for (; k < m; ++k) {
+    double *vk = basis + (size_t)k * M;
+    op(vk, w);
+    // two passes of classical Gram-Schmidt against v_0 .. v_k
+    std::vector<double> hk(k + 2, 0.0);
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(k_multidot, dim3(k + 1), dim3(kWG), 0, s, (const double *)basis, (int64_t)M,
+                         (const double *)w, (int)M, dots);
+      hipLaunchKernelGGL(k_gs_update, dim3(gM), dim3(kWG), 0, s, (const double *)basis, (int64_t)M,
+                         (const double *)dots, k + 1, (int)M, w);
+      host_dots(k + 1, h);
+      for (int q = 0; q <= k; ++q) hk[q] += h[q];
+    }
+    hipLaunchKernelGGL(k_multidot, dim3(1), dim3(kWG), 0, s, (const double *)w, (int64_t)0, (const double *)w, (int)M,
+                       dots);
+    host_dots(1, h);
+    if (err) return BC_EDEVICE;
+    hk[k + 1] = sqrt(h[0]);
+    // previous rotations, then a new one that zeroes hk[k+1]
+    for (int q = 0; q < k; ++q) {
+      const double a = hk[q], bq = hk[q + 1];
+      hk[q] = cs[q] * a + sn[q] * bq;
+      hk[q + 1] = -sn[q] * a + cs[q] * bq;
+    }
+    const double r = std::hypot(hk[k], hk[k + 1]);
+    cs[k] = r > 0.0 ? hk[k] / r : 1.0;
+    sn[k] = r > 0.0 ? hk[k + 1] / r : 0.0;
+    const double hn = hk[k + 1];
+    hk[k] = r;
+    hk[k + 1] = 0.0;
+    g[k + 1] = -sn[k] * g[k];
+    g[k] = cs[k] * g[k];
+    for (int q = 0; q <= k; ++q) H[(size_t)q * m + k] = hk[q];
+    rel = fabs(g[k + 1]) / beta;
+    if (rel <= o.rtol) {
+      status = BC_OK;
+      ++k;
+      break;
+    }
+    if (!(hn > 0.0)) {  // exact invariant subspace
+      status = BC_OK;
+      ++k;
+      break;
+    }
+    if (k + 1 < m) hipLaunchKernelGGL(k_scale, dim3(gM), dim3(kWG), 0, s, (const double *)w, 1.0 / hn, (int)M,
+                                      basis + (size_t)(k + 1) * M);
+  }
+  // y = H^{-1} g (upper triangular, k x k), x~ = V y, x = M^{-1} D_reg x~
+  std::vector<double> y(k, 0.0);
+  for (int q = k - 1; q >= 0; --q) {
+    double sum = g[q];
+    for (int c = q + 1; c < k; ++c) sum -= H[(size_t)q * m + c] * y[c];
+    y[q] = sum / H[(size_t)q * m + q];
+  }
+  put_dots(y);
+  hipLaunchKernelGGL(k_combine, dim3(gM), dim3(kWG), 0, s, (const double *)basis, (int64_t)M, (const double *)dots, k,
+                     (int)M, xt);
+  dreg(xt, t1);
+  minv(t1, x);
+  // Cap = (1/4pi) f^T x
+  hipLaunchKernelGGL(k_multidot, dim3(1), dim3(kWG), 0, s, f, (int64_t)0, (const double *)x, (int)M, dots);
+  host_dots(1, h);
+  if (err) return BC_EDEVICE;
+  res->cap = h[0] * kInv4Pi;
+  res->rel_residual = rel;
+  res->iters = k;
+  res->status = status;
+  return BC_OK;
+}
+
+int launch_dual_zz(const void *ws, const int32_t *tris, int64_t N, int64_t M, int32_t restart, const double *x,
+                   int h_mode, double *eta2, hipStream_t s) {
+  const DualLayout L(N, M, restart);
+  const char *b = static_cast<const char *>(ws);
+  hipLaunchKernelGGL(k_dual_zz, dim3(blocks(N)), dim3(kWG), 0, s, x, tris, reinterpret_cast<const double *>(b + L.area),
+                     reinterpret_cast<const double *>(b + L.diam), (int)N, h_mode, eta2);
+  return hipGetLastError() == hipSuccess ? BC_OK : BC_EDEVICE;
+}
+
+}  // namespace bc

@@ -727,6 +727,73 @@ int launch_solve(int32_t precision, const SysDesc *d_desc, int n_sys, int total_
   return e == hipSuccess ? BC_OK : BC_EDEVICE;
 }
 
+// ------------------------------------------------- standalone product
+// y = V x with the symmetric product of k_solve, as two launches (the
+// launch boundary takes the place of the system barrier): partial sums, then
+// the gather.  Same partition and order as inside the solver, so the result
+// depends on N only.
+template <typename MT>
+__global__ __launch_bounds__(kSolveWG) void k_matvec_pad(const MT *__restrict__ x, int64_t N, char *ws) {
+  const MatvecLayout Lay(N, sizeof(MT) == 8 ? BC_FP64 : BC_MIXED);
+  MT *xp = reinterpret_cast<MT *>(ws + Lay.xpad);
+  for (int64_t i = (int64_t)blockIdx.x * kSolveWG + threadIdx.x; i < Lay.ld; i += (int64_t)gridDim.x * kSolveWG)
+    xp[i] = i < N ? x[i] : MT(0);
+}
+
+template <typename MT>
+__device__ __forceinline__ HalfPlan matvec_plan(const MatvecLayout &Lay, int64_t N, int G, int rank) {
+  HalfPlan H;
+  H.ld = Lay.ld; H.m64 = Lay.ld / 64; H.T = Lay.T; H.N = (int)N; H.nB = (int)Lay.nB; H.k = Lay.k; H.G = G;
+  H.u0 = Lay.T * rank / G; H.u1 = Lay.T * (rank + 1) / G;
+  return H;
+}
+
+template <typename MT>
+__global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) void k_matvec_part(
+    const MT *__restrict__ V, int64_t N, char *ws) {
+  __shared__ double s_buf[4096];
+  const MatvecLayout Lay(N, sizeof(MT) == 8 ? BC_FP64 : BC_MIXED);
+  const HalfPlan H = matvec_plan<MT>(Lay, N, (int)gridDim.x, (int)blockIdx.x);
+  gptr<char> w = as_global(ws);
+  double unused = 0.0;
+  half_product<MT, MT, MT, false, true>(as_global(V), reinterpret_cast<gptr<const MT>>(w + Lay.xpad), H,
+                                        reinterpret_cast<gptr<MT>>(w + Lay.rpart),
+                                        reinterpret_cast<gptr<MT>>(w + Lay.cpart), reinterpret_cast<MT *>(s_buf),
+                                        unused);
+}
+
+template <typename MT>
+__global__ __launch_bounds__(kSolveWG) void k_matvec_gather(int64_t N, const char *ws, MT *__restrict__ y) {
+  __shared__ double s_part[16 * 64];
+  __shared__ double s_band[kMaxBand];
+  const MatvecLayout Lay(N, sizeof(MT) == 8 ? BC_FP64 : BC_MIXED);
+  const int G = (int)gridDim.x, rank = (int)blockIdx.x;
+  const HalfPlan H = matvec_plan<MT>(Lay, N, G, rank);
+  const int r0 = (int)(N * rank / G), r1 = (int)(N * (rank + 1) / G);
+  gptr<const char> w = as_global(ws);
+  MT *band = reinterpret_cast<MT *>(s_band);
+  half_gather<MT>(H, r0, r1, reinterpret_cast<gptr<const MT>>(w + Lay.rpart),
+                  reinterpret_cast<gptr<const MT>>(w + Lay.cpart), reinterpret_cast<MT *>(s_part), band);
+  for (int i = r0 + (int)threadIdx.x; i < r1; i += kSolveWG) y[i] = band[i - r0];
+}
+
+int launch_matvec(int32_t precision, const void *V, int64_t N, const void *x, void *y, void *ws, hipStream_t s) {
+  const int G = solve_workgroups(N);
+  char *w = static_cast<char *>(ws);
+  if (precision == BC_FP64) {
+    hipLaunchKernelGGL(k_matvec_pad<double>, dim3(16), dim3(kSolveWG), 0, s, static_cast<const double *>(x), N, w);
+    hipLaunchKernelGGL(k_matvec_part<double>, dim3(G), dim3(kSolveWG), 0, s, static_cast<const double *>(V), N, w);
+    hipLaunchKernelGGL(k_matvec_gather<double>, dim3(G), dim3(kSolveWG), 0, s, N, (const char *)w,
+                       static_cast<double *>(y));
+  } else {
+    hipLaunchKernelGGL(k_matvec_pad<float>, dim3(16), dim3(kSolveWG), 0, s, static_cast<const float *>(x), N, w);
+    hipLaunchKernelGGL(k_matvec_part<float>, dim3(G), dim3(kSolveWG), 0, s, static_cast<const float *>(V), N, w);
+    hipLaunchKernelGGL(k_matvec_gather<float>, dim3(G), dim3(kSolveWG), 0, s, N, (const char *)w,
+                       static_cast<float *>(y));
+  }
+  return hipGetLastError() == hipSuccess ? BC_OK : BC_EDEVICE;
+}
+
 // Fixed-order FP64 capacity reduction in one workgroup.
 __global__ __launch_bounds__(kWG) void k_capacity(const double *__restrict__ sigma, const double *__restrict__ area,
                                                   int N, double *cap) {
