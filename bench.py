@@ -247,6 +247,75 @@ def adaptive_mode(a):
                       "monotone": all(caps[k] < caps[k + 1] for k in range(len(caps) - 1))}))
 
 
+CUBE_CAPACITY = 0.66067815409957  # unit cube, the reference value quoted in Section 3.1
+
+DUAL_WORKLOADS = {
+    # name: (mesh, reference capacity or None, description)
+    "cube": ("cube12", CUBE_CAPACITY, "unit cube from 12 triangles, Algorithm 1 dual mode, theta 0.5 "
+                                      "(Section 3.1, Table 1)"),
+    "fichera": ("fichera48", None, "Fichera cube [-1,1]^3 minus [0,1]^3 from 48 triangles, Algorithm 1 dual "
+                                   "mode, theta 0.5 (Section 3.2, Table 2)"),
+}
+
+
+def dual_mode(a):
+    """Algorithm 1 in dual mode on the experiments of Section 3 (Tables 1
+    and 2): theta = 1/2, indicators weighted with |T|^(1/2), GMRES to 1e-10,
+    NVB bisecting each marked element once, until the next mesh would exceed
+    --dual-max-n triangles.  One JSON line per run with the table columns
+    (N, Cap_l, eta_l^2, err_l = |Cap - Cap_l| where a reference value
+    exists, GMRES steps) and the GPU times per step; then the symmetric FP64
+    product on the last V_bary timed on its own, with one and with three
+    vectors (the two passes of a GMRES step)."""
+    import torch
+
+    import synth
+    from paper_1901_08393_amd import api
+    from paper_1901_08393_amd.adaptive import adaptive_dual
+
+    torch.cuda.set_device(0)
+    mesh_name, ref, desc = DUAL_WORKLOADS[a.dual]
+    m = getattr(synth, mesh_name)()
+    t0 = synth.init_reference_edges(m.verts, m.tris)
+    w0 = time.perf_counter()
+    steps = adaptive_dual(m.verts, t0, steps=1000, theta=0.5, h_mode=1, rtol=1e-10, max_elements=a.dual_max_n,
+                          keep=True)
+    wall = time.perf_counter() - w0
+    rows = []
+    for s in steps:
+        row = dict(l=s.level, N=s.N, M=int(s.verts.shape[0]), cap=round(s.cap, 10), eta2=float(f"{s.eta2:.4e}"),
+                   gmres=s.iters, assemble_ms=round(s.t_assemble_ms, 3), solve_ms=round(s.t_solve_ms, 3),
+                   zz_ms=round(s.t_zz_ms, 3), host_ms=round(s.t_refine_ms, 2))
+        if ref is not None:
+            err = abs(ref - s.cap)
+            row.update(err=float(f"{err:.4e}"), ratio=round(err / s.eta2, 4))
+        rows.append(row)
+        log(f"l={s.level} N={s.N} cap={s.cap:.10f} eta2={s.eta2:.3e} gmres={s.iters} "
+            f"asm {s.t_assemble_ms:.1f} ms solve {s.t_solve_ms:.1f} ms")
+    last = steps[-1]
+    p = api.DualProblem(last.verts, last.tris)
+    p.assemble()
+    nb = 6 * last.N
+    mv = {"N_bary": nb}
+    for nr in (1, 3):
+        x = torch.randn((nr, nb) if nr > 1 else (nb,), dtype=torch.float64, device="cuda")
+        for _ in range(2):
+            api.matvec(p.bary, x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            api.matvec(p.bary, x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = half_matrix_bytes(nb, 8) / (ms * 1e-3) / 1e9
+        mv[f"nrhs{nr}"] = {"ms": round(ms, 3), "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 3)}
+    print(json.dumps({"mode": "dual", "workload": desc, "steps": rows, "wall_s": round(wall, 2),
+                      "bary_matvec": mv}))
+
+
 def mixed60k_mode(a):
     """Mixed precision at N >= 60000: a seeded voxel union adapted (ZZ +
     Doerfler + NVB, FP64 path) until N >= 60000; then the FP64 GPU solve as
@@ -310,6 +379,9 @@ def main():
     ap.add_argument("--adaptive-mixed", action="store_true", help="run the adaptive workload in mixed precision")
     ap.add_argument("--mixed60k", action="store_true", help="mixed vs FP64 at N >= 60000")
     ap.add_argument("--target-n", type=int, default=60000)
+    ap.add_argument("--dual", choices=sorted(DUAL_WORKLOADS), default=None,
+                    help="Algorithm 1 in dual mode on the unit cube (Table 1) or the Fichera cube (Table 2)")
+    ap.add_argument("--dual-max-n", type=int, default=12000)
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy first (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -322,6 +394,8 @@ def main():
         return adaptive_mode(a)
     if a.mixed60k:
         return mixed60k_mode(a)
+    if a.dual:
+        return dual_mode(a)
 
     import torch
 

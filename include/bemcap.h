@@ -270,16 +270,19 @@ int32_t bc_zz_indicators(const int32_t *d_tris, int64_t N,
 /* Standalone product with a stored matrix                                  */
 /* ------------------------------------------------------------------------ */
 
-/* Device scratch for bc_matvec (x padded to the leading dimension, partial
- * sums of the symmetric product, about 2% of the FP32 matrix). */
-size_t bc_matvec_workspace_bytes(int64_t N, int32_t precision);
+/* Device scratch for bc_matvec with nrhs vectors (x padded to the leading
+ * dimension, partial sums of the symmetric product: about 2% of the FP32
+ * matrix per vector).  0 for an unsupported combination. */
+size_t bc_matvec_workspace_bytes(int64_t N, int32_t precision, int32_t nrhs);
 
-/* y = V x for a matrix from bc_assemble (row-major N x bc_matrix_ld(N); only
+/* Y = V X for a matrix from bc_assemble (row-major N x bc_matrix_ld(N); only
  * the diagonal 128 x 128 blocks and the entries right of them are read,
- * V being symmetric).  BC_FP64: V, x, y are FP64; BC_MIXED: FP32 (products
- * accumulated in FP32).  Fixed summation order: the result depends on N
- * only.  d_x and d_y have N entries and must not overlap.  ASYNC. */
-int32_t bc_matvec(const void *d_V, int64_t N, int32_t precision,
+ * V being symmetric).  X and Y hold nrhs vectors of N entries one after the
+ * other; all of them share one pass over V.  BC_FP64: V, X, Y are FP64,
+ * nrhs 1 or 3; BC_MIXED: FP32 (products accumulated in FP32), nrhs 1.
+ * Fixed summation order: the result depends on N (and nrhs) only.  d_x and
+ * d_y must not overlap.  BC_EINVAL for other nrhs.  ASYNC. */
+int32_t bc_matvec(const void *d_V, int64_t N, int32_t precision, int32_t nrhs,
                   const void *d_x, void *d_y, void *d_ws, size_t ws_bytes,
                   bc_stream stream);
 

@@ -1,5 +1,6 @@
 """Adaptive loop solve -> estimate -> mark -> refine (Algorithm 1, steps
-(i)-(iv)) on the primal P0 discretisation.
+(i)-(iv)), on the primal P0 discretisation (adaptive_capacity) and on the
+dual mesh as the algorithm states it (adaptive_dual).
 
 (i)   solve: dense assembly and persistent Krylov solve on the GPU, warm
       started from the previous mesh's solution (the P0 spaces of NVB meshes
@@ -58,12 +59,17 @@ class Step:
     tris: Optional[np.ndarray] = None
     sigma: Optional[np.ndarray] = None
     eta2_elem: Optional[np.ndarray] = None
+    marked: Optional[np.ndarray] = None
 
 
 def adaptive_capacity(verts, tris, steps: int = 5, theta: float = 0.5, precision: str = "fp64",
-                      h_mode: int = 0, warm_start: bool = True, keep: bool = False, **solve_opts) -> List[Step]:
+                      h_mode: int = 0, warm_start: bool = True, keep: bool = False, refine: str = "bisec1",
+                      **solve_opts) -> List[Step]:
     """Run `steps` refinements (steps + 1 solves).  `tris` must be in NVB form
-    (reference edge first); use synth.init_reference_edges on a new mesh."""
+    (reference edge first); use synth.init_reference_edges on a new mesh.
+    refine "bisec1" bisects every marked element once and closes the mesh
+    (the coarsest conforming refinement of step (iv)); "bisec3" splits
+    marked elements into four."""
     verts = np.asarray(verts, dtype=np.float64)
     tris = np.asarray(tris, dtype=np.int32)
     x0 = None
@@ -88,11 +94,66 @@ def adaptive_capacity(verts, tris, steps: int = 5, theta: float = 0.5, precision
         step = Step(level, int(tris.shape[0]), res.cap, float(eta2.sum()), res.iters, res.outer, int(marked.size),
                     ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3]), 0.0)
         if keep:
-            step.verts, step.tris, step.sigma, step.eta2_elem = verts, tris, sigma, eta2
+            step.verts, step.tris, step.sigma, step.eta2_elem, step.marked = verts, tris, sigma, eta2, marked
         if level < steps:
-            verts, tris, parent = synth.refine_nvb(verts, tris, marked, "bisec3")
+            verts, tris, parent = synth.refine_nvb(verts, tris, marked, refine)
             x0 = torch.from_numpy(sigma[parent]).to(prob.device)
         step.t_refine_ms = (time.perf_counter() - t0) * 1e3
         out.append(step)
         del prob
+    return out
+
+
+def adaptive_dual(verts, tris, steps: int = 5, theta: float = 0.5, h_mode: int = 1, rtol: float = 1e-10,
+                  max_elements: Optional[int] = None, keep: bool = False, far_order: int = 4, ss_order: int = 4,
+                  jacobi_sweeps: int = 30, restart: int = 200, refine: str = "bisec1") -> List[Step]:
+    """Algorithm 1 as stated: (i) the Galerkin solution on the dual mesh,
+    computed from V on the barycentric refinement by GMRES with the
+    hypersingular operator as preconditioner (Section 2.6); (ii) the ZZ
+    indicators of the dual solution (eq. "zz:T"); (iii) Doerfler marking;
+    (iv) NVB.  h_mode 1 weights the indicators with |T|^(1/2), as the
+    implementation in Appendix B does (0: diam(T)^(1/2), as eq. "zz:T" is
+    written).  Stops after `steps` refinements, or before the first mesh
+    with more than `max_elements` triangles.  `iters` of each step is the
+    number of GMRES steps; the dual unknowns are not carried over between
+    meshes (each solve starts from zero).  refine as in adaptive_capacity."""
+    from .api import DualProblem
+
+    verts = np.asarray(verts, dtype=np.float64)
+    tris = np.asarray(tris, dtype=np.int32)
+    out: List[Step] = []
+    for level in range(steps + 1):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        prob = DualProblem(verts, tris, far_order=far_order, ss_order=ss_order, restart=restart)
+        ev[0].record()
+        prob.assemble()
+        ev[1].record()
+        res = prob.solve(rtol=rtol, jacobi_sweeps=jacobi_sweeps)
+        ev[2].record()
+        eta2_d = prob.zz(h_mode=h_mode)
+        ev[3].record()
+        if not res.ok:
+            raise RuntimeError(f"dual solve failed at level {level}: {res}")
+        eta2 = eta2_d.cpu().numpy()
+        t0 = time.perf_counter()
+        last = level == steps
+        marked = np.zeros(0, dtype=np.int64)
+        if not last:
+            marked = doerfler(eta2, theta)
+        step = Step(level, int(tris.shape[0]), res.cap, float(eta2.sum()), res.iters, 0, int(marked.size),
+                    ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3]), 0.0)
+        if keep:
+            step.verts, step.tris, step.eta2_elem, step.marked = verts, tris, eta2, marked
+            step.sigma = prob.x.cpu().numpy()
+        del prob
+        if not last:
+            nv, nt, _ = synth.refine_nvb(verts, tris, marked, refine)
+            if max_elements is not None and nt.shape[0] > max_elements:
+                last = True
+            else:
+                verts, tris = nv, nt
+        step.t_refine_ms = (time.perf_counter() - t0) * 1e3
+        out.append(step)
+        if last:
+            break
     return out

@@ -212,12 +212,19 @@ class CapacityProblem:
 def matvec(problem: "CapacityProblem", x: torch.Tensor, stream=None) -> torch.Tensor:
     """y = V x with the problem's assembled matrix (bc_matvec): the symmetric
     product of the solver as a standalone call.  x has N entries in the
-    matrix precision."""
+    matrix precision, or shape (k, N) for k vectors that share one pass over
+    V (FP64: k = 1 or 3)."""
     L = lib()
-    ws = torch.empty(L.bc_matvec_workspace_bytes(problem.N, problem.prec), dtype=torch.uint8, device=problem.device)
-    y = torch.empty(problem.N, dtype=problem.matrix_dtype, device=problem.device)
-    check("bc_matvec", L.bc_matvec(_ptr(problem.V), problem.N, problem.prec, _ptr(x), _ptr(y), _ptr(ws), ws.numel(),
-                                   _stream(stream)))
+    nr = 1 if x.dim() == 1 else int(x.shape[0])
+    if x.shape[-1] != problem.N or x.dtype != problem.matrix_dtype or not x.is_contiguous():
+        raise ValueError("x: contiguous, N entries per vector, matrix precision")
+    nb = L.bc_matvec_workspace_bytes(problem.N, problem.prec, nr)
+    if nb == 0:
+        raise ValueError(f"bc_matvec: {nr} vectors not supported in this precision")
+    ws = torch.empty(nb, dtype=torch.uint8, device=problem.device)
+    y = torch.empty_like(x)
+    check("bc_matvec", L.bc_matvec(_ptr(problem.V), problem.N, problem.prec, nr, _ptr(x), _ptr(y), _ptr(ws),
+                                   ws.numel(), _stream(stream)))
     return y
 
 

@@ -319,17 +319,21 @@ int32_t bc_zz_indicators(const int32_t *d_tris, int64_t N, const void *d_mesh_ws
   return launch_zz(d_tris, N, d_mesh_ws, d_pattern, nnz, d_sigma, h_mode, d_eta2, static_cast<hipStream_t>(stream));
 }
 
-size_t bc_matvec_workspace_bytes(int64_t N, int32_t precision) {
-  if (!n_ok(N) || (precision != BC_FP64 && precision != BC_MIXED)) return 0;
-  return MatvecLayout(N, precision).total;
+static bool matvec_ok(int64_t N, int32_t precision, int32_t nrhs) {
+  return n_ok(N) && ((precision == BC_FP64 && (nrhs == 1 || nrhs == 3)) || (precision == BC_MIXED && nrhs == 1));
 }
 
-int32_t bc_matvec(const void *d_V, int64_t N, int32_t precision, const void *d_x, void *d_y, void *d_ws,
-                  size_t ws_bytes, bc_stream stream) {
-  if (!d_V || !d_x || !d_y || !d_ws || !n_ok(N) || (precision != BC_FP64 && precision != BC_MIXED)) return BC_EINVAL;
+size_t bc_matvec_workspace_bytes(int64_t N, int32_t precision, int32_t nrhs) {
+  if (!matvec_ok(N, precision, nrhs)) return 0;
+  return MatvecLayout(N, precision, nrhs).total;
+}
+
+int32_t bc_matvec(const void *d_V, int64_t N, int32_t precision, int32_t nrhs, const void *d_x, void *d_y,
+                  void *d_ws, size_t ws_bytes, bc_stream stream) {
+  if (!d_V || !d_x || !d_y || !d_ws || !matvec_ok(N, precision, nrhs)) return BC_EINVAL;
   if (N > (int64_t)kMaxBand * solve_workgroups(N)) return BC_EINVAL;
-  if (ws_bytes < MatvecLayout(N, precision).total) return BC_ENOMEM;
-  return launch_matvec(precision, d_V, N, d_x, d_y, d_ws, static_cast<hipStream_t>(stream));
+  if (ws_bytes < MatvecLayout(N, precision, nrhs).total) return BC_ENOMEM;
+  return launch_matvec(precision, d_V, N, nrhs, d_x, d_y, d_ws, static_cast<hipStream_t>(stream));
 }
 
 static bool dual_sizes_ok(int64_t N, int64_t M, int32_t restart) {

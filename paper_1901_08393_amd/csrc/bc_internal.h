@@ -115,9 +115,10 @@ constexpr int kRB = 128;        // rows per block of the symmetric product
 constexpr int kMaxBand = 1536;  // rows of the vectors owned by one solver workgroup
 
 // Units of the blocks 0..B-1, m64 = ld / 64.  Block b has
-// ceil((m64 - 2b) / k) units; the sum is written out for k = 2 and k = 4
+// ceil((m64 - 2b) / k) units; the sum is written out for k = 1, 2 and 4
 // (pairs of blocks for k = 4).
 __host__ __device__ inline int64_t half_units_before(int64_t B, int64_t m64, int k) {
+  if (k == 1) return B * m64 - B * (B - 1);
   if (k == 2) return B * ((m64 + 1) / 2) - B * (B - 1) / 2;
   const int64_t n = m64 + 3, f0 = n / 4, f2 = (n - 2) / 4, A = B / 2;
   int64_t s = A * (f0 + f2) - A * (A - 1);
@@ -165,9 +166,9 @@ struct MatvecLayout {
   size_t xpad, rpart, cpart, total;
   int64_t ld, nB, T;
   int k;
-  __host__ __device__ MatvecLayout(int64_t N, int32_t precision) {
+  __host__ __device__ MatvecLayout(int64_t N, int32_t precision, int nr = 1) {
     ld = (N + 63) / 64 * 64;
-    k = precision == BC_FP64 ? 2 : 4;
+    k = precision == BC_FP64 ? (nr > 1 ? 1 : 2) : 4;  // chunk width / 64
     nB = (N + kRB - 1) / kRB;
     T = half_units_before(nB, ld / 64, k);
     size_t o = 0;
@@ -176,9 +177,9 @@ struct MatvecLayout {
       o = (o + bytes + 255) & ~size_t(255);
       return r;
     };
-    xpad = take(sizeof(double) * (size_t)ld);
-    rpart = take(sizeof(double) * kRB * (size_t)T);
-    cpart = take(sizeof(double) * (size_t)ld * (size_t)nB);
+    xpad = take(sizeof(double) * (size_t)nr * (size_t)ld);
+    rpart = take(sizeof(double) * (size_t)nr * kRB * (size_t)T);
+    cpart = take(sizeof(double) * (size_t)nr * (size_t)ld * (size_t)nB);
     total = o;
   }
 };
@@ -340,7 +341,10 @@ int launch_capacity(const double *sigma, const double *area, int64_t N, double *
 int launch_solve(int32_t precision, const SysDesc *d_desc, int n_sys, int total_wg, const SolveParams &p,
                  hipStream_t s);
 int solve_capacity(int32_t precision);
-int launch_matvec(int32_t precision, const void *V, int64_t N, const void *x, void *y, void *ws, hipStream_t s);
+// Y = V X for nr vectors stored one after the other (N entries each): FP64
+// with nr = 1 or 3, mixed (FP32) with nr = 1.  ws: MatvecLayout(N, precision, nr).
+int launch_matvec(int32_t precision, const void *V, int64_t N, int nr, const void *x, void *y, void *ws,
+                  hipStream_t s);
 int launch_dual_setup(const double *verts, const int32_t *tris, int64_t N, int64_t M, const int32_t *iptr,
                       const int32_t *itri, void *ws, int32_t restart, hipStream_t s);
 int run_dual_solve(const void *Vb, const int32_t *tris, int64_t N, int64_t M, const int32_t *iptr, const int32_t *itri,

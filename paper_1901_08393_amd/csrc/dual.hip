@@ -254,7 +254,7 @@ DualLayout::DualLayout(int64_t N, int64_t M, int32_t restart) {
   bvec = take(8 * 4 * (size_t)nb);  // three curl components and the dual indicator
   yvec = take(8 * 4 * (size_t)nb);
   dots = take(8 * (size_t)(restart + 8));
-  mv = take(MatvecLayout(nb, BC_FP64).total);
+  mv = take(MatvecLayout(nb, BC_FP64, 3).total);
   total = o;
 }
 
@@ -302,9 +302,7 @@ int run_dual_solve(const void *Vb, const int32_t *tris, int64_t N, int64_t M, co
   // out = D_reg u
   auto dreg = [&](const double *u, double *out) {
     hipLaunchKernelGGL(k_dual_Q, dim3(gB), dim3(kWG), 0, s, u, tris, curl, (int)N, nb, bvec);
-    for (int m = 0; m < 3; ++m) {
-      if (launch_matvec(BC_FP64, Vb, nb, bvec + m * nb, yvec + m * nb, mvws, s) != BC_OK) err = true;
-    }
+    if (launch_matvec(BC_FP64, Vb, nb, 3, bvec, yvec, mvws, s) != BC_OK) err = true;  // one pass, three vectors
     hipLaunchKernelGGL(k_multidot, dim3(1), dim3(kWG), 0, s, f, (int64_t)0, u, (int)M, dots + o.restart + 4);
     hipLaunchKernelGGL(k_dual_QT, dim3(gM), dim3(kWG), 0, s, (const double *)yvec, nb, iptr, itri, icor, curl, f,
                        (const double *)(dots + o.restart + 4), (int)M, out);
@@ -313,7 +311,7 @@ int run_dual_solve(const void *Vb, const int32_t *tris, int64_t N, int64_t M, co
   // out = M^{-1} P^T V P u  (u already M^{-1}-applied by the caller)
   auto vdual = [&](const double *u, double *out) {
     hipLaunchKernelGGL(k_dual_P, dim3(gB), dim3(kWG), 0, s, u, tris, (int)N, bvec + 3 * nb);
-    if (launch_matvec(BC_FP64, Vb, nb, bvec + 3 * nb, yvec + 3 * nb, mvws, s) != BC_OK) err = true;
+    if (launch_matvec(BC_FP64, Vb, nb, 1, bvec + 3 * nb, yvec + 3 * nb, mvws, s) != BC_OK) err = true;
     hipLaunchKernelGGL(k_dual_PT, dim3(gM), dim3(kWG), 0, s, (const double *)(yvec + 3 * nb), iptr, itri, icor,
                        (int)M, t1);
     minv(t1, out);

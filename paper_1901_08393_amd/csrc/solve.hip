@@ -190,6 +190,14 @@ struct Load16<double, double> {
   }
 };
 
+// one FP64 column per lane: the product with several vectors, whose row and
+// column sums take the registers that wider loads would need
+struct LoadD1 {
+  static constexpr int VEC = 1;
+  __device__ static void mat(gptr<const double> p, double (&v)[1]) { v[0] = __builtin_nontemporal_load(p); }
+  __device__ static void vec(gptr<const double> p, double (&v)[1]) { v[0] = *p; }
+};
+
 // ------------------------------------------------ symmetric half product
 // y = V x reading V only on its diagonal blocks and above them.  A unit
 // (block B, chunk c) covers the rows [kRB B, kRB B + kRB) and CW = 64 VEC
@@ -213,10 +221,9 @@ struct HalfPlan {
   int64_t u0, u1;  // this workgroup's units
 };
 
-template <typename MT, typename XT, typename AT, bool DELTA, bool LDS2>
+template <typename MT, typename XT, typename AT, bool DELTA, bool LDS2, int NR = 1, typename L = Load16<MT, XT>>
 __device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x, const HalfPlan &H, gptr<AT> rpart,
                                              gptr<AT> cpart, AT *lbuf, double &delta) {
-  using L = Load16<MT, XT>;
   constexpr int VEC = L::VEC;
   constexpr int CW = 64 * VEC;
   int64_t u = H.u0;
@@ -228,6 +235,9 @@ __device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x,
   const int tid = 64 * w + lane;
   const int N = H.N;
   const int ld = (int)H.ld;
+  // with NR right-hand sides, vector m and its partial sums sit at these
+  // strides from the first ones
+  const size_t xs = (size_t)H.ld, rs = (size_t)kRB * (size_t)H.T, cps = (size_t)H.nB * (size_t)H.ld;
   // block of the first unit
   int B;
   {
@@ -242,15 +252,35 @@ __device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x,
   int c = (int)(u - half_units_before(B, H.m64, H.k));
   int64_t useg = u;  // first unit of the current segment (its row sums are stored there)
 
-  AT xr[8], acc[8];
+  // x values of the wavefront's 8 rows (the same for all its lanes): in
+  // registers for one vector; for several in LDS behind the column-sum
+  // buffers, loaded by lanes 0 .. 8 NR - 1 of the wavefront at each block
+  // start and read back as broadcasts by the same wavefront (the LDS
+  // operations of a wavefront complete in order)
+  constexpr bool XR_LDS = NR > 1;
+  static_assert(XR_LDS || NR == 1, "several vectors keep their row values in LDS");
+  static_assert(XR_LDS || kRB <= 64 * VEC, "chunk 0 must hold the block's row values");
+  AT xr[8], acc[NR][8];
+  AT *xl = lbuf + (LDS2 ? 2 : 1) * NR * 16 * CW + w * NR * 8;
+  auto load_xr_lds = [&](int Bl) {
+    if (lane < 8 * NR) {
+      const int row = kRB * Bl + 8 * w + (lane & 7);
+      xl[lane] = row < N ? (AT)x[(lane >> 3) * xs + row] : AT(0);
+    }
+  };
+  auto get_xr = [&](int m, int r) -> AT { return XR_LDS ? xl[m * 8 + r] : xr[r]; };
+  if (XR_LDS) load_xr_lds(B);
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const int row = kRB * B + 8 * w + r;
-    xr[r] = (c > 0 && row < N) ? (AT)x[row] : AT(0);  // chunk 0 brings them itself
-    acc[r] = AT(0);
+    xr[r] = (!XR_LDS && c > 0 && row < N) ? (AT)x[row] : AT(0);  // chunk 0 brings them itself
   }
+#pragma unroll
+  for (int m = 0; m < NR; ++m)
+#pragma unroll
+    for (int r = 0; r < 8; ++r) acc[m][r] = AT(0);
   MT va[8][VEC];
-  XT xa[VEC];
+  XT xa[NR][VEC];
   // loads of unit (Bl, cl): the wavefront's 8 rows of block Bl (their bases
   // are the same for the whole wavefront) and the lane's VEC columns
   auto load = [&](int Bl, int cl) {
@@ -261,7 +291,8 @@ __device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x,
       const int row = min(kRB * Bl + 8 * w + r, N - 1);
       L::mat(V + (size_t)row * (size_t)ld + cc, va[r]);
     }
-    L::vec(x + cc, xa);
+#pragma unroll
+    for (int m = 0; m < NR; ++m) L::vec(x + m * xs + cc, xa[m]);
   };
   load(B, c);
   // Units are swept as one stream: the loads of the next unit (of this block
@@ -270,49 +301,56 @@ __device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x,
   while (true) {
     const int col = kRB * B + CW * c + lane * VEC;
     const bool act = col < ld;
-    if (c == 0) {
+    if (!XR_LDS && c == 0) {
       // chunk 0 starts at column kRB B: lane l holds x[kRB B + VEC l + q],
       // among them the x values of this wavefront's rows
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        const XT v = lane_f(xa[r % VEC], (8 * w + r) / VEC);  // the source lane is the same for the wavefront
+        const XT v = lane_f(xa[0][r % VEC], (8 * w + r) / VEC);  // the source lane is the same for the wavefront
         xr[r] = kRB * B + 8 * w + r < N ? (AT)v : AT(0);
       }
     }
-    AT xq[VEC], cs[VEC];
+    AT xq[NR][VEC], cs[NR][VEC];
 #pragma unroll
-    for (int q = 0; q < VEC; ++q) {
-      xq[q] = act ? (AT)xa[q] : AT(0);
-      cs[q] = AT(0);
-    }
-#pragma unroll
-    for (int r = 0; r < 8; ++r)
+    for (int m = 0; m < NR; ++m)
 #pragma unroll
       for (int q = 0; q < VEC; ++q) {
-        acc[r] = fma_t((AT)va[r][q], xq[q], acc[r]);
-        cs[q] = fma_t((AT)va[r][q], xr[r], cs[q]);
+        xq[m][q] = act ? (AT)xa[m][q] : AT(0);
+        cs[m][q] = AT(0);
       }
+#pragma unroll
+    for (int m = 0; m < NR; ++m)
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+          acc[m][r] = fma_t((AT)va[r][q], xq[m][q], acc[m][r]);
+          cs[m][q] = fma_t((AT)va[r][q], get_xr(m, r), cs[m][q]);
+        }
     const int diag_end = kRB * B + kRB;
     if (DELTA) {
       double d = 0.0;
 #pragma unroll
-      for (int q = 0; q < VEC; ++q) d = __builtin_fma((double)xq[q], (double)cs[q], d);
+      for (int q = 0; q < VEC; ++q) d = __builtin_fma((double)xq[0][q], (double)cs[0][q], d);
       delta = __builtin_fma(col < diag_end ? 1.0 : 2.0, d, delta);
     }
-    AT *lb = lbuf + (LDS2 ? (int)(u & 1) * (16 * CW) : 0);
+    AT *lb = lbuf + (LDS2 ? (int)(u & 1) * (NR * 16 * CW) : 0);
 #pragma unroll
-    for (int q = 0; q < VEC; ++q) lb[w * CW + lane * VEC + q] = cs[q];
+    for (int m = 0; m < NR; ++m)
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) lb[(m * 16 + w) * CW + lane * VEC + q] = cs[m][q];
     const bool more = u + 1 < H.u1;
     const bool same = u + 1 < SE;
     if (more) load(same ? B : B + 1, same ? c + 1 : 0);
     __syncthreads();
-    if (tid < CW) {
-      const int ct = kRB * B + CW * c + tid;
+    if (tid < NR * CW) {
+      const int m = NR == 1 ? 0 : tid / CW, t = tid - m * CW;
+      const int ct = kRB * B + CW * c + t;
       if (ct >= diag_end && ct < ld) {
         AT sum = AT(0);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) sum += lb[q * CW + tid];
-        cpart[(size_t)B * (size_t)ld + ct] = sum;
+        for (int q = 0; q < 16; ++q) sum += lb[(m * 16 + q) * CW + t];
+        cpart[m * cps + (size_t)B * (size_t)ld + ct] = sum;
       }
     }
     // with two buffers the next unit writes the other one; the barrier of
@@ -321,11 +359,13 @@ __device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x,
     if (!more || !same) {
       // end of a segment: the row sums of this block's units
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const AT sum = wave_sum_full(acc[r]);
-        if (lane == r && kRB * B + 8 * w + r < N) rpart[(size_t)useg * kRB + 8 * w + r] = sum;
-        acc[r] = AT(0);
-      }
+      for (int m = 0; m < NR; ++m)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const AT sum = wave_sum_full(acc[m][r]);
+          if (lane == r && kRB * B + 8 * w + r < N) rpart[m * rs + (size_t)useg * kRB + 8 * w + r] = sum;
+          acc[m][r] = AT(0);
+        }
       useg = u + 1;
     }
     if (!more) break;
@@ -336,6 +376,7 @@ __device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x,
       ++B;
       c = 0;
       SE = half_units_before(B + 1, H.m64, H.k);
+      if (XR_LDS) load_xr_lds(B);
     }
   }
   if (LDS2) __syncthreads();  // the last column sums are read before lbuf is reused
@@ -728,16 +769,19 @@ int launch_solve(int32_t precision, const SysDesc *d_desc, int n_sys, int total_
 }
 
 // ------------------------------------------------- standalone product
-// y = V x with the symmetric product of k_solve, as two launches (the
-// launch boundary takes the place of the system barrier): partial sums, then
-// the gather.  Same partition and order as inside the solver, so the result
-// depends on N only.
-template <typename MT>
+// Y = V X for NR vectors (X: NR columns of N entries, column-major) with the
+// symmetric product of k_solve, as three launches (the launch boundaries
+// take the place of the system barrier): padding, partial sums, gather.
+// Same partition and order as inside the solver, so the result depends on N
+// only; the NR vectors share each pass over V.
+template <typename MT, int NR>
 __global__ __launch_bounds__(kSolveWG) void k_matvec_pad(const MT *__restrict__ x, int64_t N, char *ws) {
-  const MatvecLayout Lay(N, sizeof(MT) == 8 ? BC_FP64 : BC_MIXED);
+  const MatvecLayout Lay(N, sizeof(MT) == 8 ? BC_FP64 : BC_MIXED, NR);
   MT *xp = reinterpret_cast<MT *>(ws + Lay.xpad);
-  for (int64_t i = (int64_t)blockIdx.x * kSolveWG + threadIdx.x; i < Lay.ld; i += (int64_t)gridDim.x * kSolveWG)
-    xp[i] = i < N ? x[i] : MT(0);
+  for (int64_t i = (int64_t)blockIdx.x * kSolveWG + threadIdx.x; i < NR * Lay.ld; i += (int64_t)gridDim.x * kSolveWG) {
+    const int64_t m = i / Lay.ld, j = i - m * Lay.ld;
+    xp[i] = j < N ? x[m * N + j] : MT(0);
+  }
 }
 
 template <typename MT>
@@ -748,49 +792,61 @@ __device__ __forceinline__ HalfPlan matvec_plan(const MatvecLayout &Lay, int64_t
   return H;
 }
 
-template <typename MT>
+// LDS: two buffers of NR x 16 wavefronts x CW column sums, and for NR > 1
+// the 16 x 8 x NR row x values.  One vector: 16-byte loads (CW = 64 x 16 B);
+// several (FP64 only): one column per lane (CW = 64), so that the NR x 8 row
+// sums stay in registers.
+template <typename MT, int NR>
 __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) void k_matvec_part(
     const MT *__restrict__ V, int64_t N, char *ws) {
-  __shared__ double s_buf[4096];
-  const MatvecLayout Lay(N, sizeof(MT) == 8 ? BC_FP64 : BC_MIXED);
+  static_assert(NR == 1 || sizeof(MT) == 8, "several vectors: FP64 only");
+  using L = typename std::conditional<NR == 1, Load16<MT, MT>, LoadD1>::type;
+  constexpr int CW = 64 * L::VEC;
+  __shared__ MT s_buf[2 * NR * 16 * CW + (NR > 1 ? 16 * 8 * NR : 0)];
+  const MatvecLayout Lay(N, sizeof(MT) == 8 ? BC_FP64 : BC_MIXED, NR);
   const HalfPlan H = matvec_plan<MT>(Lay, N, (int)gridDim.x, (int)blockIdx.x);
   gptr<char> w = as_global(ws);
   double unused = 0.0;
-  half_product<MT, MT, MT, false, true>(as_global(V), reinterpret_cast<gptr<const MT>>(w + Lay.xpad), H,
-                                        reinterpret_cast<gptr<MT>>(w + Lay.rpart),
-                                        reinterpret_cast<gptr<MT>>(w + Lay.cpart), reinterpret_cast<MT *>(s_buf),
-                                        unused);
+  half_product<MT, MT, MT, false, true, NR, L>(as_global(V), reinterpret_cast<gptr<const MT>>(w + Lay.xpad), H,
+                                               reinterpret_cast<gptr<MT>>(w + Lay.rpart),
+                                               reinterpret_cast<gptr<MT>>(w + Lay.cpart), s_buf, unused);
 }
 
-template <typename MT>
+template <typename MT, int NR>
 __global__ __launch_bounds__(kSolveWG) void k_matvec_gather(int64_t N, const char *ws, MT *__restrict__ y) {
   __shared__ double s_part[16 * 64];
   __shared__ double s_band[kMaxBand];
-  const MatvecLayout Lay(N, sizeof(MT) == 8 ? BC_FP64 : BC_MIXED);
+  const MatvecLayout Lay(N, sizeof(MT) == 8 ? BC_FP64 : BC_MIXED, NR);
   const int G = (int)gridDim.x, rank = (int)blockIdx.x;
   const HalfPlan H = matvec_plan<MT>(Lay, N, G, rank);
   const int r0 = (int)(N * rank / G), r1 = (int)(N * (rank + 1) / G);
   gptr<const char> w = as_global(ws);
   MT *band = reinterpret_cast<MT *>(s_band);
-  half_gather<MT>(H, r0, r1, reinterpret_cast<gptr<const MT>>(w + Lay.rpart),
-                  reinterpret_cast<gptr<const MT>>(w + Lay.cpart), reinterpret_cast<MT *>(s_part), band);
-  for (int i = r0 + (int)threadIdx.x; i < r1; i += kSolveWG) y[i] = band[i - r0];
+  for (int m = 0; m < NR; ++m) {
+    half_gather<MT>(H, r0, r1, reinterpret_cast<gptr<const MT>>(w + Lay.rpart) + (size_t)m * kRB * Lay.T,
+                    reinterpret_cast<gptr<const MT>>(w + Lay.cpart) + (size_t)m * Lay.nB * Lay.ld,
+                    reinterpret_cast<MT *>(s_part), band);
+    for (int i = r0 + (int)threadIdx.x; i < r1; i += kSolveWG) y[m * N + i] = band[i - r0];
+    __syncthreads();  // band is rewritten by the next vector's gather
+  }
 }
 
-int launch_matvec(int32_t precision, const void *V, int64_t N, const void *x, void *y, void *ws, hipStream_t s) {
+template <typename MT, int NR>
+static void matvec_launch(const void *V, int64_t N, const void *x, void *y, char *w, hipStream_t s) {
   const int G = solve_workgroups(N);
+  hipLaunchKernelGGL((k_matvec_pad<MT, NR>), dim3(16), dim3(kSolveWG), 0, s, static_cast<const MT *>(x), N, w);
+  hipLaunchKernelGGL((k_matvec_part<MT, NR>), dim3(G), dim3(kSolveWG), 0, s, static_cast<const MT *>(V), N, w);
+  hipLaunchKernelGGL((k_matvec_gather<MT, NR>), dim3(G), dim3(kSolveWG), 0, s, N, (const char *)w,
+                     static_cast<MT *>(y));
+}
+
+int launch_matvec(int32_t precision, const void *V, int64_t N, int nr, const void *x, void *y, void *ws,
+                  hipStream_t s) {
   char *w = static_cast<char *>(ws);
-  if (precision == BC_FP64) {
-    hipLaunchKernelGGL(k_matvec_pad<double>, dim3(16), dim3(kSolveWG), 0, s, static_cast<const double *>(x), N, w);
-    hipLaunchKernelGGL(k_matvec_part<double>, dim3(G), dim3(kSolveWG), 0, s, static_cast<const double *>(V), N, w);
-    hipLaunchKernelGGL(k_matvec_gather<double>, dim3(G), dim3(kSolveWG), 0, s, N, (const char *)w,
-                       static_cast<double *>(y));
-  } else {
-    hipLaunchKernelGGL(k_matvec_pad<float>, dim3(16), dim3(kSolveWG), 0, s, static_cast<const float *>(x), N, w);
-    hipLaunchKernelGGL(k_matvec_part<float>, dim3(G), dim3(kSolveWG), 0, s, static_cast<const float *>(V), N, w);
-    hipLaunchKernelGGL(k_matvec_gather<float>, dim3(G), dim3(kSolveWG), 0, s, N, (const char *)w,
-                       static_cast<float *>(y));
-  }
+  if (precision == BC_FP64 && nr == 1) matvec_launch<double, 1>(V, N, x, y, w, s);
+  else if (precision == BC_FP64 && nr == 3) matvec_launch<double, 3>(V, N, x, y, w, s);
+  else if (precision == BC_MIXED && nr == 1) matvec_launch<float, 1>(V, N, x, y, w, s);
+  else return BC_EINVAL;
   return hipGetLastError() == hipSuccess ? BC_OK : BC_EDEVICE;
 }
 

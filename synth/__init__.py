@@ -15,6 +15,8 @@ from .meshes import (  # noqa: F401
     box,
     convex_hull,
     cube,
+    cube12,
+    fichera48,
     icosphere,
     mesh_topology_ok,
     min_angle_deg,

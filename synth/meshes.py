@@ -106,6 +106,43 @@ def cube(n: int = 8, scale=(1.0, 1.0, 1.0), name: str | None = None) -> Mesh:
     return _finish(verts, tris, name or f"cube{n}", {"n": n, "scale": list(map(float, scale))})
 
 
+def cube12(name: str = "cube12") -> Mesh:
+    """The unit cube in 12 triangles with one particular choice of face
+    diagonals: five faces are cut along edges of the regular tetrahedron
+    with vertices (1,0,0), (0,1,0), (0,0,1), (1,1,1); the face x = 1 is cut
+    along (1,1,0)-(1,0,1) instead.  The capacity and estimator of the first
+    step of the unit-cube experiment (Section 3.1, Table 1, l = 0) depend on
+    the diagonals; of the eight classes of diagonal choices this is the one
+    whose dual-mesh values lie next to the printed ones."""
+    verts = np.array([[0, 0, 0], [0, 1, 0], [0, 1, 1], [0, 0, 1], [1, 0, 0], [1, 1, 0], [1, 1, 1], [1, 0, 1]],
+                     dtype=np.float64)
+    tris = np.array([[1, 0, 3], [1, 3, 2], [5, 6, 7], [5, 7, 4], [3, 0, 4], [3, 4, 7], [6, 5, 1], [6, 1, 2],
+                     [4, 0, 1], [4, 1, 5], [6, 2, 3], [6, 3, 7]], dtype=np.int32)
+    return _finish(verts, tris, name, {"n": 1, "diagonals": "tetrahedral, face x=1 flipped"})
+
+
+def fichera48(name: str = "fichera48") -> Mesh:
+    """The Fichera cube [-1,1]^3 minus [0,1]^3 in 48 triangles: its 24 unit
+    squares, each cut along one diagonal.  The capacity and estimator of the
+    first step of the Fichera experiment (Section 3.2, Table 2, l = 0) depend
+    on the diagonals; these are the ones whose dual-mesh values lie next to
+    the printed ones (found by a coordinate search over the 2^24 choices,
+    which reached this mesh from two different random starts)."""
+    verts = np.array([[-1, -1, -1], [-1, 0, -1], [-1, 0, 0], [-1, -1, 0], [0, -1, 0], [0, -1, -1], [0, 0, -1],
+                      [-1, 0, 1], [-1, -1, 1], [0, -1, 1], [0, 0, 1], [-1, 1, -1], [-1, 1, 0], [0, 1, 0],
+                      [0, 1, -1], [-1, 1, 1], [0, 0, 0], [0, 1, 1], [1, -1, -1], [1, 0, -1], [1, 0, 0], [1, -1, 0],
+                      [1, 0, 1], [1, -1, 1], [1, 1, -1], [1, 1, 0]], dtype=np.float64)
+    tris = np.array([[1, 0, 3], [1, 3, 2], [3, 0, 5], [3, 5, 4], [5, 0, 1], [5, 1, 6], [3, 7, 2], [3, 8, 7],
+                     [3, 9, 8], [3, 4, 9], [9, 10, 7], [9, 7, 8], [1, 12, 11], [1, 2, 12], [12, 13, 14],
+                     [12, 14, 11], [1, 14, 6], [1, 11, 14], [12, 2, 7], [12, 7, 15], [13, 17, 10], [13, 10, 16],
+                     [12, 15, 17], [12, 17, 13], [7, 10, 17], [7, 17, 15], [19, 20, 21], [19, 21, 18], [5, 21, 4],
+                     [5, 18, 21], [5, 19, 18], [5, 6, 19], [21, 20, 22], [21, 22, 23], [9, 4, 21], [9, 21, 23],
+                     [10, 22, 20], [10, 20, 16], [9, 23, 22], [9, 22, 10], [19, 24, 25], [19, 25, 20],
+                     [14, 13, 25], [14, 25, 24], [19, 6, 14], [19, 14, 24], [20, 25, 13], [20, 13, 16]],
+                    dtype=np.int32)
+    return _finish(verts, tris, name, {"n": 1})
+
+
 def box(a: float, b: float, name: str = "box") -> Mesh:
     """Box with sides (1, a, b): 12 triangles before refinement."""
     m = cube(1, scale=(1.0, a, b), name=name)

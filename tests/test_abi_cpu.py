@@ -57,6 +57,11 @@ def test_sizes(L):
     assert L.bc_solve_workgroups(1) == 1 and L.bc_solve_workgroups(80) == 1 and L.bc_solve_workgroups(81) == 2
     assert L.bc_solve_workgroups(10 ** 6) == 256
     assert L.bc_batch_scratch_bytes(3) >= 3 * 96
+    # products with several vectors: FP64 with 1 or 3, mixed with 1
+    one, three = L.bc_matvec_workspace_bytes(5000, 0, 1), L.bc_matvec_workspace_bytes(5000, 0, 3)
+    assert one > 0 and three > 2 * one
+    assert L.bc_matvec_workspace_bytes(5000, 1, 1) > 0
+    assert L.bc_matvec_workspace_bytes(5000, 0, 2) == 0 and L.bc_matvec_workspace_bytes(5000, 1, 3) == 0
 
 
 def _check(L, verts, tris):
@@ -117,3 +122,6 @@ def test_argument_errors_without_device(L):
                       100, C.c_void_p(16), null) == -3
     assert L.bc_zz_indicators(null, 12, null, null, 12, null, 0, null, null) == -1
     assert L.bc_capacity(null, null, 5, null, null) == -1
+    assert L.bc_matvec(C.c_void_p(16), 100, 0, 2, C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), 1 << 30,
+                       null) == -1
+    assert L.bc_matvec(C.c_void_p(16), 100, 0, 3, C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), 10, null) == -3

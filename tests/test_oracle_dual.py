@@ -170,3 +170,55 @@ def test_zz_dual():
         ref[t] += ab[k] * np.mean(g * g)
     ref *= geo["diam"]
     assert np.allclose(eta2, ref, rtol=1e-3), (eta2, ref)
+
+
+def test_table1_first_step():
+    """Section 3.1, Table 1, l = 0: the dual-mesh capacity and estimator of
+    the 12-triangle unit cube.  The printed values depend on the face
+    diagonals of T_0 (eight classes, capacities 0.64889 .. 0.64971 at the
+    same quadrature); on the class built by synth.cube12 the converged
+    capacity lies 2.3e-6 below the printed one (the paper's quadrature
+    orders are not stated; our own order 4 -> 8 changes the value by 2e-5).
+    eta^2 uses the mesh size |T|^(1/2) of the paper's implementation listing
+    (Appendix B); with diam(T)^(1/2) it would be twice as large on this mesh,
+    and on every other diagonal class it is off by more than a factor 2.
+    (This row's error column, 1.114e-2, does not equal the literature value
+    minus its capacity column, 1.1397e-2; later rows do.  The capacity column
+    is the one pinned.)"""
+    import json
+    import os
+
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+    row = g["cube_table1"]["rows"][0]
+    m = synth.cube12()
+    assert m.N == row["N"]
+    Vb, P, bv, bt = dual.assemble_dual(m.verts, m.tris, 8, 8)
+    f = dual.dual_load(m.verts, m.tris)
+    x, Vd = dual.solve_dual(Vb, P, f)
+    cap = dual.capacity_dual(x, f)
+    assert abs(cap - row["cap"]) < 1e-5, cap
+    eta2 = dual.zz_dual(m.verts, m.tris, x, "area").sum()
+    assert abs(eta2 / row["eta2"] - 1.0) < 2e-3, eta2
+
+
+def test_table2_first_step():
+    """Section 3.2, Table 2, l = 0: the dual-mesh capacity and estimator of
+    the 48-triangle Fichera cube (synth.fichera48).  Converged quadrature
+    (order 8) gives 1.2813949, 3.6e-6 below the printed 1.2813985240 (order
+    4: 1.28141130, so the paper's unstated orders explain the gap), and
+    eta^2 = 0.323868 with |T|^(1/2), inside the printed 3.239e-1's rounding
+    interval."""
+    import json
+    import os
+
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+    row = g["fichera_table2"]["rows"][0]
+    m = synth.fichera48()
+    assert m.N == row["N"]
+    Vb, P, bv, bt = dual.assemble_dual(m.verts, m.tris, 8, 8)
+    f = dual.dual_load(m.verts, m.tris)
+    x, Vd = dual.solve_dual(Vb, P, f)
+    cap = dual.capacity_dual(x, f)
+    assert abs(cap - row["cap"]) < 1e-5, cap
+    eta2 = dual.zz_dual(m.verts, m.tris, x, "area").sum()
+    assert abs(eta2 - row["eta2"]) <= 5e-5, eta2
