@@ -316,6 +316,36 @@ def dual_mode(a):
                       "bary_matvec": mv}))
 
 
+def adaptive_cube_mode(a):
+    """The unit-cube experiment of Section 3.1 on the primal P0 path: the
+    12-triangle cube, solve -> ZZ -> Doerfler (theta = 1/2) -> NVB (bisect
+    once), warm-started, until the next mesh would exceed --target-n
+    triangles.  Reports the capacity error against the reference value of
+    Section 3.1 per step (the paper's claim: order 1e-6 for the cube)."""
+    import torch
+
+    import synth
+    from paper_1901_08393_amd.adaptive import adaptive_capacity
+
+    torch.cuda.set_device(0)
+    m = synth.cube12()
+    t0 = synth.init_reference_edges(m.verts, m.tris)
+    w0 = time.perf_counter()
+    steps = adaptive_capacity(m.verts, t0, steps=1000, theta=0.5, precision=a.precision, h_mode=1,
+                              max_elements=a.target_n)
+    wall = time.perf_counter() - w0
+    rows = []
+    for s in steps:
+        err = abs(CUBE_CAPACITY - s.cap)
+        rows.append(dict(l=s.level, N=s.N, cap=round(s.cap, 12), eta2=float(f"{s.eta2:.4e}"), err=float(f"{err:.4e}"),
+                         iters=s.iters, outer=s.outer, assemble_ms=round(s.t_assemble_ms, 2),
+                         solve_ms=round(s.t_solve_ms, 2), host_ms=round(s.t_refine_ms, 1)))
+        log(f"l={s.level} N={s.N} cap={s.cap:.12f} err={err:.3e} eta2={s.eta2:.3e} its={s.iters} "
+            f"asm {s.t_assemble_ms:.1f} ms solve {s.t_solve_ms:.1f} ms")
+    print(json.dumps({"mode": "adaptive_cube", "precision": a.precision, "steps": rows, "wall_s": round(wall, 2),
+                      "monotone": all(steps[k].cap < steps[k + 1].cap for k in range(len(steps) - 1))}))
+
+
 def mixed60k_mode(a):
     """Mixed precision at N >= 60000: a seeded voxel union adapted (ZZ +
     Doerfler + NVB, FP64 path) until N >= 60000; then the FP64 GPU solve as
@@ -382,6 +412,8 @@ def main():
     ap.add_argument("--dual", choices=sorted(DUAL_WORKLOADS), default=None,
                     help="Algorithm 1 in dual mode on the unit cube (Table 1) or the Fichera cube (Table 2)")
     ap.add_argument("--dual-max-n", type=int, default=12000)
+    ap.add_argument("--adaptive-cube", action="store_true",
+                    help="the unit-cube experiment on the primal path, up to --target-n triangles")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy first (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -396,6 +428,8 @@ def main():
         return mixed60k_mode(a)
     if a.dual:
         return dual_mode(a)
+    if a.adaptive_cube:
+        return adaptive_cube_mode(a)
 
     import torch
 

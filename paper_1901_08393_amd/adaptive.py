@@ -64,8 +64,9 @@ class Step:
 
 def adaptive_capacity(verts, tris, steps: int = 5, theta: float = 0.5, precision: str = "fp64",
                       h_mode: int = 0, warm_start: bool = True, keep: bool = False, refine: str = "bisec1",
-                      **solve_opts) -> List[Step]:
-    """Run `steps` refinements (steps + 1 solves).  `tris` must be in NVB form
+                      max_elements: Optional[int] = None, **solve_opts) -> List[Step]:
+    """Run `steps` refinements (steps + 1 solves), or stop before the first
+    mesh with more than `max_elements` triangles.  `tris` must be in NVB form
     (reference edge first); use synth.init_reference_edges on a new mesh.
     refine "bisec1" bisects every marked element once and closes the mesh
     (the coarsest conforming refinement of step (iv)); "bisec3" splits
@@ -90,17 +91,25 @@ def adaptive_capacity(verts, tris, steps: int = 5, theta: float = 0.5, precision
         eta2 = eta2_d.cpu().numpy()
         sigma = prob.sigma.cpu().numpy()
         t0 = time.perf_counter()
-        marked = doerfler(eta2, theta) if level < steps else np.zeros(0, dtype=np.int64)
+        last = level == steps
+        marked = np.zeros(0, dtype=np.int64) if last else doerfler(eta2, theta)
         step = Step(level, int(tris.shape[0]), res.cap, float(eta2.sum()), res.iters, res.outer, int(marked.size),
                     ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3]), 0.0)
         if keep:
             step.verts, step.tris, step.sigma, step.eta2_elem, step.marked = verts, tris, sigma, eta2, marked
-        if level < steps:
-            verts, tris, parent = synth.refine_nvb(verts, tris, marked, refine)
-            x0 = torch.from_numpy(sigma[parent]).to(prob.device)
+        device = prob.device
+        del prob, eta2_d
+        if not last:
+            nv, nt, parent = synth.refine_nvb(verts, tris, marked, refine)
+            if max_elements is not None and nt.shape[0] > max_elements:
+                last = True
+            else:
+                verts, tris = nv, nt
+                x0 = torch.from_numpy(sigma[parent]).to(device)
         step.t_refine_ms = (time.perf_counter() - t0) * 1e3
         out.append(step)
-        del prob
+        if last:
+            break
     return out
 
 

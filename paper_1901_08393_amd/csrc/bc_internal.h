@@ -256,17 +256,6 @@ __device__ __forceinline__ double rsqrt64(double x) {
   return __builtin_fma(y * e, c, y);
 }
 
-// Inverse square root in FP32: hardware estimate refined by one Newton step
-// y <- y + (y/2)(1 - x y^2).  The estimate alone carries a small one-sided
-// error that would bias every far-field entry the same way; after the step
-// the remaining error is rounding of either sign.
-__device__ __forceinline__ float rsqrt32(float x) {
-  float y = __builtin_amdgcn_rsqf(x);
-  float t = x * y;
-  float e = __builtin_fmaf(-t, y, 1.0f);
-  return __builtin_fmaf(0.5f * y, e, y);
-}
-
 // Squared distance between two axis-aligned boxes given as (min xyz, max
 // xyz); 0 if they touch or overlap.
 __device__ __forceinline__ double box_dist2(const double *a, const double *b) {
