@@ -303,24 +303,39 @@ int32_t bc_matvec(const void *d_V, int64_t N, int32_t precision, int32_t nrhs,
 typedef struct {
   double rtol;           /* stop when the preconditioned residual of GMRES
                             has dropped by rtol, e.g. 1e-12 */
+  double inexact_lambda; /* > 0: also stop at the first step k with
+                            ||x_k - x_{k-1}||_V <= lambda eta(x_k), the energy
+                            norm of the last update against the ZZ estimator
+                            of the current iterate (Section 2.5, Remark (i),
+                            lambda ~ 1e-3); 0: off */
   int32_t max_iter;      /* GMRES steps, <= restart */
   int32_t restart;       /* Krylov basis size the workspace was sized for */
   int32_t jacobi_sweeps; /* sweeps approximating M^{-1} (a fixed linear
                             operator; the solution does not depend on it) */
-  int32_t reserved;      /* must be 0 */
+  int32_t h_mode;        /* mesh size of eta in the inexact stop: 0 diam(T),
+                            1 |T|^(1/2) */
 } bc_dual_opts;
 
 typedef struct {
   double cap;            /* (1/4pi) sum_j x_j |T_j^dual|   (eq. "cap:ell") */
   double rel_residual;   /* last preconditioned relative residual */
-  int32_t iters;         /* GMRES steps (four products with V_bary each) */
+  double energy_step;    /* ||x_k - x_{k-1}||_V of the last step (inexact
+                            stop only, else 0) */
+  double eta;            /* eta(x_k) = (sum_T eta_T^2)^(1/2) of the returned
+                            iterate (inexact stop only, else 0) */
+  int32_t iters;         /* GMRES steps (two passes over V_bary each: the
+                            three curl components, then V_dual) */
   int32_t status;        /* BC_OK or BC_ENOCONV */
+  int32_t stop;          /* 1 residual tolerance, 2 inexact-solve criterion,
+                            3 exact invariant subspace, 0 step limit */
+  int32_t reserved;
 } bc_dual_result;
 
 /* Device scratch for the dual system: per-triangle geometry and curls,
  * dual areas, mass matrix diagonal, the Krylov basis (restart + 1 vectors of
- * length M), four vectors on the barycentric mesh and the product's
- * scratch. */
+ * length M) and two more bases of restart vectors (the preconditioned basis
+ * vectors and V_dual applied to them), vectors on the barycentric mesh and
+ * the product's scratch. */
 size_t bc_dual_workspace_bytes(int64_t N, int64_t M, int32_t restart);
 
 /* Per triangle: area, diameter, surface curls of the hat functions
@@ -336,8 +351,11 @@ int32_t bc_dual_setup(const double *d_verts, int64_t M, const int32_t *d_tris,
  * |T_j^dual|) with the hypersingular operator D_reg = sum_m Q_m^T V_bary Q_m
  * + a a^T as right and the inverse mass matrix as left preconditioner
  * (Section 2.6).  Writes x (M entries, FP64) to d_x and the capacity,
- * iteration count and status to *h_result.  Host-driven: SYNCHRONOUS (waits
- * for `stream` once per Gram-Schmidt pass).  Errors: BC_EINVAL for bad
+ * iteration count and status to *h_result.  x is formed as the combination
+ * of the preconditioned basis vectors M^{-1} D_reg z_i, kept during the
+ * iteration, which also gives every iterate's energy-norm update for the
+ * inexact stop without further products.  Host-driven: SYNCHRONOUS (waits
+ * for `stream` a few times per GMRES step).  Errors: BC_EINVAL for bad
  * options or sizes, BC_ENOMEM for a short workspace. */
 int32_t bc_dual_solve(const double *d_Vbary, const int32_t *d_tris, int64_t N,
                       int64_t M, const int32_t *d_iptr, const int32_t *d_itri,

@@ -55,12 +55,13 @@ class bc_system(C.Structure):
 
 
 class bc_dual_opts(C.Structure):
-    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("restart", C.c_int32),
-                ("jacobi_sweeps", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("rtol", C.c_double), ("inexact_lambda", C.c_double), ("max_iter", C.c_int32),
+                ("restart", C.c_int32), ("jacobi_sweeps", C.c_int32), ("h_mode", C.c_int32)]
 
 
 class bc_dual_result(C.Structure):
-    _fields_ = [("cap", C.c_double), ("rel_residual", C.c_double), ("iters", C.c_int32), ("status", C.c_int32)]
+    _fields_ = [("cap", C.c_double), ("rel_residual", C.c_double), ("energy_step", C.c_double), ("eta", C.c_double),
+                ("iters", C.c_int32), ("status", C.c_int32), ("stop", C.c_int32), ("reserved", C.c_int32)]
 
 
 P = C.c_void_p

@@ -64,7 +64,8 @@ class Step:
 
 def adaptive_capacity(verts, tris, steps: int = 5, theta: float = 0.5, precision: str = "fp64",
                       h_mode: int = 0, warm_start: bool = True, keep: bool = False, refine: str = "bisec1",
-                      max_elements: Optional[int] = None, **solve_opts) -> List[Step]:
+                      max_elements: Optional[int] = None, far_order: int = 4, ss_order: int = 4,
+                      **solve_opts) -> List[Step]:
     """Run `steps` refinements (steps + 1 solves), or stop before the first
     mesh with more than `max_elements` triangles.  `tris` must be in NVB form
     (reference edge first); use synth.init_reference_edges on a new mesh.
@@ -77,7 +78,7 @@ def adaptive_capacity(verts, tris, steps: int = 5, theta: float = 0.5, precision
     out: List[Step] = []
     for level in range(steps + 1):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        prob = CapacityProblem(verts, tris, precision)
+        prob = CapacityProblem(verts, tris, precision, far_order, ss_order)
         ev[0].record()
         prob.assemble()
         ev[1].record()
@@ -115,7 +116,8 @@ def adaptive_capacity(verts, tris, steps: int = 5, theta: float = 0.5, precision
 
 def adaptive_dual(verts, tris, steps: int = 5, theta: float = 0.5, h_mode: int = 1, rtol: float = 1e-10,
                   max_elements: Optional[int] = None, keep: bool = False, far_order: int = 4, ss_order: int = 4,
-                  jacobi_sweeps: int = 30, restart: int = 200, refine: str = "bisec1") -> List[Step]:
+                  jacobi_sweeps: int = 30, restart: int = 200, refine: str = "bisec1",
+                  inexact_lambda: float = 0.0) -> List[Step]:
     """Algorithm 1 as stated: (i) the Galerkin solution on the dual mesh,
     computed from V on the barycentric refinement by GMRES with the
     hypersingular operator as preconditioner (Section 2.6); (ii) the ZZ
@@ -125,7 +127,10 @@ def adaptive_dual(verts, tris, steps: int = 5, theta: float = 0.5, h_mode: int =
     written).  Stops after `steps` refinements, or before the first mesh
     with more than `max_elements` triangles.  `iters` of each step is the
     number of GMRES steps; the dual unknowns are not carried over between
-    meshes (each solve starts from zero).  refine as in adaptive_capacity."""
+    meshes (each solve starts from zero).  refine as in adaptive_capacity.
+    inexact_lambda > 0 couples the solver to the estimator (Section 2.5,
+    Remark (i)): GMRES also stops once the energy norm of its last update is
+    at most inexact_lambda times the estimator of the current iterate."""
     from .api import DualProblem
 
     verts = np.asarray(verts, dtype=np.float64)
@@ -137,7 +142,7 @@ def adaptive_dual(verts, tris, steps: int = 5, theta: float = 0.5, h_mode: int =
         ev[0].record()
         prob.assemble()
         ev[1].record()
-        res = prob.solve(rtol=rtol, jacobi_sweeps=jacobi_sweeps)
+        res = prob.solve(rtol=rtol, jacobi_sweeps=jacobi_sweeps, inexact_lambda=inexact_lambda, h_mode=h_mode)
         ev[2].record()
         eta2_d = prob.zz(h_mode=h_mode)
         ev[3].record()

@@ -234,6 +234,9 @@ class DualResult:
     rel_residual: float
     iters: int
     status: int
+    energy_step: float = 0.0  # ||x_k - x_{k-1}||_V of the last step (inexact stop)
+    eta: float = 0.0  # ZZ estimator of the returned iterate (inexact stop)
+    stop: int = 0  # 1 residual, 2 inexact-solve criterion, 3 invariant subspace, 0 step limit
 
     @property
     def ok(self) -> bool:
@@ -282,16 +285,20 @@ class DualProblem:
         return self.bary.assemble(stream)
 
     def solve(self, rtol: float = 1e-12, max_iter: Optional[int] = None, jacobi_sweeps: int = 30,
-              stream=None) -> DualResult:
+              inexact_lambda: float = 0.0, h_mode: int = 1, stream=None) -> DualResult:
+        """GMRES to the relative residual rtol; with inexact_lambda > 0 also
+        stops once the energy norm of the last update is at most
+        inexact_lambda times the ZZ estimator (mesh size h_mode) of the
+        current iterate (Section 2.5, Remark (i))."""
         if self.bary.V is None:
             raise RuntimeError("assemble() first")
-        o = _lib.bc_dual_opts(rtol, int(max_iter or self.restart), self.restart, jacobi_sweeps, 0)
+        o = _lib.bc_dual_opts(rtol, inexact_lambda, int(max_iter or self.restart), self.restart, jacobi_sweeps, h_mode)
         r = _lib.bc_dual_result()
         check("bc_dual_solve", lib().bc_dual_solve(_ptr(self.bary.V), _ptr(self.d_tris), self.N, self.M,
                                                    _ptr(self.d_iptr), _ptr(self.d_itri), _ptr(self.d_icor),
                                                    _ptr(self.ws), self.ws.numel(), C.byref(o), _ptr(self.x),
                                                    C.byref(r), _stream(stream)))
-        return DualResult(r.cap, r.rel_residual, r.iters, r.status)
+        return DualResult(r.cap, r.rel_residual, r.iters, r.status, r.energy_step, r.eta, r.stop)
 
     def zz(self, h_mode: int = 0, stream=None) -> torch.Tensor:
         eta2 = torch.empty(self.N, dtype=torch.float64, device=self.device)

@@ -359,7 +359,8 @@ int32_t bc_dual_solve(const double *d_Vbary, const int32_t *d_tris, int64_t N, i
   if (!d_Vbary || !d_tris || !d_iptr || !d_itri || !d_icor || !d_ws || !opts || !d_x || !h_result) return BC_EINVAL;
   if (!dual_sizes_ok(N, M, opts->restart)) return BC_EINVAL;
   if (!(opts->rtol > 0.0) || !std::isfinite(opts->rtol) || opts->max_iter < 1 || opts->max_iter > opts->restart ||
-      opts->jacobi_sweeps < 0 || opts->jacobi_sweeps > 1000 || opts->reserved != 0)
+      opts->jacobi_sweeps < 0 || opts->jacobi_sweeps > 1000 || (opts->h_mode != 0 && opts->h_mode != 1) ||
+      !(opts->inexact_lambda >= 0.0) || !std::isfinite(opts->inexact_lambda))
     return BC_EINVAL;
   if (ws_bytes < DualLayout(N, M, opts->restart).total) return BC_ENOMEM;
   return run_dual_solve(d_Vbary, d_tris, N, M, d_iptr, d_itri, d_icor, d_ws, *opts, d_x, h_result,

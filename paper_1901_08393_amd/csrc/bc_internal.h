@@ -186,7 +186,7 @@ struct MatvecLayout {
 
 // Workspace of the dual-mesh system (bc_dual_*).
 struct DualLayout {
-  size_t area, diam, curl, f, mdiag, basis, w, t1, t2, t3, xt, bvec, yvec, dots, mv, total;
+  size_t area, diam, curl, f, mdiag, basis, wbas, ubas, w, t1, t2, t3, eta2, ones, bvec, yvec, dots, mv, total;
   int64_t nb;
   DualLayout(int64_t N, int64_t M, int32_t restart);
 };

@@ -186,6 +186,12 @@ __global__ void k_gs_update(const double *__restrict__ A, int64_t lda, const dou
   w[i] = s;
 }
 
+// out_i = v
+__global__ void k_fill(double v, int n, double *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = v;
+}
+
 // out_i = alpha * in_i
 __global__ void k_scale(const double *__restrict__ in, double alpha, int M, double *__restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -232,6 +238,11 @@ inline int blocks(int64_t n) { return (int)((n + kWG - 1) / kWG); }
 }  // namespace
 
 // ---------------------------------------------------------------- layout
+// dots: [0, restart) Gram-Schmidt inner products and norms; restart + 4:
+// a^T u of D_reg; [restart + 8, 2 restart + 8): a row of the energy Gram
+// matrix; 2 restart + 8: sum of eta^2; [2 restart + 9, 3 restart + 9): the
+// coefficients y of the current iterate.
+constexpr int64_t kDotsAu = 4, kDotsGram = 8;
 DualLayout::DualLayout(int64_t N, int64_t M, int32_t restart) {
   nb = 6 * N;
   size_t o = 0;
@@ -246,14 +257,17 @@ DualLayout::DualLayout(int64_t N, int64_t M, int32_t restart) {
   f = take(8 * M);
   mdiag = take(8 * M);
   basis = take(8 * (size_t)(restart + 1) * M);
+  wbas = take(8 * (size_t)restart * M);  // M^{-1} D_reg z_i
+  ubas = take(8 * (size_t)restart * M);  // V_dual M^{-1} D_reg z_i
   w = take(8 * M);
   t1 = take(8 * M);
   t2 = take(8 * M);
   t3 = take(8 * M);
-  xt = take(8 * M);
+  eta2 = take(8 * N);
+  ones = take(8 * N);
   bvec = take(8 * 4 * (size_t)nb);  // three curl components and the dual indicator
   yvec = take(8 * 4 * (size_t)nb);
-  dots = take(8 * (size_t)(restart + 8));
+  dots = take(8 * (size_t)(3 * restart + 16));
   mv = take(MatvecLayout(nb, BC_FP64, 3).total);
   total = o;
 }
@@ -267,24 +281,45 @@ int launch_dual_setup(const double *verts, const int32_t *tris, int64_t N, int64
                      reinterpret_cast<double *>(b + L.curl));
   hipLaunchKernelGGL(k_dual_vertex, dim3(blocks(M)), dim3(kWG), 0, s, iptr, itri, (int)M, (const double *)area,
                      reinterpret_cast<double *>(b + L.f), reinterpret_cast<double *>(b + L.mdiag));
+  hipLaunchKernelGGL(k_fill, dim3(blocks(N)), dim3(kWG), 0, s, 1.0, (int)N, reinterpret_cast<double *>(b + L.ones));
   return hipGetLastError() == hipSuccess ? BC_OK : BC_EDEVICE;
+}
+
+// y = R^{-1} g for the leading n x n upper triangle of the rotated Hessenberg
+// matrix (row stride m).
+static void back_substitute(const std::vector<double> &H, int m, const std::vector<double> &g, int n,
+                            std::vector<double> &y) {
+  y.assign(n, 0.0);
+  for (int q = n - 1; q >= 0; --q) {
+    double sum = g[q];
+    for (int c = q + 1; c < n; ++c) sum -= H[(size_t)q * m + c] * y[c];
+    y[q] = sum / H[(size_t)q * m + q];
+  }
 }
 
 // Host-driven GMRES (no restart within max_iter <= restart): Arnoldi with
 // classical Gram-Schmidt applied twice (all inner products of a pass in one
-// launch), Givens rotations on the host.
+// launch), Givens rotations on the host.  Besides the Krylov basis z_i it
+// keeps w_i = M^{-1} D_reg z_i and u_i = V_dual w_i, which the operator forms
+// anyway: the iterate is x_k = sum_i y_i w_i without a further product, and
+// the energy norm of an update x_k - x_{k-1} = sum_i dy_i w_i is
+// dy^T G dy with G_ij = w_i^T u_j, one new row of inner products per step.
 int run_dual_solve(const void *Vb, const int32_t *tris, int64_t N, int64_t M, const int32_t *iptr, const int32_t *itri,
                    const int32_t *icor, void *ws, const bc_dual_opts &o, double *x, bc_dual_result *res, hipStream_t s) {
   const DualLayout L(N, M, o.restart);
   char *b = static_cast<char *>(ws);
   auto D = [&](size_t off) { return reinterpret_cast<double *>(b + off); };
   const double *area = D(L.area), *diam = D(L.diam), *curl = D(L.curl), *f = D(L.f), *mdiag = D(L.mdiag);
-  (void)diam;
-  double *basis = D(L.basis), *w = D(L.w), *t1 = D(L.t1), *t2 = D(L.t2), *t3 = D(L.t3), *xt = D(L.xt);
+  double *basis = D(L.basis), *wbas = D(L.wbas), *ubas = D(L.ubas), *w = D(L.w), *t1 = D(L.t1), *t2 = D(L.t2),
+         *t3 = D(L.t3), *eta2 = D(L.eta2);
+  const double *ones = D(L.ones);
   double *bvec = D(L.bvec), *yvec = D(L.yvec), *dots = D(L.dots);
+  double *dots_au = dots + o.restart + kDotsAu, *dots_gram = dots + o.restart + kDotsGram;
+  double *dots_eta = dots + 2 * o.restart + kDotsGram, *dots_y = dots + 2 * o.restart + kDotsGram + 1;
   void *mvws = b + L.mv;
   const int64_t nb = L.nb;
-  const int gM = blocks(M), gB = blocks(nb);
+  const int gM = blocks(M), gB = blocks(nb), gN = blocks(N);
+  const bool inexact = o.inexact_lambda > 0.0;
   bool err = false;
   auto chk = [&]() { err = err || hipGetLastError() != hipSuccess; };
   // z = M^{-1} r by o.jacobi_sweeps Jacobi sweeps from z0 = r / diag (ping-pong t2/t3)
@@ -299,56 +334,60 @@ int run_dual_solve(const void *Vb, const int32_t *tris, int64_t N, int64_t M, co
     hipLaunchKernelGGL(k_scale, dim3(gM), dim3(kWG), 0, s, (const double *)cur, 1.0, (int)M, z);
     chk();
   };
-  // out = D_reg u
+  // out = D_reg u: the three curl components share one pass over V_bary
   auto dreg = [&](const double *u, double *out) {
     hipLaunchKernelGGL(k_dual_Q, dim3(gB), dim3(kWG), 0, s, u, tris, curl, (int)N, nb, bvec);
-    if (launch_matvec(BC_FP64, Vb, nb, 3, bvec, yvec, mvws, s) != BC_OK) err = true;  // one pass, three vectors
-    hipLaunchKernelGGL(k_multidot, dim3(1), dim3(kWG), 0, s, f, (int64_t)0, u, (int)M, dots + o.restart + 4);
+    if (launch_matvec(BC_FP64, Vb, nb, 3, bvec, yvec, mvws, s) != BC_OK) err = true;
+    hipLaunchKernelGGL(k_multidot, dim3(1), dim3(kWG), 0, s, f, (int64_t)0, u, (int)M, dots_au);
     hipLaunchKernelGGL(k_dual_QT, dim3(gM), dim3(kWG), 0, s, (const double *)yvec, nb, iptr, itri, icor, curl, f,
-                       (const double *)(dots + o.restart + 4), (int)M, out);
+                       (const double *)dots_au, (int)M, out);
     chk();
   };
-  // out = M^{-1} P^T V P u  (u already M^{-1}-applied by the caller)
+  // out = V_dual u = P^T V_bary P u
   auto vdual = [&](const double *u, double *out) {
     hipLaunchKernelGGL(k_dual_P, dim3(gB), dim3(kWG), 0, s, u, tris, (int)N, bvec + 3 * nb);
     if (launch_matvec(BC_FP64, Vb, nb, 1, bvec + 3 * nb, yvec + 3 * nb, mvws, s) != BC_OK) err = true;
     hipLaunchKernelGGL(k_dual_PT, dim3(gM), dim3(kWG), 0, s, (const double *)(yvec + 3 * nb), iptr, itri, icor,
-                       (int)M, t1);
-    minv(t1, out);
+                       (int)M, out);
+    chk();
   };
-  // out = M^{-1} V_dual M^{-1} D_reg u
-  auto op = [&](const double *u, double *out) {
-    dreg(u, t1);
-    minv(t1, w);
-    vdual(w, out);
-  };
-  auto host_dots = [&](int n, std::vector<double> &h) {
+  // asynchronous reads of device values; wait() makes them valid
+  auto read = [&](const double *src, int n, std::vector<double> &h) {
     h.resize(n);
-    if (hipMemcpyAsync(h.data(), dots, 8 * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      err = true;
+    if (hipMemcpyAsync(h.data(), src, 8 * (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess) err = true;
   };
-  auto put_dots = [&](const std::vector<double> &h) {
-    if (hipMemcpyAsync(dots, h.data(), 8 * h.size(), hipMemcpyHostToDevice, s) != hipSuccess) err = true;
+  auto wait = [&]() {
+    if (hipStreamSynchronize(s) != hipSuccess) err = true;
   };
-
   const int m = o.max_iter;
-  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), h;
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), h, hg, he, G((size_t)m * m, 0.0);
+  std::vector<double> y, yprev;
   // rhs = M^{-1} f, v0 = rhs / |rhs|
   minv(f, w);
   hipLaunchKernelGGL(k_multidot, dim3(1), dim3(kWG), 0, s, (const double *)w, (int64_t)0, (const double *)w, (int)M, dots);
-  host_dots(1, h);
+  read(dots, 1, h);
+  wait();
   if (err) return BC_EDEVICE;
   const double beta = sqrt(h[0]);
   if (!(beta > 0.0)) return BC_EINVAL;
   hipLaunchKernelGGL(k_scale, dim3(gM), dim3(kWG), 0, s, (const double *)w, 1.0 / beta, (int)M, basis);
   g[0] = beta;
   int k = 0;
-  double rel = 1.0;
-  int status = BC_ENOCONV;
+  double rel = 1.0, energy = 0.0, eta = 0.0;
+  int status = BC_ENOCONV, stop = 0;
   for (; k < m; ++k) {
-    double *vk = basis + (size_t)k * M;
-    op(vk, w);
+    const double *vk = basis + (size_t)k * M;
+    double *wk = wbas + (size_t)k * M, *uk = ubas + (size_t)k * M;
+    // w_k = M^{-1} D_reg z_k, u_k = V_dual w_k, Arnoldi vector M^{-1} u_k
+    dreg(vk, t1);
+    minv(t1, wk);
+    vdual(wk, uk);
+    minv(uk, w);
+    if (inexact) {
+      hipLaunchKernelGGL(k_multidot, dim3(k + 1), dim3(kWG), 0, s, (const double *)ubas, (int64_t)M,
+                         (const double *)wk, (int)M, dots_gram);
+      read(dots_gram, k + 1, hg);
+    }
     // two passes of classical Gram-Schmidt against v_0 .. v_k
     std::vector<double> hk(k + 2, 0.0);
     for (int pass = 0; pass < 2; ++pass) {
@@ -356,13 +395,17 @@ int run_dual_solve(const void *Vb, const int32_t *tris, int64_t N, int64_t M, co
                          (const double *)w, (int)M, dots);
       hipLaunchKernelGGL(k_gs_update, dim3(gM), dim3(kWG), 0, s, (const double *)basis, (int64_t)M,
                          (const double *)dots, k + 1, (int)M, w);
-      host_dots(k + 1, h);
+      read(dots, k + 1, h);
+      wait();
       for (int q = 0; q <= k; ++q) hk[q] += h[q];
     }
     hipLaunchKernelGGL(k_multidot, dim3(1), dim3(kWG), 0, s, (const double *)w, (int64_t)0, (const double *)w, (int)M,
                        dots);
-    host_dots(1, h);
+    read(dots, 1, h);
+    wait();
     if (err) return BC_EDEVICE;
+    if (inexact)
+      for (int q = 0; q <= k; ++q) G[(size_t)k * m + q] = G[(size_t)q * m + k] = hg[q];
     hk[k + 1] = sqrt(h[0]);
     // previous rotations, then a new one that zeroes hk[k+1]
     for (int q = 0; q < k; ++q) {
@@ -380,12 +423,33 @@ int run_dual_solve(const void *Vb, const int32_t *tris, int64_t N, int64_t M, co
     g[k] = cs[k] * g[k];
     for (int q = 0; q <= k; ++q) H[(size_t)q * m + k] = hk[q];
     rel = fabs(g[k + 1]) / beta;
-    if (rel <= o.rtol) {
-      status = BC_OK;
-      ++k;
-      break;
+    if (rel <= o.rtol) stop = 1;
+    else if (!(hn > 0.0)) stop = 3;  // exact invariant subspace
+    if (inexact) {
+      // x_k and its update's energy norm; eta(x_k) from the ZZ indicators
+      back_substitute(H, m, g, k + 1, y);
+      double e2 = 0.0;
+      for (int i = 0; i <= k; ++i) {
+        const double di = y[i] - (i < (int)yprev.size() ? yprev[i] : 0.0);
+        for (int j = 0; j <= k; ++j) e2 += di * G[(size_t)i * m + j] * (y[j] - (j < (int)yprev.size() ? yprev[j] : 0.0));
+      }
+      if (hipMemcpyAsync(dots_y, y.data(), 8 * (size_t)(k + 1), hipMemcpyHostToDevice, s) != hipSuccess) err = true;
+      hipLaunchKernelGGL(k_combine, dim3(gM), dim3(kWG), 0, s, (const double *)wbas, (int64_t)M,
+                         (const double *)dots_y, k + 1, (int)M, x);
+      hipLaunchKernelGGL(k_dual_zz, dim3(gN), dim3(kWG), 0, s, (const double *)x, tris, area, diam, (int)N, o.h_mode,
+                         eta2);
+      hipLaunchKernelGGL(k_multidot, dim3(1), dim3(kWG), 0, s, (const double *)eta2, (int64_t)0, ones, (int)N,
+                         dots_eta);
+      read(dots_eta, 1, he);
+      wait();
+      chk();
+      if (err) return BC_EDEVICE;
+      energy = sqrt(e2 > 0.0 ? e2 : 0.0);
+      eta = sqrt(he[0] > 0.0 ? he[0] : 0.0);
+      yprev = y;
+      if (stop == 0 && energy <= o.inexact_lambda * eta) stop = 2;
     }
-    if (!(hn > 0.0)) {  // exact invariant subspace
+    if (stop != 0) {
       status = BC_OK;
       ++k;
       break;
@@ -393,26 +457,25 @@ int run_dual_solve(const void *Vb, const int32_t *tris, int64_t N, int64_t M, co
     if (k + 1 < m) hipLaunchKernelGGL(k_scale, dim3(gM), dim3(kWG), 0, s, (const double *)w, 1.0 / hn, (int)M,
                                       basis + (size_t)(k + 1) * M);
   }
-  // y = H^{-1} g (upper triangular, k x k), x~ = V y, x = M^{-1} D_reg x~
-  std::vector<double> y(k, 0.0);
-  for (int q = k - 1; q >= 0; --q) {
-    double sum = g[q];
-    for (int c = q + 1; c < k; ++c) sum -= H[(size_t)q * m + c] * y[c];
-    y[q] = sum / H[(size_t)q * m + q];
-  }
-  put_dots(y);
-  hipLaunchKernelGGL(k_combine, dim3(gM), dim3(kWG), 0, s, (const double *)basis, (int64_t)M, (const double *)dots, k,
-                     (int)M, xt);
-  dreg(xt, t1);
-  minv(t1, x);
+  // x = sum_i y_i w_i with y = R^{-1} g (k x k)
+  back_substitute(H, m, g, k, y);
+  if (hipMemcpyAsync(dots_y, y.data(), 8 * (size_t)k, hipMemcpyHostToDevice, s) != hipSuccess) err = true;
+  hipLaunchKernelGGL(k_combine, dim3(gM), dim3(kWG), 0, s, (const double *)wbas, (int64_t)M, (const double *)dots_y, k,
+                     (int)M, x);
   // Cap = (1/4pi) f^T x
   hipLaunchKernelGGL(k_multidot, dim3(1), dim3(kWG), 0, s, f, (int64_t)0, (const double *)x, (int)M, dots);
-  host_dots(1, h);
+  read(dots, 1, h);
+  wait();
+  chk();
   if (err) return BC_EDEVICE;
   res->cap = h[0] * kInv4Pi;
   res->rel_residual = rel;
+  res->energy_step = inexact ? energy : 0.0;
+  res->eta = inexact ? eta : 0.0;
   res->iters = k;
   res->status = status;
+  res->stop = stop;
+  res->reserved = 0;
   return BC_OK;
 }
 

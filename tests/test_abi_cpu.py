@@ -124,4 +124,10 @@ def test_argument_errors_without_device(L):
     assert L.bc_capacity(null, null, 5, null, null) == -1
     assert L.bc_matvec(C.c_void_p(16), 100, 0, 2, C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), 1 << 30,
                        null) == -1
+    # dual solve options: negative lambda and unknown h_mode are argument errors
+    res = _lib.bc_dual_result()
+    v = C.c_void_p(16)
+    for o in (_lib.bc_dual_opts(1e-10, -1.0, 10, 20, 30, 1), _lib.bc_dual_opts(1e-10, 1e-3, 10, 20, 30, 2),
+              _lib.bc_dual_opts(1e-10, 0.0, 30, 20, 30, 1)):
+        assert L.bc_dual_solve(v, v, 100, 60, v, v, v, v, 1 << 40, C.byref(o), v, C.byref(res), null) == -1
     assert L.bc_matvec(C.c_void_p(16), 100, 0, 3, C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), 10, null) == -3

@@ -175,3 +175,44 @@ def test_fichera_first_step(api):
     xref, _ = odual.solve_dual(Vb, P, f)
     assert abs(r.cap - odual.capacity_dual(xref, f)) <= 1e-12 * r.cap
     assert np.allclose(eta2, odual.zz_dual(m.verts, m.tris, xref, "area"), rtol=1e-9)
+
+
+@pytest.mark.parametrize("lam", [1e-3, 3e-2])
+def test_inexact_stop(api, lam):
+    """Section 2.5, Remark (i): GMRES stops at the first step k with
+    ||x_k - x_{k-1}||_V <= lambda eta(x_k).  The reported energy norm and
+    estimator are checked against the oracle's V_dual and ZZ on the iterates
+    x_{k-2}, x_{k-1}, x_k (the same GMRES run cut after k-2, k-1 and k
+    steps); the criterion holds at k and fails at k - 1."""
+    m = synth.voxel_union(2, 0.4, 7)
+    Vb, P, bv, bt = odual.assemble_dual(m.verts, m.tris)
+    Vd = P.T @ Vb @ P
+    p = api.DualProblem(m.verts, m.tris, restart=60)
+    p.assemble()
+    r = p.solve(rtol=1e-14, inexact_lambda=lam, h_mode=1)
+    _flush(f"lambda {lam}: stop {r.stop} after {r.iters} steps, energy {r.energy_step:.3e} eta {r.eta:.3e}")
+    assert r.ok and r.stop == 2
+    k = r.iters
+    assert k >= 2
+    xs = {k: p.x.cpu().numpy().copy()}
+    for kk in (k - 1, k - 2):
+        rr = p.solve(rtol=1e-14, max_iter=kk) if kk > 0 else None
+        xs[kk] = p.x.cpu().numpy().copy() if kk > 0 else np.zeros(m.verts.shape[0])
+        if rr is not None:
+            assert rr.iters == kk
+    # the same k steps without the inexact stop give the same iterate
+    rk = p.solve(rtol=1e-14, max_iter=k)
+    assert np.array_equal(p.x.cpu().numpy(), xs[k]) and rk.iters == k
+
+    def energy(a, b):
+        d = a - b
+        return float(np.sqrt(d @ Vd @ d))
+
+    def eta(x):
+        return float(np.sqrt(odual.zz_dual(m.verts, m.tris, x, "area").sum()))
+
+    ek, ek1 = energy(xs[k], xs[k - 1]), energy(xs[k - 1], xs[k - 2])
+    assert abs(r.energy_step - ek) <= 1e-6 * ek + 1e-14
+    assert abs(r.eta - eta(xs[k])) <= 1e-10 * r.eta
+    assert ek <= lam * eta(xs[k]) * (1 + 1e-9)
+    assert ek1 > lam * eta(xs[k - 1])
