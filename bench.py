@@ -280,7 +280,7 @@ def dual_mode(a):
     t0 = synth.init_reference_edges(m.verts, m.tris)
     w0 = time.perf_counter()
     steps = adaptive_dual(m.verts, t0, steps=1000, theta=0.5, h_mode=1, rtol=1e-10, max_elements=a.dual_max_n,
-                          keep=True, inexact_lambda=a.inexact_lambda)
+                          keep=True, inexact_lambda=a.inexact_lambda, precision=a.dual_precision)
     wall = time.perf_counter() - w0
     rows = []
     for s in steps:
@@ -294,10 +294,11 @@ def dual_mode(a):
         log(f"l={s.level} N={s.N} cap={s.cap:.10f} eta2={s.eta2:.3e} gmres={s.iters} "
             f"asm {s.t_assemble_ms:.1f} ms solve {s.t_solve_ms:.1f} ms")
     last = steps[-1]
-    p = api.DualProblem(last.verts, last.tris)
+    p = api.DualProblem(last.verts, last.tris, precision=a.dual_precision)
     p.assemble()
     nb = 6 * last.N
-    mv = {"N_bary": nb}
+    elem = 8 if a.dual_precision == "fp64" else 4
+    mv = {"N_bary": nb, "matrix": "fp64" if elem == 8 else "fp32 (fp64 vectors)"}
     for nr in (1, 3):
         x = torch.randn((nr, nb) if nr > 1 else (nb,), dtype=torch.float64, device="cuda")
         for _ in range(2):
@@ -311,9 +312,10 @@ def dual_mode(a):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        gbs = half_matrix_bytes(nb, 8) / (ms * 1e-3) / 1e9
+        gbs = half_matrix_bytes(nb, elem) / (ms * 1e-3) / 1e9
         mv[f"nrhs{nr}"] = {"ms": round(ms, 3), "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 3)}
-    print(json.dumps({"mode": "dual", "workload": desc, "inexact_lambda": a.inexact_lambda, "steps": rows,
+    print(json.dumps({"mode": "dual", "workload": desc, "precision": a.dual_precision,
+                      "inexact_lambda": a.inexact_lambda, "steps": rows,
                       "wall_s": round(wall, 2), "bary_matvec": mv}))
 
 
@@ -417,6 +419,8 @@ def main():
     ap.add_argument("--dual", choices=sorted(DUAL_WORKLOADS), default=None,
                     help="Algorithm 1 in dual mode on the unit cube (Table 1) or the Fichera cube (Table 2)")
     ap.add_argument("--dual-max-n", type=int, default=12000)
+    ap.add_argument("--dual-precision", default="fp64", choices=["fp64", "mixed"],
+                    help="dual mode: V_bary in FP64, or FP32 with FP64 corrections of touching and near entries")
     ap.add_argument("--inexact-lambda", type=float, default=0.0,
                     help="dual mode: stop GMRES when the energy of its update is below lambda x the estimator")
     ap.add_argument("--ss-order", type=int, default=4, help="--adaptive-cube: Gauss points per coordinate of the "

@@ -56,10 +56,13 @@ typedef enum bc_status {
 
 typedef enum bc_precision {
   BC_FP64 = 0,  /* FP64 matrix, FP64 Krylov iterations */
-  BC_MIXED = 1  /* FP32 matrix (far field computed in FP32, touching and
+  BC_MIXED = 1, /* FP32 matrix (far field computed in FP32, touching and
                    near pairs computed in FP64 and kept as an FP64 sparse
                    correction), FP32 CG with FP32 accumulation inside FP64
                    iterative refinement of the residual b - V sigma */
+  BC_F32_F64 = 2 /* bc_matvec only: the FP32 matrix of a BC_MIXED assembly
+                   applied to FP64 vectors with FP64 sums (the dense part
+                   of the mixed dual system's products) */
 } bc_precision;
 
 /* ------------------------------------------------------------------------ */
@@ -279,7 +282,9 @@ size_t bc_matvec_workspace_bytes(int64_t N, int32_t precision, int32_t nrhs);
  * the diagonal 128 x 128 blocks and the entries right of them are read,
  * V being symmetric).  X and Y hold nrhs vectors of N entries one after the
  * other; all of them share one pass over V.  BC_FP64: V, X, Y are FP64,
- * nrhs 1 or 3; BC_MIXED: FP32 (products accumulated in FP32), nrhs 1.
+ * nrhs 1 or 3; BC_MIXED: FP32 (products accumulated in FP32), nrhs 1;
+ * BC_F32_F64: FP32 V, FP64 X and Y (FP64 sums), nrhs 1 or 3.  The FP64
+ * correction of a mixed matrix's touching and near entries is not applied.
  * Fixed summation order: the result depends on N (and nrhs) only.  d_x and
  * d_y must not overlap.  BC_EINVAL for other nrhs.  ASYNC. */
 int32_t bc_matvec(const void *d_V, int64_t N, int32_t precision, int32_t nrhs,
@@ -354,11 +359,19 @@ int32_t bc_dual_setup(const double *d_verts, int64_t M, const int32_t *d_tris,
  * iteration count and status to *h_result.  x is formed as the combination
  * of the preconditioned basis vectors M^{-1} D_reg z_i, kept during the
  * iteration, which also gives every iterate's energy-norm update for the
- * inexact stop without further products.  Host-driven: SYNCHRONOUS (waits
- * for `stream` a few times per GMRES step).  Errors: BC_EINVAL for bad
+ * inexact stop without further products.  precision BC_FP64: d_Vbary is
+ * the FP64 matrix (d_pattern unused); BC_MIXED: d_Vbary is the FP32 matrix
+ * of a mixed bc_assemble and d_pattern / nnz its pattern, whose FP64
+ * corrections of the touching and near entries are added to every product;
+ * products are formed with FP64 vectors and sums, so GMRES solves
+ * (V32 + C64) exactly and the capacity differs from the FP64 one by the
+ * solution-weighted rounding of the stored far field only.  Host-driven:
+ * SYNCHRONOUS (waits for `stream` a few times per GMRES step).  Errors: BC_EINVAL for bad
  * options or sizes, BC_ENOMEM for a short workspace. */
-int32_t bc_dual_solve(const double *d_Vbary, const int32_t *d_tris, int64_t N,
-                      int64_t M, const int32_t *d_iptr, const int32_t *d_itri,
+int32_t bc_dual_solve(const void *d_Vbary, int32_t precision,
+                      const void *d_pattern, int64_t nnz,
+                      const int32_t *d_tris, int64_t N, int64_t M,
+                      const int32_t *d_iptr, const int32_t *d_itri,
                       const int32_t *d_icor, void *d_ws, size_t ws_bytes,
                       const bc_dual_opts *opts, double *d_x,
                       bc_dual_result *h_result, bc_stream stream);

@@ -25,6 +25,7 @@ BC_RUNNING = 1
 
 BC_FP64 = 0
 BC_MIXED = 1
+BC_F32_F64 = 2
 
 
 class bc_assembly_opts(C.Structure):
@@ -94,7 +95,8 @@ SIGNATURES = {
     "bc_matvec": (I32, [P, I64, I32, I32, P, P, P, SZ, P]),
     "bc_dual_workspace_bytes": (SZ, [I64, I64, I32]),
     "bc_dual_setup": (I32, [P, I64, P, I64, P, P, P, SZ, I32, P]),
-    "bc_dual_solve": (I32, [P, P, I64, I64, P, P, P, P, SZ, C.POINTER(bc_dual_opts), P, C.POINTER(bc_dual_result), P]),
+    "bc_dual_solve": (I32, [P, I32, P, I64, P, I64, I64, P, P, P, P, SZ, C.POINTER(bc_dual_opts), P,
+                            C.POINTER(bc_dual_result), P]),
     "bc_dual_zz": (I32, [P, SZ, P, I64, I64, I32, P, I32, P, P]),
 }
 

@@ -117,7 +117,7 @@ def adaptive_capacity(verts, tris, steps: int = 5, theta: float = 0.5, precision
 def adaptive_dual(verts, tris, steps: int = 5, theta: float = 0.5, h_mode: int = 1, rtol: float = 1e-10,
                   max_elements: Optional[int] = None, keep: bool = False, far_order: int = 4, ss_order: int = 4,
                   jacobi_sweeps: int = 30, restart: int = 200, refine: str = "bisec1",
-                  inexact_lambda: float = 0.0) -> List[Step]:
+                  inexact_lambda: float = 0.0, precision: str = "fp64") -> List[Step]:
     """Algorithm 1 as stated: (i) the Galerkin solution on the dual mesh,
     computed from V on the barycentric refinement by GMRES with the
     hypersingular operator as preconditioner (Section 2.6); (ii) the ZZ
@@ -130,7 +130,9 @@ def adaptive_dual(verts, tris, steps: int = 5, theta: float = 0.5, h_mode: int =
     meshes (each solve starts from zero).  refine as in adaptive_capacity.
     inexact_lambda > 0 couples the solver to the estimator (Section 2.5,
     Remark (i)): GMRES also stops once the energy norm of its last update is
-    at most inexact_lambda times the estimator of the current iterate."""
+    at most inexact_lambda times the estimator of the current iterate.
+    precision "mixed" stores V_bary in FP32 with FP64 corrections of the
+    touching and near entries (half the memory, about twice as fast)."""
     from .api import DualProblem
 
     verts = np.asarray(verts, dtype=np.float64)
@@ -138,7 +140,7 @@ def adaptive_dual(verts, tris, steps: int = 5, theta: float = 0.5, h_mode: int =
     out: List[Step] = []
     for level in range(steps + 1):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        prob = DualProblem(verts, tris, far_order=far_order, ss_order=ss_order, restart=restart)
+        prob = DualProblem(verts, tris, far_order=far_order, ss_order=ss_order, restart=restart, precision=precision)
         ev[0].record()
         prob.assemble()
         ev[1].record()

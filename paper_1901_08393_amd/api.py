@@ -211,20 +211,26 @@ class CapacityProblem:
 
 def matvec(problem: "CapacityProblem", x: torch.Tensor, stream=None) -> torch.Tensor:
     """y = V x with the problem's assembled matrix (bc_matvec): the symmetric
-    product of the solver as a standalone call.  x has N entries in the
-    matrix precision, or shape (k, N) for k vectors that share one pass over
-    V (FP64: k = 1 or 3)."""
+    product of the solver as a standalone call.  x has N entries, or shape
+    (k, N) for k vectors that share one pass over V (k = 1 or 3 with FP64
+    vectors).  x in the matrix precision, or FP64 with a mixed problem's
+    FP32 matrix (FP64 sums; the sparse FP64 correction is not applied)."""
     L = lib()
     nr = 1 if x.dim() == 1 else int(x.shape[0])
-    if x.shape[-1] != problem.N or x.dtype != problem.matrix_dtype or not x.is_contiguous():
-        raise ValueError("x: contiguous, N entries per vector, matrix precision")
-    nb = L.bc_matvec_workspace_bytes(problem.N, problem.prec, nr)
+    prec = problem.prec
+    if problem.precision == "mixed" and x.dtype == torch.float64:
+        prec = _lib.BC_F32_F64
+    elif x.dtype != problem.matrix_dtype:
+        raise ValueError("x: the matrix precision, or FP64 with a mixed problem")
+    if x.shape[-1] != problem.N or not x.is_contiguous():
+        raise ValueError("x: contiguous, N entries per vector")
+    nb = L.bc_matvec_workspace_bytes(problem.N, prec, nr)
     if nb == 0:
         raise ValueError(f"bc_matvec: {nr} vectors not supported in this precision")
     ws = torch.empty(nb, dtype=torch.uint8, device=problem.device)
     y = torch.empty_like(x)
-    check("bc_matvec", L.bc_matvec(_ptr(problem.V), problem.N, problem.prec, nr, _ptr(x), _ptr(y), _ptr(ws),
-                                   ws.numel(), _stream(stream)))
+    check("bc_matvec", L.bc_matvec(_ptr(problem.V), problem.N, prec, nr, _ptr(x), _ptr(y), _ptr(ws), ws.numel(),
+                                   _stream(stream)))
     return y
 
 
@@ -245,12 +251,14 @@ class DualResult:
 
 class DualProblem:
     """The paper's dual-mesh Galerkin system (Algorithm 1, step (i)): V on
-    the barycentric refinement (FP64, assembled by the library like any
-    mesh), the unknowns on the dual cells of the vertices, solved by GMRES
-    with the hypersingular operator as preconditioner (Section 2.6)."""
+    the barycentric refinement (FP64, or FP32 with FP64 corrections of the
+    touching and near entries for precision="mixed", assembled by the
+    library like any mesh), the unknowns on the dual cells of the vertices,
+    solved by GMRES with the hypersingular operator as preconditioner
+    (Section 2.6); vectors and sums are FP64 in both precisions."""
 
     def __init__(self, verts, tris, far_order: int = 4, ss_order: int = 4, restart: int = 200, device: str = "cuda",
-                 stream=None):
+                 stream=None, precision: str = "fp64"):
         import synth
 
         L = lib()
@@ -263,8 +271,10 @@ class DualProblem:
         self.restart = int(restart)
         self.device = torch.device(device)
         bary, _, _ = synth.barycentric(verts, tris)
-        self.bary = CapacityProblem(bary.verts, bary.tris, "fp64", far_order, ss_order, device=device, validate=False,
-                                    stream=stream)
+        # V_bary in FP64, or FP32 with the FP64 correction of touching and near entries
+        self.precision = precision
+        self.bary = CapacityProblem(bary.verts, bary.tris, precision, far_order, ss_order, device=device,
+                                    validate=False, stream=stream)
         iptr, itri, icor = synth.vertex_incidence(tris, self.M)
         self.d_verts = torch.from_numpy(verts).to(self.device)
         self.d_tris = torch.from_numpy(tris).to(self.device)
@@ -294,7 +304,8 @@ class DualProblem:
             raise RuntimeError("assemble() first")
         o = _lib.bc_dual_opts(rtol, inexact_lambda, int(max_iter or self.restart), self.restart, jacobi_sweeps, h_mode)
         r = _lib.bc_dual_result()
-        check("bc_dual_solve", lib().bc_dual_solve(_ptr(self.bary.V), _ptr(self.d_tris), self.N, self.M,
+        check("bc_dual_solve", lib().bc_dual_solve(_ptr(self.bary.V), self.bary.prec, _ptr(self.bary.pattern),
+                                                   self.bary.nnz, _ptr(self.d_tris), self.N, self.M,
                                                    _ptr(self.d_iptr), _ptr(self.d_itri), _ptr(self.d_icor),
                                                    _ptr(self.ws), self.ws.numel(), C.byref(o), _ptr(self.x),
                                                    C.byref(r), _stream(stream)))

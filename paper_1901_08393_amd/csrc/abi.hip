@@ -320,7 +320,8 @@ int32_t bc_zz_indicators(const int32_t *d_tris, int64_t N, const void *d_mesh_ws
 }
 
 static bool matvec_ok(int64_t N, int32_t precision, int32_t nrhs) {
-  return n_ok(N) && ((precision == BC_FP64 && (nrhs == 1 || nrhs == 3)) || (precision == BC_MIXED && nrhs == 1));
+  return n_ok(N) && (((precision == BC_FP64 || precision == BC_F32_F64) && (nrhs == 1 || nrhs == 3)) ||
+                     (precision == BC_MIXED && nrhs == 1));
 }
 
 size_t bc_matvec_workspace_bytes(int64_t N, int32_t precision, int32_t nrhs) {
@@ -353,18 +354,21 @@ int32_t bc_dual_setup(const double *d_verts, int64_t M, const int32_t *d_tris, i
   return launch_dual_setup(d_verts, d_tris, N, M, d_iptr, d_itri, d_ws, restart, static_cast<hipStream_t>(stream));
 }
 
-int32_t bc_dual_solve(const double *d_Vbary, const int32_t *d_tris, int64_t N, int64_t M, const int32_t *d_iptr,
-                      const int32_t *d_itri, const int32_t *d_icor, void *d_ws, size_t ws_bytes,
-                      const bc_dual_opts *opts, double *d_x, bc_dual_result *h_result, bc_stream stream) {
+int32_t bc_dual_solve(const void *d_Vbary, int32_t precision, const void *d_pattern, int64_t nnz,
+                      const int32_t *d_tris, int64_t N, int64_t M, const int32_t *d_iptr, const int32_t *d_itri,
+                      const int32_t *d_icor, void *d_ws, size_t ws_bytes, const bc_dual_opts *opts, double *d_x,
+                      bc_dual_result *h_result, bc_stream stream) {
   if (!d_Vbary || !d_tris || !d_iptr || !d_itri || !d_icor || !d_ws || !opts || !d_x || !h_result) return BC_EINVAL;
+  if (precision != BC_FP64 && precision != BC_MIXED) return BC_EINVAL;
+  if (precision == BC_MIXED && (!d_pattern || nnz < 0)) return BC_EINVAL;
   if (!dual_sizes_ok(N, M, opts->restart)) return BC_EINVAL;
   if (!(opts->rtol > 0.0) || !std::isfinite(opts->rtol) || opts->max_iter < 1 || opts->max_iter > opts->restart ||
       opts->jacobi_sweeps < 0 || opts->jacobi_sweeps > 1000 || (opts->h_mode != 0 && opts->h_mode != 1) ||
       !(opts->inexact_lambda >= 0.0) || !std::isfinite(opts->inexact_lambda))
     return BC_EINVAL;
   if (ws_bytes < DualLayout(N, M, opts->restart).total) return BC_ENOMEM;
-  return run_dual_solve(d_Vbary, d_tris, N, M, d_iptr, d_itri, d_icor, d_ws, *opts, d_x, h_result,
-                        static_cast<hipStream_t>(stream));
+  return run_dual_solve(d_Vbary, precision, d_pattern, nnz, d_tris, N, M, d_iptr, d_itri, d_icor, d_ws, *opts, d_x,
+                        h_result, static_cast<hipStream_t>(stream));
 }
 
 int32_t bc_dual_zz(const void *d_ws, size_t ws_bytes, const int32_t *d_tris, int64_t N, int64_t M, int32_t restart,

@@ -160,15 +160,20 @@ struct SolveLayout {
   }
 };
 
+// Product kind of an FP32 matrix with FP64 vectors.
+constexpr int32_t kMatvecF32X64 = BC_F32_F64;
+
 // Workspace of a standalone product y = V x (bc_matvec): x padded to ld
 // with zeros, then the partial sums of the symmetric product.
 struct MatvecLayout {
   size_t xpad, rpart, cpart, total;
   int64_t ld, nB, T;
   int k;
-  __host__ __device__ MatvecLayout(int64_t N, int32_t precision, int nr = 1) {
+  // kind: BC_FP64, BC_MIXED (FP32 matrix and vectors) or kMatvecF32X64
+  // (FP32 matrix, FP64 vectors); k = chunk width / 64
+  __host__ __device__ MatvecLayout(int64_t N, int32_t kind, int nr = 1) {
     ld = (N + 63) / 64 * 64;
-    k = precision == BC_FP64 ? (nr > 1 ? 1 : 2) : 4;  // chunk width / 64
+    k = kind == BC_MIXED ? 4 : (nr > 1 ? 1 : 2);
     nB = (N + kRB - 1) / kRB;
     T = half_units_before(nB, ld / 64, k);
     size_t o = 0;
@@ -330,14 +335,18 @@ int launch_capacity(const double *sigma, const double *area, int64_t N, double *
 int launch_solve(int32_t precision, const SysDesc *d_desc, int n_sys, int total_wg, const SolveParams &p,
                  hipStream_t s);
 int solve_capacity(int32_t precision);
-// Y = V X for nr vectors stored one after the other (N entries each): FP64
-// with nr = 1 or 3, mixed (FP32) with nr = 1.  ws: MatvecLayout(N, precision, nr).
-int launch_matvec(int32_t precision, const void *V, int64_t N, int nr, const void *x, void *y, void *ws,
-                  hipStream_t s);
+// Y = V X for nr vectors stored one after the other (N entries each): kind
+// BC_FP64 with nr = 1 or 3, BC_MIXED (FP32 matrix and vectors) with nr = 1,
+// kMatvecF32X64 (FP32 matrix, FP64 vectors and sums) with nr = 1 or 3.
+// ws: MatvecLayout(N, kind, nr).
+int launch_matvec(int32_t kind, const void *V, int64_t N, int nr, const void *x, void *y, void *ws, hipStream_t s);
 int launch_dual_setup(const double *verts, const int32_t *tris, int64_t N, int64_t M, const int32_t *iptr,
                       const int32_t *itri, void *ws, int32_t restart, hipStream_t s);
-int run_dual_solve(const void *Vb, const int32_t *tris, int64_t N, int64_t M, const int32_t *iptr, const int32_t *itri,
-                   const int32_t *icor, void *ws, const bc_dual_opts &o, double *x, bc_dual_result *res, hipStream_t s);
+// V_bary: FP64 (precision BC_FP64) or FP32 plus the FP64 correction of the
+// pattern's entries (BC_MIXED; pattern = the bc_assemble pattern buffer).
+int run_dual_solve(const void *Vb, int32_t precision, const void *pattern, int64_t nnz, const int32_t *tris, int64_t N,
+                   int64_t M, const int32_t *iptr, const int32_t *itri, const int32_t *icor, void *ws,
+                   const bc_dual_opts &o, double *x, bc_dual_result *res, hipStream_t s);
 int launch_dual_zz(const void *ws, const int32_t *tris, int64_t N, int64_t M, int32_t restart, const double *x,
                    int h_mode, double *eta2, hipStream_t s);
 int solve_workgroups(int64_t N);

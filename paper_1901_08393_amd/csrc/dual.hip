@@ -19,6 +19,7 @@
 // count; the count only sets the quality of the preconditioner.  Each GMRES
 // step makes four products with V_bary (three curl components, one dual
 // indicator).  Every reduction has a fixed order.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -186,6 +187,25 @@ __global__ void k_gs_update(const double *__restrict__ A, int64_t lda, const dou
   w[i] = s;
 }
 
+// y_m[i] += sum_e corr[e] x_m[col[e]] over row i of the pattern (e
+// ascending), for the NR vectors at stride n: the FP64 correction of the
+// touching and near entries of an FP32 matrix.
+template <int NR>
+__global__ void k_csr_add(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                          const double *__restrict__ corr, int n, int64_t stride, const double *__restrict__ x,
+                          double *__restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc[NR];
+  for (int m = 0; m < NR; ++m) acc[m] = y[m * stride + i];
+  for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+    const double c = corr[e];
+    const int j = col[e];
+    for (int m = 0; m < NR; ++m) acc[m] = fma(c, x[m * stride + j], acc[m]);
+  }
+  for (int m = 0; m < NR; ++m) y[m * stride + i] = acc[m];
+}
+
 // out_i = v
 __global__ void k_fill(double v, int n, double *__restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -268,7 +288,10 @@ DualLayout::DualLayout(int64_t N, int64_t M, int32_t restart) {
   bvec = take(8 * 4 * (size_t)nb);  // three curl components and the dual indicator
   yvec = take(8 * 4 * (size_t)nb);
   dots = take(8 * (size_t)(3 * restart + 16));
-  mv = take(MatvecLayout(nb, BC_FP64, 3).total);
+  size_t mvb = 0;  // the largest product scratch of the FP64 and the FP32-matrix kinds
+  for (int32_t kind : {(int32_t)BC_FP64, kMatvecF32X64})
+    for (int nr : {1, 3}) mvb = std::max(mvb, MatvecLayout(nb, kind, nr).total);
+  mv = take(mvb);
   total = o;
 }
 
@@ -304,9 +327,17 @@ static void back_substitute(const std::vector<double> &H, int m, const std::vect
 // anyway: the iterate is x_k = sum_i y_i w_i without a further product, and
 // the energy norm of an update x_k - x_{k-1} = sum_i dy_i w_i is
 // dy^T G dy with G_ij = w_i^T u_j, one new row of inner products per step.
-int run_dual_solve(const void *Vb, const int32_t *tris, int64_t N, int64_t M, const int32_t *iptr, const int32_t *itri,
-                   const int32_t *icor, void *ws, const bc_dual_opts &o, double *x, bc_dual_result *res, hipStream_t s) {
+int run_dual_solve(const void *Vb, int32_t precision, const void *pattern, int64_t nnz, const int32_t *tris, int64_t N,
+                   int64_t M, const int32_t *iptr, const int32_t *itri, const int32_t *icor, void *ws,
+                   const bc_dual_opts &o, double *x, bc_dual_result *res, hipStream_t s) {
   const DualLayout L(N, M, o.restart);
+  const bool mixed = precision == BC_MIXED;
+  const int32_t kind = mixed ? kMatvecF32X64 : (int32_t)BC_FP64;
+  const PatternLayout PL(6 * N, nnz, BC_MIXED);
+  const char *pb = static_cast<const char *>(pattern);
+  const int32_t *prow = mixed ? reinterpret_cast<const int32_t *>(pb + PL.rowptr) : nullptr;
+  const int32_t *pcol = mixed ? reinterpret_cast<const int32_t *>(pb + PL.col) : nullptr;
+  const double *pcorr = mixed ? reinterpret_cast<const double *>(pb + PL.corr) : nullptr;
   char *b = static_cast<char *>(ws);
   auto D = [&](size_t off) { return reinterpret_cast<double *>(b + off); };
   const double *area = D(L.area), *diam = D(L.diam), *curl = D(L.curl), *f = D(L.f), *mdiag = D(L.mdiag);
@@ -337,7 +368,10 @@ int run_dual_solve(const void *Vb, const int32_t *tris, int64_t N, int64_t M, co
   // out = D_reg u: the three curl components share one pass over V_bary
   auto dreg = [&](const double *u, double *out) {
     hipLaunchKernelGGL(k_dual_Q, dim3(gB), dim3(kWG), 0, s, u, tris, curl, (int)N, nb, bvec);
-    if (launch_matvec(BC_FP64, Vb, nb, 3, bvec, yvec, mvws, s) != BC_OK) err = true;
+    if (launch_matvec(kind, Vb, nb, 3, bvec, yvec, mvws, s) != BC_OK) err = true;
+    if (mixed)
+      hipLaunchKernelGGL(k_csr_add<3>, dim3(gB), dim3(kWG), 0, s, prow, pcol, pcorr, (int)nb, nb,
+                         (const double *)bvec, yvec);
     hipLaunchKernelGGL(k_multidot, dim3(1), dim3(kWG), 0, s, f, (int64_t)0, u, (int)M, dots_au);
     hipLaunchKernelGGL(k_dual_QT, dim3(gM), dim3(kWG), 0, s, (const double *)yvec, nb, iptr, itri, icor, curl, f,
                        (const double *)dots_au, (int)M, out);
@@ -346,7 +380,10 @@ int run_dual_solve(const void *Vb, const int32_t *tris, int64_t N, int64_t M, co
   // out = V_dual u = P^T V_bary P u
   auto vdual = [&](const double *u, double *out) {
     hipLaunchKernelGGL(k_dual_P, dim3(gB), dim3(kWG), 0, s, u, tris, (int)N, bvec + 3 * nb);
-    if (launch_matvec(BC_FP64, Vb, nb, 1, bvec + 3 * nb, yvec + 3 * nb, mvws, s) != BC_OK) err = true;
+    if (launch_matvec(kind, Vb, nb, 1, bvec + 3 * nb, yvec + 3 * nb, mvws, s) != BC_OK) err = true;
+    if (mixed)
+      hipLaunchKernelGGL(k_csr_add<1>, dim3(gB), dim3(kWG), 0, s, prow, pcol, pcorr, (int)nb, nb,
+                         (const double *)(bvec + 3 * nb), yvec + 3 * nb);
     hipLaunchKernelGGL(k_dual_PT, dim3(gM), dim3(kWG), 0, s, (const double *)(yvec + 3 * nb), iptr, itri, icor,
                        (int)M, out);
     chk();

@@ -36,6 +36,7 @@ enum Phase : int32_t { PH_INIT = 0, PH_RESID = 1, PH_CG = 2, PH_UPDATE = 3, PH_D
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
 
 constexpr int kWaves = kSolveWG / 64;
 
@@ -195,6 +196,27 @@ struct Load16<double, double> {
 struct LoadD1 {
   static constexpr int VEC = 1;
   __device__ static void mat(gptr<const double> p, double (&v)[1]) { v[0] = __builtin_nontemporal_load(p); }
+  __device__ static void vec(gptr<const double> p, double (&v)[1]) { v[0] = *p; }
+};
+
+// two FP32 columns per lane with FP64 vectors: the product of an FP32 matrix
+// with several FP64 vectors (8-byte matrix loads, as LoadD1)
+struct LoadF2D {
+  static constexpr int VEC = 2;
+  __device__ static void mat(gptr<const float> p, float (&v)[2]) {
+    f2 t = __builtin_nontemporal_load(reinterpret_cast<gptr<const f2>>(p));
+    v[0] = t.x; v[1] = t.y;
+  }
+  __device__ static void vec(gptr<const double> p, double (&v)[2]) {
+    d2 t = *reinterpret_cast<gptr<const d2>>(p);
+    v[0] = t.x; v[1] = t.y;
+  }
+};
+
+// one FP32 column per lane with FP64 vectors
+struct LoadF1D {
+  static constexpr int VEC = 1;
+  __device__ static void mat(gptr<const float> p, float (&v)[1]) { v[0] = __builtin_nontemporal_load(p); }
   __device__ static void vec(gptr<const double> p, double (&v)[1]) { v[0] = *p; }
 };
 
@@ -773,18 +795,24 @@ int launch_solve(int32_t precision, const SysDesc *d_desc, int n_sys, int total_
 // symmetric product of k_solve, as three launches (the launch boundaries
 // take the place of the system barrier): padding, partial sums, gather.
 // Same partition and order as inside the solver, so the result depends on N
-// only; the NR vectors share each pass over V.
-template <typename MT, int NR>
-__global__ __launch_bounds__(kSolveWG) void k_matvec_pad(const MT *__restrict__ x, int64_t N, char *ws) {
-  const MatvecLayout Lay(N, sizeof(MT) == 8 ? BC_FP64 : BC_MIXED, NR);
-  MT *xp = reinterpret_cast<MT *>(ws + Lay.xpad);
+// only; the NR vectors share each pass over V.  MT is the matrix type, XT
+// the vectors' and the accumulation's: (double, double), (float, float) or
+// (float, double).
+template <typename MT, typename XT>
+constexpr int32_t matvec_kind() {
+  return sizeof(MT) == 8 ? BC_FP64 : (sizeof(XT) == 8 ? kMatvecF32X64 : BC_MIXED);
+}
+
+template <typename MT, typename XT, int NR>
+__global__ __launch_bounds__(kSolveWG) void k_matvec_pad(const XT *__restrict__ x, int64_t N, char *ws) {
+  const MatvecLayout Lay(N, matvec_kind<MT, XT>(), NR);
+  XT *xp = reinterpret_cast<XT *>(ws + Lay.xpad);
   for (int64_t i = (int64_t)blockIdx.x * kSolveWG + threadIdx.x; i < NR * Lay.ld; i += (int64_t)gridDim.x * kSolveWG) {
     const int64_t m = i / Lay.ld, j = i - m * Lay.ld;
-    xp[i] = j < N ? x[m * N + j] : MT(0);
+    xp[i] = j < N ? x[m * N + j] : XT(0);
   }
 }
 
-template <typename MT>
 __device__ __forceinline__ HalfPlan matvec_plan(const MatvecLayout &Lay, int64_t N, int G, int rank) {
   HalfPlan H;
   H.ld = Lay.ld; H.m64 = Lay.ld / 64; H.T = Lay.T; H.N = (int)N; H.nB = (int)Lay.nB; H.k = Lay.k; H.G = G;
@@ -793,59 +821,62 @@ __device__ __forceinline__ HalfPlan matvec_plan(const MatvecLayout &Lay, int64_t
 }
 
 // LDS: two buffers of NR x 16 wavefronts x CW column sums, and for NR > 1
-// the 16 x 8 x NR row x values.  One vector: 16-byte loads (CW = 64 x 16 B);
-// several (FP64 only): one column per lane (CW = 64), so that the NR x 8 row
-// sums stay in registers.
-template <typename MT, int NR>
+// the 16 x 8 x NR row x values.  One vector: 16-byte matrix loads; several:
+// 8-byte matrix loads (one FP64 or two FP32 columns per lane), so that the
+// NR x 8 row sums stay in registers.
+template <typename MT, typename XT, int NR>
 __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) void k_matvec_part(
     const MT *__restrict__ V, int64_t N, char *ws) {
-  static_assert(NR == 1 || sizeof(MT) == 8, "several vectors: FP64 only");
-  using L = typename std::conditional<NR == 1, Load16<MT, MT>, LoadD1>::type;
+  static_assert(NR == 1 || sizeof(XT) == 8, "several vectors: FP64 vectors only");
+  using L = typename std::conditional<
+      sizeof(MT) == sizeof(XT), typename std::conditional<NR == 1, Load16<MT, XT>, LoadD1>::type,
+      typename std::conditional<NR == 1, LoadF2D, LoadF1D>::type>::type;
   constexpr int CW = 64 * L::VEC;
-  __shared__ MT s_buf[2 * NR * 16 * CW + (NR > 1 ? 16 * 8 * NR : 0)];
-  const MatvecLayout Lay(N, sizeof(MT) == 8 ? BC_FP64 : BC_MIXED, NR);
-  const HalfPlan H = matvec_plan<MT>(Lay, N, (int)gridDim.x, (int)blockIdx.x);
+  __shared__ XT s_buf[2 * NR * 16 * CW + (NR > 1 ? 16 * 8 * NR : 0)];
+  const MatvecLayout Lay(N, matvec_kind<MT, XT>(), NR);
+  const HalfPlan H = matvec_plan(Lay, N, (int)gridDim.x, (int)blockIdx.x);
   gptr<char> w = as_global(ws);
   double unused = 0.0;
-  half_product<MT, MT, MT, false, true, NR, L>(as_global(V), reinterpret_cast<gptr<const MT>>(w + Lay.xpad), H,
-                                               reinterpret_cast<gptr<MT>>(w + Lay.rpart),
-                                               reinterpret_cast<gptr<MT>>(w + Lay.cpart), s_buf, unused);
+  half_product<MT, XT, XT, false, true, NR, L>(as_global(V), reinterpret_cast<gptr<const XT>>(w + Lay.xpad), H,
+                                               reinterpret_cast<gptr<XT>>(w + Lay.rpart),
+                                               reinterpret_cast<gptr<XT>>(w + Lay.cpart), s_buf, unused);
 }
 
-template <typename MT, int NR>
-__global__ __launch_bounds__(kSolveWG) void k_matvec_gather(int64_t N, const char *ws, MT *__restrict__ y) {
+template <typename MT, typename XT, int NR>
+__global__ __launch_bounds__(kSolveWG) void k_matvec_gather(int64_t N, const char *ws, XT *__restrict__ y) {
   __shared__ double s_part[16 * 64];
   __shared__ double s_band[kMaxBand];
-  const MatvecLayout Lay(N, sizeof(MT) == 8 ? BC_FP64 : BC_MIXED, NR);
+  const MatvecLayout Lay(N, matvec_kind<MT, XT>(), NR);
   const int G = (int)gridDim.x, rank = (int)blockIdx.x;
-  const HalfPlan H = matvec_plan<MT>(Lay, N, G, rank);
+  const HalfPlan H = matvec_plan(Lay, N, G, rank);
   const int r0 = (int)(N * rank / G), r1 = (int)(N * (rank + 1) / G);
   gptr<const char> w = as_global(ws);
-  MT *band = reinterpret_cast<MT *>(s_band);
+  XT *band = reinterpret_cast<XT *>(s_band);
   for (int m = 0; m < NR; ++m) {
-    half_gather<MT>(H, r0, r1, reinterpret_cast<gptr<const MT>>(w + Lay.rpart) + (size_t)m * kRB * Lay.T,
-                    reinterpret_cast<gptr<const MT>>(w + Lay.cpart) + (size_t)m * Lay.nB * Lay.ld,
-                    reinterpret_cast<MT *>(s_part), band);
+    half_gather<XT>(H, r0, r1, reinterpret_cast<gptr<const XT>>(w + Lay.rpart) + (size_t)m * kRB * Lay.T,
+                    reinterpret_cast<gptr<const XT>>(w + Lay.cpart) + (size_t)m * Lay.nB * Lay.ld,
+                    reinterpret_cast<XT *>(s_part), band);
     for (int i = r0 + (int)threadIdx.x; i < r1; i += kSolveWG) y[m * N + i] = band[i - r0];
     __syncthreads();  // band is rewritten by the next vector's gather
   }
 }
 
-template <typename MT, int NR>
+template <typename MT, typename XT, int NR>
 static void matvec_launch(const void *V, int64_t N, const void *x, void *y, char *w, hipStream_t s) {
   const int G = solve_workgroups(N);
-  hipLaunchKernelGGL((k_matvec_pad<MT, NR>), dim3(16), dim3(kSolveWG), 0, s, static_cast<const MT *>(x), N, w);
-  hipLaunchKernelGGL((k_matvec_part<MT, NR>), dim3(G), dim3(kSolveWG), 0, s, static_cast<const MT *>(V), N, w);
-  hipLaunchKernelGGL((k_matvec_gather<MT, NR>), dim3(G), dim3(kSolveWG), 0, s, N, (const char *)w,
-                     static_cast<MT *>(y));
+  hipLaunchKernelGGL((k_matvec_pad<MT, XT, NR>), dim3(16), dim3(kSolveWG), 0, s, static_cast<const XT *>(x), N, w);
+  hipLaunchKernelGGL((k_matvec_part<MT, XT, NR>), dim3(G), dim3(kSolveWG), 0, s, static_cast<const MT *>(V), N, w);
+  hipLaunchKernelGGL((k_matvec_gather<MT, XT, NR>), dim3(G), dim3(kSolveWG), 0, s, N, (const char *)w,
+                     static_cast<XT *>(y));
 }
 
-int launch_matvec(int32_t precision, const void *V, int64_t N, int nr, const void *x, void *y, void *ws,
-                  hipStream_t s) {
+int launch_matvec(int32_t kind, const void *V, int64_t N, int nr, const void *x, void *y, void *ws, hipStream_t s) {
   char *w = static_cast<char *>(ws);
-  if (precision == BC_FP64 && nr == 1) matvec_launch<double, 1>(V, N, x, y, w, s);
-  else if (precision == BC_FP64 && nr == 3) matvec_launch<double, 3>(V, N, x, y, w, s);
-  else if (precision == BC_MIXED && nr == 1) matvec_launch<float, 1>(V, N, x, y, w, s);
+  if (kind == BC_FP64 && nr == 1) matvec_launch<double, double, 1>(V, N, x, y, w, s);
+  else if (kind == BC_FP64 && nr == 3) matvec_launch<double, double, 3>(V, N, x, y, w, s);
+  else if (kind == BC_MIXED && nr == 1) matvec_launch<float, float, 1>(V, N, x, y, w, s);
+  else if (kind == kMatvecF32X64 && nr == 1) matvec_launch<float, double, 1>(V, N, x, y, w, s);
+  else if (kind == kMatvecF32X64 && nr == 3) matvec_launch<float, double, 3>(V, N, x, y, w, s);
   else return BC_EINVAL;
   return hipGetLastError() == hipSuccess ? BC_OK : BC_EDEVICE;
 }

@@ -62,6 +62,8 @@ def test_sizes(L):
     assert one > 0 and three > 2 * one
     assert L.bc_matvec_workspace_bytes(5000, 1, 1) > 0
     assert L.bc_matvec_workspace_bytes(5000, 0, 2) == 0 and L.bc_matvec_workspace_bytes(5000, 1, 3) == 0
+    # FP32 matrix with FP64 vectors: 1 or 3
+    assert L.bc_matvec_workspace_bytes(5000, 2, 1) > 0 and L.bc_matvec_workspace_bytes(5000, 2, 3) > 0
 
 
 def _check(L, verts, tris):
@@ -129,5 +131,11 @@ def test_argument_errors_without_device(L):
     v = C.c_void_p(16)
     for o in (_lib.bc_dual_opts(1e-10, -1.0, 10, 20, 30, 1), _lib.bc_dual_opts(1e-10, 1e-3, 10, 20, 30, 2),
               _lib.bc_dual_opts(1e-10, 0.0, 30, 20, 30, 1)):
-        assert L.bc_dual_solve(v, v, 100, 60, v, v, v, v, 1 << 40, C.byref(o), v, C.byref(res), null) == -1
+        assert L.bc_dual_solve(v, 0, null, 0, v, 100, 60, v, v, v, v, 1 << 40, C.byref(o), v, C.byref(res),
+                               null) == -1
+    # mixed dual solve without its pattern; unknown precision
+    o = _lib.bc_dual_opts(1e-10, 0.0, 10, 20, 30, 1)
+    for prec, pat in ((1, null), (7, v)):
+        assert L.bc_dual_solve(v, prec, pat, 10, v, 100, 60, v, v, v, v, 1 << 40, C.byref(o), v, C.byref(res),
+                               null) == -1
     assert L.bc_matvec(C.c_void_p(16), 100, 0, 3, C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), 10, null) == -3

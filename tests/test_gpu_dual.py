@@ -63,6 +63,16 @@ def test_matvec_matches_dense(api, prec):
         else:
             with pytest.raises(ValueError):
                 api.matvec(p, torch.zeros((3, m.N), dtype=p.matrix_dtype, device="cuda"))
+            # the FP32 matrix with FP64 vectors and sums, one and three vectors in a pass
+            V32 = p.dense().cpu().numpy().astype(np.float64)
+            X = rng.standard_normal((3, m.N))
+            for XX in (X[0], X):
+                Y = api.matvec(p, torch.from_numpy(np.ascontiguousarray(XX)).cuda()).cpu().numpy()
+                assert Y.dtype == np.float64
+                for k, (yk, xk) in enumerate(zip(np.atleast_2d(Y), np.atleast_2d(XX))):
+                    ref = V32 @ xk
+                    scale = np.abs(V32) @ np.abs(xk)
+                    assert (np.abs(yk - ref) / scale).max() <= 1e-13, (m.N, k)
 
 
 DUAL_MESHES = {
@@ -216,3 +226,26 @@ def test_inexact_stop(api, lam):
     assert abs(r.eta - eta(xs[k])) <= 1e-10 * r.eta
     assert ek <= lam * eta(xs[k]) * (1 + 1e-9)
     assert ek1 > lam * eta(xs[k - 1])
+
+
+@pytest.mark.parametrize("name", list(DUAL_MESHES) + ["cube12", "fichera48"])
+def test_dual_solve_mixed(api, name):
+    """V_bary stored in FP32 with the FP64 correction of touching and near
+    entries; products with FP64 vectors and sums (three-vector pass with one
+    FP32 column per lane).  GMRES solves V32 + C64 exactly, so the capacity
+    differs from the FP64 oracle only by the solution-weighted rounding of
+    the stored far field: relative 1e-8, the primal mixed bar."""
+    _flush(f"mixed dual solve {name}")
+    m = DUAL_MESHES[name]() if name in DUAL_MESHES else getattr(synth, name)()
+    Vb, P, bv, bt = odual.assemble_dual(m.verts, m.tris)
+    f = odual.dual_load(m.verts, m.tris)
+    xref, _ = odual.solve_dual(Vb, P, f)
+    cap_ref = odual.capacity_dual(xref, f)
+    p = api.DualProblem(m.verts, m.tris, restart=100, precision="mixed")
+    p.assemble()
+    r = p.solve(rtol=1e-13)
+    _flush(f"  N={m.N} iters {r.iters} cap {r.cap:.15f} ref {cap_ref:.15f} rel {abs(r.cap - cap_ref) / cap_ref:.2e}")
+    assert r.ok, r
+    assert abs(r.cap - cap_ref) <= 1e-8 * cap_ref
+    x = p.x.cpu().numpy()
+    assert np.abs(x - xref).max() <= 1e-6 * np.abs(xref).max()
