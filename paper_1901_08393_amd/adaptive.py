@@ -116,7 +116,7 @@ def adaptive_capacity(verts, tris, steps: int = 5, theta: float = 0.5, precision
 
 def adaptive_dual(verts, tris, steps: int = 5, theta: float = 0.5, h_mode: int = 1, rtol: float = 1e-10,
                   max_elements: Optional[int] = None, keep: bool = False, far_order: int = 4, ss_order: int = 4,
-                  jacobi_sweeps: int = 30, restart: int = 200, refine: str = "bisec1",
+                  jacobi_sweeps: int = 2, restart: int = 200, refine: str = "bisec1",
                   inexact_lambda: float = 0.0, precision: str = "fp64") -> List[Step]:
     """Algorithm 1 as stated: (i) the Galerkin solution on the dual mesh,
     computed from V on the barycentric refinement by GMRES with the

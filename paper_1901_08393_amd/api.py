@@ -294,7 +294,7 @@ class DualProblem:
         """V_bary (6N x 6N, FP64)."""
         return self.bary.assemble(stream)
 
-    def solve(self, rtol: float = 1e-12, max_iter: Optional[int] = None, jacobi_sweeps: int = 30,
+    def solve(self, rtol: float = 1e-12, max_iter: Optional[int] = None, jacobi_sweeps: int = 2,
               inexact_lambda: float = 0.0, h_mode: int = 1, stream=None) -> DualResult:
         """GMRES to the relative residual rtol; with inexact_lambda > 0 also
         stops once the energy norm of the last update is at most

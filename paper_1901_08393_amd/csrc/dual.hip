@@ -17,8 +17,10 @@
 // applied as a fixed number of Jacobi sweeps: a fixed linear operator, used
 // the same way on both sides, so the solution is exact whatever the sweep
 // count; the count only sets the quality of the preconditioner.  Each GMRES
-// step makes four products with V_bary (three curl components, one dual
-// indicator).  Every reduction has a fixed order.
+// step applies V_bary to four vectors in two passes over the matrix: the
+// three curl components together, then the dual indicator.  V_bary is FP64,
+// or FP32 with the FP64 correction of its touching and near entries; the
+// vectors and sums are FP64 either way.  Every reduction has a fixed order.
 #include <algorithm>
 #include <cmath>
 #include <vector>
