@@ -10,7 +10,8 @@ residual refinement) to a capacity within 1e-8 of the FP64 result.
     python bench.py [--steps K] [--warmup W] [--precision mixed|fp64]
 
 Prints one JSON line.  Also reported: the plain FP64 GPU form on the same
-mesh, per-phase times, assembly Gpairs/s, matrix-product GB/s, and the CPU
+mesh, per-phase times, assembly Gpairs/s, matrix-product GB/s, a summary of
+the paper's Algorithm 1 (dual mode) on the unit cube of Table 1, and the CPU
 oracle timed on a bounded sample on the host cores.
 """
 
@@ -353,6 +354,27 @@ def adaptive_cube_mode(a):
                       "monotone": all(steps[k].cap < steps[k + 1].cap for k in range(len(steps) - 1))}))
 
 
+def dual_summary(max_n: int = 12000) -> dict:
+    """Algorithm 1 in dual mode on the unit cube of Section 3.1 (FP64, theta
+    1/2, GMRES to 1e-10), reported beside the headline: the last step's
+    size, capacity error against the reference value, estimator, GMRES steps
+    and times, and the whole loop's wall time."""
+    import synth
+    from paper_1901_08393_amd.adaptive import adaptive_dual
+
+    m = synth.cube12()
+    t0 = synth.init_reference_edges(m.verts, m.tris)
+    w0 = time.perf_counter()
+    steps = adaptive_dual(m.verts, t0, steps=1000, theta=0.5, h_mode=1, rtol=1e-10, max_elements=max_n)
+    wall = time.perf_counter() - w0
+    s = steps[-1]
+    return {"workload": "unit cube from 12 triangles, Algorithm 1 dual mode, theta 0.5, FP64 (Section 3.1, Table 1)",
+            "steps": len(steps), "N": s.N, "N_bary": 6 * s.N, "cap": s.cap,
+            "cap_err_vs_reference": abs(CUBE_CAPACITY - s.cap), "eta2": s.eta2,
+            "gmres_max": max(x.iters for x in steps), "last_assemble_ms": round(s.t_assemble_ms, 2),
+            "last_solve_ms": round(s.t_solve_ms, 2), "wall_s": round(wall, 2)}
+
+
 def mixed60k_mode(a):
     """Mixed precision at N >= 60000: a seeded voxel union adapted (ZZ +
     Doerfler + NVB, FP64 path) until N >= 60000; then the FP64 GPU solve as
@@ -410,6 +432,7 @@ def main():
     ap.add_argument("--level", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-dual", action="store_true", help="skip the Algorithm 1 (dual mode) summary")
     ap.add_argument("--serve", action="store_true", help="serving workload instead of the sphere")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--adaptive", action="store_true", help="adaptive voxel-union workload (FP64 path)")
@@ -548,6 +571,10 @@ def main():
         out["cap_rel_err_vs_fp64"] = abs(res.cap - cap64) / cap64
         del prob64
         torch.cuda.empty_cache()
+
+    if not a.no_dual:
+        log("Algorithm 1 (dual mode) on the unit cube of Table 1 ...")
+        out["algorithm1_dual"] = dual_summary()
 
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample) ...")
