@@ -38,6 +38,11 @@ __device__ __forceinline__ void tile_of(int t, int &I, int &J) {
 // diameters apart use the expanded distance form in the far-field kernels.
 constexpr double kSepFar = 4.0;
 
+__device__ __forceinline__ bool far_separated(const double *bbox, int I, int J) {
+  const double *bi = bbox + 8 * I, *bj = bbox + 8 * J;
+  return box_dist2(bi, bj) >= kSepFar * kSepFar * fmax(bi[6], bj[6]);
+}
+
 // FP64 far field: V_ij = (1/4pi) sum_a sum_b W_a W_b / |x_a - y_b| over the
 // tensor rule's points (absolute coordinates, FP64), the inverse square root
 // refined by one Newton step (rsqrt64_far).  Tiles at least kSepFar block
@@ -66,11 +71,7 @@ __global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, 
   const int j = J * 64 + lane;
   const bool jv = j < N;
   const int jj = jv ? j : N - 1;
-  bool sep;
-  {
-    const double *bi = bbox + 8 * I, *bj = bbox + 8 * J;
-    sep = box_dist2(bi, bj) >= kSepFar * kSepFar * fmax(bi[6], bj[6]);
-  }
+  const bool sep = far_separated(bbox, I, J);
   // column element's points relative to its centroid (separated tiles) or
   // absolute (close tiles)
   const double4 cj = cen4[jj];
@@ -180,13 +181,14 @@ static int rsq_bias_ready(hipStream_t s) {
   return BC_OK;
 }
 
-template <int Q>
+template <int Q, bool SKIP_SEP>
 __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, const float *__restrict__ qpS,
                                                const double4 *__restrict__ cen4, const double *__restrict__ area,
                                                const double *__restrict__ bbox, double scale, int N, int64_t ld,
                                                float *__restrict__ V) {
   int I, J;
   tile_of(blockIdx.x, I, J);
+  if (SKIP_SEP && I != J && far_separated(bbox, I, J)) return;  // k_far32m integrates it
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int j = J * 64 + lane;
@@ -201,11 +203,7 @@ __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, c
     vw[b] = qpS[(size_t)(b * 4 + 3) * N + jj];
     vn[b] = -(vx[b] * vx[b] + vy[b] * vy[b] + vz[b] * vz[b]);
   }
-  bool sep;
-  {
-    const double *bi = bbox + 8 * I, *bj = bbox + 8 * J;
-    sep = box_dist2(bi, bj) >= kSepFar * kSepFar * fmax(bi[6], bj[6]);
-  }
+  const bool sep = far_separated(bbox, I, J);
   const double4 cj = cen4[jj];
   const double aj = 4.0 * area[jj] * (scale / (1.0 + g_rsq_bias));
   const int i0 = I * 64 + w * 16;
@@ -251,6 +249,81 @@ __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, c
     const int i = i0 + k;
     if (i >= N) break;
     if (sep) row(std::true_type{}, i); else row(std::false_type{}, i);
+  }
+}
+
+// FP32 far field of separated tiles (I < J, at least kSepFar block diameters
+// apart) on the matrix cores.  A wavefront takes 16 x 16 element pairs; for
+// each pair of points (a, b) one v_mfma_f32_16x16x4f32 forms
+//   -r^2 = 2 e.y - |e|^2 - |y|^2        for all 16 x 16 element pairs,
+// A[i][k] = (2 e_x, 2 e_y, 2 e_z, -|e|^2) of point a of row element i,
+// B[k][j] = (y_x, y_y, y_z, 1) of point b of column element j, C = -|y|^2,
+// with e and y relative to the centre of the column block's bounding box
+// (formed in FP64 and rounded once, like the norms).  Lane l then holds
+// -r^2 for rows 4 (l / 16) .. + 3 and column l % 16, and only the inverse
+// square roots and the weighted sums remain on the vector ALU.  The sums,
+// weights, scale and bias correction are those of k_far32.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(1024) void k_far32m(const double4 *__restrict__ qpA64, const double *__restrict__ qpS64,
+                                                 const float4 *__restrict__ qpA32, const double *__restrict__ area,
+                                                 const double *__restrict__ bbox, double scale, int N, int64_t ld,
+                                                 float *__restrict__ V) {
+  constexpr int Q = 16;
+  int I, J;
+  tile_of(blockIdx.x, I, J);
+  if (I == J || !far_separated(bbox, I, J)) return;  // k_far32 integrates it
+  const int lane = (int)__lane_id();
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int i0 = I * 64 + 16 * (w >> 2), j0 = J * 64 + 16 * (w & 3);
+  if (i0 >= N || j0 >= N) return;  // the wavefront's block lies past the end (wavefront-uniform)
+  const int k = lane >> 4;
+  const int ia = min(i0 + (lane & 15), N - 1), jb = min(j0 + (lane & 15), N - 1);
+  const double *bj = bbox + 8 * J;
+  const double fx = 0.5 * (bj[0] + bj[3]), fy = 0.5 * (bj[1] + bj[4]), fz = 0.5 * (bj[2] + bj[5]);
+  float av[Q], wt[Q];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const double4 p = qpA64[(size_t)ia * kQMax + a];
+    const double ex = p.x - fx, ey = p.y - fy, ez = p.z - fz;
+    const double comp = k == 0 ? 2.0 * ex : (k == 1 ? 2.0 * ey : (k == 2 ? 2.0 * ez : -(ex * ex + ey * ey + ez * ez)));
+    av[a] = (float)comp;
+    wt[a] = qpA32[a].w;  // reference weights (the same for every element)
+  }
+  float S[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int b = 0; b < Q; ++b) {
+    const double yx = qpS64[(size_t)(b * 4 + 0) * N + jb] - fx;
+    const double yy = qpS64[(size_t)(b * 4 + 1) * N + jb] - fy;
+    const double yz = qpS64[(size_t)(b * 4 + 2) * N + jb] - fz;
+    const float bv = k == 0 ? (float)yx : (k == 1 ? (float)yy : (k == 2 ? (float)yz : 1.0f));
+    const float yn = (float)(yx * yx + yy * yy + yz * yz);
+    const float wb = qpA32[b].w;
+    const v4f C = {-yn, -yn, -yn, -yn};
+    float Sb[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const v4f D = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv, C, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Sb[r] = __builtin_fmaf(wt[a], __builtin_amdgcn_rsqf(-D[r]), Sb[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) S[r] = __builtin_fmaf(wb, Sb[r], S[r]);
+  }
+  const int j = j0 + (lane & 15), ib = i0 + 4 * k;
+  if (j >= N) return;
+  const double aj = 4.0 * area[j] * (scale / (1.0 + g_rsq_bias));
+  float v[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = ib + r < N ? (float)((double)S[r] * (area[ib + r] * aj)) : 0.f;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (ib + r < N) V[(size_t)(ib + r) * ld + j] = v[r];
+  // the mirrored entries (j, ib .. ib + 3) are consecutive in row j
+  if (ib + 3 < N) {
+    *reinterpret_cast<float4 *>(V + (size_t)j * ld + ib) = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+    for (int r = 0; r < 4; ++r)
+      if (ib + r < N) V[(size_t)j * ld + ib + r] = v[r];
   }
 }
 
@@ -421,12 +494,19 @@ __global__ __launch_bounds__(kWG) void k_pad(T *V, int N, int64_t ld) {
 template <int Q>
 static void far_launch(bool mixed, const MeshView &m, int N, int64_t ld, void *V, int tiles, double scale,
                        hipStream_t s) {
-  if (!mixed)
+  if (!mixed) {
     hipLaunchKernelGGL(k_far64<Q>, dim3(tiles), dim3(kWG), 0, s, m.qpA64, m.qpS64, m.cen4, m.bbox, N, ld,
                        static_cast<double *>(V));
-  else
-    hipLaunchKernelGGL(k_far32<Q>, dim3(tiles), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox, scale, N,
+  } else if (Q == 16) {
+    // separated tiles on the matrix cores, the others on the vector ALU
+    hipLaunchKernelGGL((k_far32<Q, true>), dim3(tiles), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox,
+                       scale, N, ld, static_cast<float *>(V));
+    hipLaunchKernelGGL(k_far32m, dim3(tiles), dim3(1024), 0, s, m.qpA64, m.qpS64, m.qpA32, m.area, m.bbox, scale, N,
                        ld, static_cast<float *>(V));
+  } else {
+    hipLaunchKernelGGL((k_far32<Q, false>), dim3(tiles), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox,
+                       scale, N, ld, static_cast<float *>(V));
+  }
 }
 
 // (1/4pi) (sum_k w_k / sum_k fl32(w_k))^2 for the collapsed rule of order n
