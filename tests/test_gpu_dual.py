@@ -249,3 +249,30 @@ def test_dual_solve_mixed(api, name):
     assert abs(r.cap - cap_ref) <= 1e-8 * cap_ref
     x = p.x.cpu().numpy()
     assert np.abs(x - xref).max() <= 1e-6 * np.abs(xref).max()
+
+
+def test_dual_edge_cases(api):
+    """Step limit: status BC_ENOCONV with the last iterate returned (finite,
+    its residual above the tolerance); a huge lambda stops at once; the
+    coupled stop works on the mixed system too; more steps than
+    the workspace's restart are rejected."""
+    from paper_1901_08393_amd import _lib
+
+    m = synth.voxel_union(2, 0.4, 7)
+    p = api.DualProblem(m.verts, m.tris, restart=40)
+    p.assemble()
+    full = p.solve(rtol=1e-13)
+    r = p.solve(rtol=1e-13, max_iter=2)
+    assert r.status == _lib.BC_ENOCONV and r.iters == 2 and r.stop == 0
+    assert np.isfinite(p.x.cpu().numpy()).all() and r.rel_residual > 1e-13 and np.isfinite(r.cap)
+    # the first iterate is nearly constant (M 1 = f and D_reg maps constants to
+    # a multiple of a = f), so its estimator nearly vanishes: a huge lambda
+    # stops at the second step at the latest
+    r1 = p.solve(rtol=1e-13, inexact_lambda=1e6)
+    assert r1.ok and r1.stop == 2 and r1.iters <= 2
+    pm = api.DualProblem(m.verts, m.tris, restart=40, precision="mixed")
+    pm.assemble()
+    rm = pm.solve(rtol=1e-13, inexact_lambda=1e-3)
+    assert rm.ok and rm.stop in (1, 2) and abs(rm.cap - full.cap) <= 1e-6 * full.cap
+    with pytest.raises(_lib.BemcapError):
+        p.solve(rtol=1e-13, max_iter=41)
