@@ -11,6 +11,11 @@
  *   V[i][j] = (1/4pi) int_{T_i} int_{T_j} 1/|x - y| dy dx,
  *   b[i]    = |T_i|,     V sigma = b,     Cap = (1/4pi) sum_i sigma_i |T_i|.
  *
+ * The paper's own discretisation (Algorithm 1, step (i); Section 2.6) is
+ * provided too: the Galerkin system on the dual mesh, built from V on the
+ * barycentric refinement and solved with the hypersingular operator as
+ * preconditioner (bc_dual_*).
+ *
  * Conventions shared by every call
  *   - All functions are extern "C", reentrant, and keep no state between
  *     calls.  The library never allocates device memory: the caller passes
