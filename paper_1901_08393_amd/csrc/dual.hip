@@ -31,8 +31,6 @@ namespace bc {
 
 namespace {
 
-constexpr int kSonVertex[6] = {0, 1, 1, 2, 2, 0};
-
 // per corner a of a triangle, its two sons (the dual cell of that vertex)
 __device__ __forceinline__ void sons_of_corner(int a, int &s1, int &s2) {
   s1 = a == 0 ? 0 : (a == 1 ? 1 : 3);
@@ -84,7 +82,7 @@ __global__ void k_dual_P(const double *__restrict__ x, const int32_t *__restrict
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= 6 * N) return;
   const int t = k / 6, s = k - 6 * t;
-  const int sv = s == 0 || s == 5 ? 0 : (s <= 2 ? 1 : 2);
+  const int sv = s == 0 || s == 5 ? 0 : (s <= 2 ? 1 : 2);  // sons 0, 5 touch v0; 1, 2 touch v1; 3, 4 touch v2
   out[k] = x[tris[3 * t + sv]];
 }
 
