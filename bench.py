@@ -457,8 +457,8 @@ def main():
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy first (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU design is "
-                                   "described in DESIGN.md, not implemented)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU: --gpus must be 1 (the path is not sharded "
+                                   "across GPUs)"}))
         sys.exit(2)
     if a.serve:
         return serve_mode(a)
