@@ -379,6 +379,39 @@ def dual_summary(max_n: int = 12000) -> dict:
             "last_solve_ms": round(s.t_solve_ms, 2), "wall_s": round(wall, 2)}
 
 
+def dual_theta_mode(a):
+    """The marking parameter study of Section 3.1 (unit cube, Algorithm 1 in
+    dual mode): theta in {0.2, 0.4, 0.6, 0.8, 1}, each run until the next
+    mesh would exceed --dual-max-n triangles; theta = 1 refines uniformly.
+    Reports |Cap - Cap_l| per step and the rate alpha of err ~ N^-alpha
+    fitted over the steps with N >= 500 (the paper: alpha = 1 for theta < 1,
+    2/3 for uniform refinement)."""
+    import torch
+
+    import synth
+    from paper_1901_08393_amd.adaptive import adaptive_dual
+
+    torch.cuda.set_device(0)
+    m = synth.cube12()
+    t0 = synth.init_reference_edges(m.verts, m.tris)
+    out = {}
+    for theta in (0.2, 0.4, 0.6, 0.8, 1.0):
+        w0 = time.perf_counter()
+        steps = adaptive_dual(m.verts, t0, steps=1000, theta=theta, h_mode=1, rtol=1e-10,
+                              max_elements=a.dual_max_n, precision=a.dual_precision)
+        wall = time.perf_counter() - w0
+        Ns = np.array([s.N for s in steps], dtype=np.float64)
+        errs = np.array([abs(CUBE_CAPACITY - s.cap) for s in steps])
+        sel = Ns >= 500
+        alpha = float(-np.polyfit(np.log(Ns[sel]), np.log(errs[sel]), 1)[0]) if sel.sum() >= 2 else None
+        out[str(theta)] = {"N": [int(n) for n in Ns], "err": [float(f"{e:.4e}") for e in errs],
+                           "eta2": [float(f"{s.eta2:.4e}") for s in steps], "rate": alpha, "wall_s": round(wall, 2)}
+        log(f"theta={theta}: {len(steps)} steps to N={int(Ns[-1])}, err {errs[-1]:.3e}, rate {alpha}")
+    print(json.dumps({"mode": "dual_theta", "precision": a.dual_precision,
+                      "workload": "unit cube from 12 triangles, Algorithm 1 dual mode (Section 3.1, theta study)",
+                      "runs": out}))
+
+
 def mixed60k_mode(a):
     """Mixed precision at N >= 60000: a seeded voxel union adapted (ZZ +
     Doerfler + NVB, FP64 path) until N >= 60000; then the FP64 GPU solve as
@@ -448,6 +481,7 @@ def main():
     ap.add_argument("--dual-max-n", type=int, default=12000)
     ap.add_argument("--dual-precision", default="fp64", choices=["fp64", "mixed"],
                     help="dual mode: V_bary in FP64, or FP32 with FP64 corrections of touching and near entries")
+    ap.add_argument("--dual-theta", action="store_true", help="Algorithm 1 on the unit cube for five marking parameters")
     ap.add_argument("--inexact-lambda", type=float, default=0.0,
                     help="dual mode: stop GMRES when the energy of its update is below lambda x the estimator")
     ap.add_argument("--ss-order", type=int, default=4, help="--adaptive-cube: Gauss points per coordinate of the "
@@ -470,6 +504,8 @@ def main():
         return dual_mode(a)
     if a.adaptive_cube:
         return adaptive_cube_mode(a)
+    if a.dual_theta:
+        return dual_theta_mode(a)
 
     import torch
 
