@@ -226,7 +226,8 @@ def serve_mode(a):
 def adaptive_mode(a):
     """Adaptive workload: seeded voxel union (26 of 64 unit voxels),
     uniform NVB refinement to about 2k triangles, then 5 steps of solve,
-    ZZ, Doerfler (theta = 0.5) and NVB (FP64 path)."""
+    ZZ, Doerfler (theta = 0.5) and NVB with the marked elements split into
+    four (FP64 path): about 2.5k to 28k triangles."""
     import torch
 
     import synth
@@ -239,7 +240,8 @@ def adaptive_mode(a):
     while len(t) * 4 <= 2600:
         v, t, _ = synth.refine_uniform(v, t, 1)
     prec = "fp64" if a.precision == "mixed" and not a.adaptive_mixed else a.precision
-    steps = adaptive_capacity(v, t, steps=5, theta=0.5, precision=prec)
+    # marked elements split into four (bisec3): the workload grows about tenfold in five steps
+    steps = adaptive_capacity(v, t, steps=5, theta=0.5, precision=prec, refine="bisec3")
     rows = [dict(level=s.level, N=s.N, cap=s.cap, eta2=s.eta2, iters=s.iters, outer=s.outer, marked=s.n_marked,
                  assemble_ms=round(s.t_assemble_ms, 3), solve_ms=round(s.t_solve_ms, 3), zz_ms=round(s.t_zz_ms, 3),
                  refine_ms=round(s.t_refine_ms, 2)) for s in steps]
