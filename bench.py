@@ -598,6 +598,24 @@ def main():
         "roofline_other": other,
     }
 
+    # the solver's symmetric product as a standalone call (bc_matvec) on the same V
+    xv = torch.randn(N, dtype=prob.matrix_dtype, device="cuda")
+    for _ in range(3):
+        api.matvec(prob, xv)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(20):
+        api.matvec(prob, xv)
+    ev1.record()
+    torch.cuda.synchronize()
+    mv_ms = ev0.elapsed_time(ev1) / 20
+    mv_gbs = half_matrix_bytes(N, 4 if a.precision == "mixed" else 8) / (mv_ms * 1e-3) / 1e9
+    out["matvec_standalone"] = {"kernel": "bc_matvec (k_matvec_pad + k_matvec_part + k_matvec_gather)",
+                                "ms": round(mv_ms, 4), "gbs": round(mv_gbs, 1),
+                                "frac_of_hbm_peak": round(mv_gbs / HBM_PEAK_GBS, 4)}
+    del xv
+
     if not a.no_fp64_compare and a.precision == "mixed":
         prob64 = api.CapacityProblem(mesh.verts, mesh.tris, "fp64")
         r64 = run_steps(prob64, 1, torch)  # warm
