@@ -17,9 +17,12 @@
  * preconditioner (bc_dual_*).
  *
  * Conventions shared by every call
- *   - All functions are extern "C", reentrant, and keep no state between
- *     calls.  The library never allocates device memory: the caller passes
- *     device buffers (inputs, outputs and a workspace whose size the matching
+ *   - All functions are extern "C" and reentrant, and keep no state between
+ *     calls other than one constant per device: the mean error of the
+ *     hardware FP32 inverse square root, measured by the first mixed
+ *     assembly on that device (a fixed computation on fixed inputs).
+ *   - The library never allocates device memory: the caller passes device
+ *     buffers (inputs, outputs and a workspace whose size the matching
  *     *_bytes function returns) and owns all of them.
  *   - "d_" pointers are device pointers, "h_" pointers host pointers.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Device work is
