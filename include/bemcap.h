@@ -184,6 +184,15 @@ typedef struct bc_solve_opts {
   int32_t max_outer;  /* cap on FP64 residual evaluations */
   int32_t jacobi;     /* 1: diagonal (Jacobi) preconditioning */
   int32_t x0_given;   /* 1: start from the caller's sigma; 0: from zero */
+  double cap_rtol;    /* 0: off.  > 0: also stop once ||sigma|| ||r|| <=
+                         cap_rtol |b^T sigma| at an FP64 residual r = b -
+                         A sigma.  For symmetric A the capacity error of an
+                         iterate is exactly 4pi (Cap* - Cap) = sigma*^T r
+                         (the algebraic form of the identity behind
+                         Section 2.7's Proposition), so the left side bounds
+                         Cap's relative algebraic error to first order;
+                         solving to a capacity tolerance needs no tighter
+                         residual than this.  Must be finite and < 1. */
 } bc_solve_opts;
 
 /* Device-side result, written when a system finishes. */
@@ -195,6 +204,10 @@ typedef struct bc_result {
   int32_t status;      /* BC_OK, BC_ENOCONV, BC_EBREAKDOWN, BC_ETIMEOUT, or
                           BC_RUNNING while a chunked batch is unfinished */
   int32_t precision;
+  double cap_bound;    /* ||sigma|| ||b - A sigma|| / |b^T sigma| at the last
+                          FP64 residual: the first-order bound on Cap's
+                          relative error from the unsolved residual (see
+                          bc_solve_opts.cap_rtol); 0 if not finished */
 } bc_result;
 
 /* Workspace of one system's solver state.  Depends on N and precision. */

@@ -40,12 +40,14 @@ class bc_pattern_info(C.Structure):
 
 class bc_solve_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("inner_rtol", C.c_double), ("max_iter", C.c_int32),
-                ("max_outer", C.c_int32), ("jacobi", C.c_int32), ("x0_given", C.c_int32)]
+                ("max_outer", C.c_int32), ("jacobi", C.c_int32), ("x0_given", C.c_int32),
+                ("cap_rtol", C.c_double)]
 
 
 class bc_result(C.Structure):
     _fields_ = [("cap", C.c_double), ("rel_residual", C.c_double), ("iters", C.c_int32),
-                ("outer", C.c_int32), ("status", C.c_int32), ("precision", C.c_int32)]
+                ("outer", C.c_int32), ("status", C.c_int32), ("precision", C.c_int32),
+                ("cap_bound", C.c_double)]
 
 
 class bc_system(C.Structure):

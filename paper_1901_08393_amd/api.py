@@ -43,6 +43,7 @@ class SolveResult:
     outer: int
     status: int
     precision: int
+    cap_bound: float = 0.0  # ||sigma|| ||r|| / |b^T sigma|: first-order bound on Cap's relative algebraic error
 
     @property
     def ok(self) -> bool:
@@ -51,14 +52,14 @@ class SolveResult:
     @staticmethod
     def from_bytes(b: bytes) -> "SolveResult":
         r = _lib.bc_result.from_buffer_copy(b)
-        return SolveResult(r.cap, r.rel_residual, r.iters, r.outer, r.status, r.precision)
+        return SolveResult(r.cap, r.rel_residual, r.iters, r.outer, r.status, r.precision, r.cap_bound)
 
 
 def default_solve_opts(precision: str, **over) -> _lib.bc_solve_opts:
     if precision == "fp64":
-        o = dict(rtol=1e-12, inner_rtol=1e-11, max_iter=20000, max_outer=40, jacobi=1, x0_given=0)
+        o = dict(rtol=1e-12, inner_rtol=1e-11, max_iter=20000, max_outer=40, jacobi=1, x0_given=0, cap_rtol=0.0)
     else:
-        o = dict(rtol=1e-10, inner_rtol=1e-5, max_iter=20000, max_outer=60, jacobi=1, x0_given=0)
+        o = dict(rtol=1e-10, inner_rtol=1e-5, max_iter=20000, max_outer=60, jacobi=1, x0_given=0, cap_rtol=0.0)
     o.update({k: v for k, v in over.items() if v is not None})
     return _lib.bc_solve_opts(**o)
 
@@ -107,7 +108,7 @@ class CapacityProblem:
         self.V: Optional[torch.Tensor] = None
         self.sigma = torch.zeros(self.N, dtype=torch.float64, device=self.device)
         self.solve_ws: Optional[torch.Tensor] = None
-        self.result_buf = torch.zeros(32, dtype=torch.uint8, device=self.device)
+        self.result_buf = torch.zeros(C.sizeof(_lib.bc_result), dtype=torch.uint8, device=self.device)
 
     def prepare(self, stream=None):
         """Geometry tables and pair classification (bc_prepare; waits for

@@ -218,13 +218,14 @@ size_t bc_batch_scratch_bytes(int32_t n_sys) { return n_sys < 1 ? 0 : align256(s
 static bool solve_opts_ok(const bc_solve_opts *o) {
   return o && o->rtol >= 0.0 && std::isfinite(o->rtol) && o->inner_rtol > 0.0 && o->inner_rtol < 1.0 &&
          o->max_iter >= 1 && o->max_outer >= 1 && (o->jacobi == 0 || o->jacobi == 1) &&
-         (o->x0_given == 0 || o->x0_given == 1);
+         (o->x0_given == 0 || o->x0_given == 1) && o->cap_rtol >= 0.0 && o->cap_rtol < 1.0;
 }
 
 static SolveParams params_of(const bc_solve_opts *o, int32_t budget, int n_sys) {
   SolveParams p{};
   p.rtol = o->rtol;
   p.inner_rtol = o->inner_rtol;
+  p.cap_rtol = o->cap_rtol;
   p.max_iter = o->max_iter;
   p.max_outer = o->max_outer;
   p.jacobi = o->jacobi;

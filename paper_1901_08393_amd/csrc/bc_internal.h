@@ -232,7 +232,7 @@ struct SysDesc {
 };
 
 struct SolveParams {
-  double rtol, inner_rtol;
+  double rtol, inner_rtol, cap_rtol;
   int32_t max_iter, max_outer, jacobi, x0_given;
   int32_t iter_budget;
   uint32_t spin_limit;
@@ -245,6 +245,8 @@ struct SolveParams {
 // casting them once makes every access a global load/store.
 template <typename T>
 using gptr = T __attribute__((address_space(1))) *;
+template <typename T>
+using lptr = T __attribute__((address_space(3))) *;  // LDS
 template <typename T>
 __device__ __forceinline__ gptr<T> as_global(T *p) {
   return (gptr<T>)p;

@@ -9,7 +9,11 @@
 //
 //   RESID  r = b - A x in FP64 (A = V, plus the FP64 sparse correction of
 //          touching/near entries in mixed precision); stop if
-//          ||r|| <= rtol ||b||; else start an inner CG on A d = r / ||r||.
+//          ||r|| <= rtol ||b||, or, with a capacity tolerance, if
+//          ||x|| ||r|| <= cap_rtol |b^T x| (for symmetric A,
+//          4pi (Cap* - Cap) = x*^T r, the algebraic form of the identity
+//          in the proof of Section 2.7's Proposition); else start an
+//          inner CG on A d = r / ||r||.
 //   CG     preconditioned CG in the Chronopoulos-Gear arrangement: the two
 //          inner products of an iteration are reduced together, so an
 //          iteration costs one product with V and two cross-workgroup
@@ -245,7 +249,7 @@ struct HalfPlan {
 
 template <typename MT, typename XT, typename AT, bool DELTA, bool LDS2, int NR = 1, typename L = Load16<MT, XT>>
 __device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x, const HalfPlan &H, gptr<AT> rpart,
-                                             gptr<AT> cpart, AT *lbuf, double &delta) {
+                                             gptr<AT> cpart, lptr<AT> lbuf, double &delta) {
   constexpr int VEC = L::VEC;
   constexpr int CW = 64 * VEC;
   int64_t u = H.u0;
@@ -283,7 +287,7 @@ __device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x,
   static_assert(XR_LDS || NR == 1, "several vectors keep their row values in LDS");
   static_assert(XR_LDS || kRB <= 64 * VEC, "chunk 0 must hold the block's row values");
   AT xr[8], acc[NR][8];
-  AT *xl = lbuf + (LDS2 ? 2 : 1) * NR * 16 * CW + w * NR * 8;
+  lptr<AT> xl = lbuf + (LDS2 ? 2 : 1) * NR * 16 * CW + w * NR * 8;
   auto load_xr_lds = [&](int Bl) {
     if (lane < 8 * NR) {
       const int row = kRB * Bl + 8 * w + (lane & 7);
@@ -356,7 +360,7 @@ __device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x,
       for (int q = 0; q < VEC; ++q) d = __builtin_fma((double)xq[0][q], (double)cs[0][q], d);
       delta = __builtin_fma(col < diag_end ? 1.0 : 2.0, d, delta);
     }
-    AT *lb = lbuf + (LDS2 ? (int)(u & 1) * (NR * 16 * CW) : 0);
+    lptr<AT> lb = lbuf + (LDS2 ? (int)(u & 1) * (NR * 16 * CW) : 0);
 #pragma unroll
     for (int m = 0; m < NR; ++m)
 #pragma unroll
@@ -407,19 +411,29 @@ __device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x,
 // y_i for the rows [r0, r1) of this workgroup into band[i - r0]: the row
 // sums of the segments of i's block (one per workgroup that holds units of
 // it, in workgroup order) and then the column sums of the row blocks
-// 0 .. B(i)-1.  Lanes take rows and the sixteen wavefronts take every
-// sixteenth term; a wavefront keeps four partial sums (terms 16k + w with k
-// mod 4 fixed) so that four loads are in flight, adds them as
-// (s0 + s1) + (s2 + s3), and the wavefronts' sums are added in wavefront
-// order.  The order depends on N and the workgroup count only.
+// 0 .. B(i)-1.  The band is cut into groups of 64 rows (a lane per row);
+// the sixteen wavefronts are shared out over up to sixteen groups at a time,
+// S per group, and the S wavefronts of a group take every S-th term.  A
+// wavefront issues the loads of sixteen of its terms before adding any, so
+// that a band's column sums arrive in one or two memory round trips; it
+// keeps one partial sum per load slot and adds them in a fixed tree, and the
+// S wavefront sums of a row are added in wavefront order.  The order depends
+// on N and the workgroup count only.
 template <typename AT>
 __device__ __noinline__ void half_gather(const HalfPlan &H, int r0, int r1, gptr<const AT> rpart,
                                          gptr<const AT> cpart, AT *lpart, AT *band) {
+  constexpr int NB = 16;  // loads in flight per wavefront
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int t0 = r0; t0 < r1; t0 += 64) {
-    const int i = t0 + lane;
-    AT s[4] = {AT(0), AT(0), AT(0), AT(0)};
-    if (i < r1) {
+  const int ngr = (r1 - r0 + 63) >> 6;  // groups of 64 rows
+  const int gpp = ngr < 16 ? ngr : 16;  // groups per pass
+  const int S = 16 / (gpp > 0 ? gpp : 1);  // wavefronts per group
+  for (int p0 = 0; p0 < ngr; p0 += gpp) {
+    const int g = p0 + w / S, sl = w % S;
+    const int i = r0 + 64 * g + lane;
+    AT s[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) s[k] = AT(0);
+    if (w < S * gpp && g < ngr && i < r1) {
       const int B = i / kRB;
       const int64_t SB = half_units_before(B, H.m64, H.k), SE = half_units_before(B + 1, H.m64, H.k);
       // workgroups holding the units SB and SE - 1 (ranges [T g / G, T (g+1) / G))
@@ -428,40 +442,81 @@ __device__ __noinline__ void half_gather(const HalfPlan &H, int r0, int r1, gptr
       const int nseg = ghi - glo + 1;
       const int nterm = nseg + B;
       const int ii = i - kRB * B;
-      int q = w;
-      for (; q < nseg && q < nterm; q += 16) {  // segment row sums (few)
+      int q = sl;
+      for (; q < nseg && q < nterm; q += S) {  // segment row sums (few)
         int64_t us = SB;
         bool ok = true;
         if (q > 0) {
-          const int g = glo + q;
-          us = H.T * g / H.G;
-          ok = H.T * (g + 1) / H.G != us;  // a workgroup without units has no segment
+          const int gq = glo + q;
+          us = H.T * gq / H.G;
+          ok = H.T * (gq + 1) / H.G != us;  // a workgroup without units has no segment
         }
-        if (ok) s[(q >> 4) & 3] += rpart[(size_t)us * kRB + ii];
+        if (ok) s[0] += rpart[(size_t)us * kRB + ii];
       }
-      // column sums of the blocks above: four independent loads per step
-      for (; q + 48 < nterm; q += 64) {
-        const AT v0 = cpart[(size_t)(q - nseg) * (size_t)H.ld + i];
-        const AT v1 = cpart[(size_t)(q + 16 - nseg) * (size_t)H.ld + i];
-        const AT v2 = cpart[(size_t)(q + 32 - nseg) * (size_t)H.ld + i];
-        const AT v3 = cpart[(size_t)(q + 48 - nseg) * (size_t)H.ld + i];
-        s[(q >> 4) & 3] += v0;
-        s[((q >> 4) + 1) & 3] += v1;
-        s[((q >> 4) + 2) & 3] += v2;
-        s[((q >> 4) + 3) & 3] += v3;
-      }
-      for (; q < nterm; q += 16) s[(q >> 4) & 3] += cpart[(size_t)(q - nseg) * (size_t)H.ld + i];
-    }
-    lpart[w * 64 + lane] = (s[0] + s[1]) + (s[2] + s[3]);
-    __syncthreads();
-    if (w == 0 && i < r1) {
-      AT tot = AT(0);
+      // column sums of the blocks above, NB loads issued before any add
+      for (; q < nterm; q += NB * S) {
+        AT v[NB];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) tot += lpart[q * 64 + lane];
-      band[i - r0] = tot;
+        for (int k = 0; k < NB; ++k) {
+          const int qk = q + k * S;
+          v[k] = qk < nterm ? cpart[(size_t)(qk - nseg) * (size_t)H.ld + i] : AT(0);
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) s[k] += v[k];
+      }
+    }
+#pragma unroll
+    for (int h = NB / 2; h > 0; h >>= 1)
+#pragma unroll
+      for (int k = 0; k < h; ++k) s[k] += s[k + h];
+    lpart[w * 64 + lane] = s[0];
+    __syncthreads();
+    if (w < gpp) {
+      const int gg = p0 + w, iw = r0 + 64 * gg + lane;
+      if (gg < ngr && iw < r1) {
+        AT tot = AT(0);
+        for (int q = 0; q < S; ++q) tot += lpart[(w * S + q) * 64 + lane];
+        band[iw - r0] = tot;
+      }
     }
     __syncthreads();
   }
+}
+
+// The solver's products as a call of their own.  Inlined into k_solve, the
+// product loop shares the kernel's 128 registers with the state of the
+// whole state machine and spills inside the loop; as a call it has the
+// registers to itself and the caller's state is saved once per product.
+// Arguments of a call arrive in vector registers, so the plan and the
+// pointers, the same in every lane, are first read back as such.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ gptr<T> uniform_ptr(gptr<T> p) {
+  return (gptr<T>)uniform64((int64_t)(uintptr_t)p);
+}
+
+template <typename MT, typename XT, typename AT, bool DELTA, bool LDS2>
+__device__ __noinline__ double solver_product(gptr<const MT> V, gptr<const XT> x, HalfPlan H, gptr<AT> rpart,
+                                              gptr<AT> cpart, lptr<AT> lbuf) {
+  HalfPlan U;
+  U.ld = uniform64(H.ld);
+  U.m64 = uniform64(H.m64);
+  U.T = uniform64(H.T);
+  U.N = __builtin_amdgcn_readfirstlane(H.N);
+  U.nB = __builtin_amdgcn_readfirstlane(H.nB);
+  U.k = __builtin_amdgcn_readfirstlane(H.k);
+  U.G = __builtin_amdgcn_readfirstlane(H.G);
+  U.u0 = uniform64(H.u0);
+  U.u1 = uniform64(H.u1);
+  lbuf = (lptr<AT>)(uintptr_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(uintptr_t)lbuf);
+  double delta = 0.0;
+  half_product<MT, XT, AT, DELTA, LDS2>(uniform_ptr(V), uniform_ptr(x), U, uniform_ptr(rpart), uniform_ptr(cpart),
+                                        lbuf, delta);
+  return delta;
 }
 
 // At most 128 VGPRs, so that one 1024-thread workgroup fits on every CU.
@@ -555,34 +610,42 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       const bool zero_x = outer == 0 && !P.x0_given;
       if (!zero_x) {
         double unused = 0.0, dummy[1];
-        half_product<MT, double, double, false, false>(V, x64, H, rpD, cpD, s_buf, unused);
+        unused = solver_product<MT, double, double, false, false>(V, x64, H, rpD, cpD, (lptr<double>)s_buf);
         if (!sys_sync<1>(bar, none, dummy, s_red, &s_flag)) { aborted = true; break; }
         half_gather<double>(H, r0, r1, rpD, cpD, s_part, s_band);
       }
-      double pr = 0.0, pb = 0.0;
+      double pr = 0.0, pb = 0.0, pxx = 0.0, pbx = 0.0;
       for (int i = r0 + t; i < r1; i += kSolveWG) {
         double acc = zero_x ? 0.0 : s_band[i - r0];
         if (MIXED && S.pcorr != nullptr && !zero_x) {
           for (int e = prowptr[i]; e < prowptr[i + 1]; ++e) acc = __builtin_fma(pcorr[e], x64[pcol[e]], acc);
         }
-        const double ri = b[i] - acc;
+        const double ri = b[i] - acc, xi = x64[i];
         r64[i] = ri;
         pr = __builtin_fma(ri, ri, pr);
         pb = __builtin_fma(b[i], b[i], pb);
+        pxx = __builtin_fma(xi, xi, pxx);
+        pbx = __builtin_fma(b[i], xi, pbx);
       }
+      // the residual norm to reach: rtol ||b||, or with a capacity tolerance
+      // the norm at which ||x|| ||r|| / |b^T x|, the first-order bound on
+      // Cap's relative error (4pi (Cap* - Cap) = x*^T r), is cap_rtol
+      double target;
       {
-        const double v[2] = {pr, pb};
-        double tot[2];
-        if (!sys_sync<2>(bar, v, tot, s_red, &s_flag)) { aborted = true; break; }
+        const double v[4] = {pr, pb, pxx, pbx};
+        double tot[4];
+        if (!sys_sync<4>(bar, v, tot, s_red, &s_flag)) { aborted = true; break; }
         if (outer == 0) bnorm = sqrt(tot[1]);
         rnorm = sqrt(tot[0]);
+        target = P.rtol * bnorm;
+        if (P.cap_rtol > 0.0 && tot[2] > 0.0) target = fmax(target, P.cap_rtol * fabs(tot[3]) / sqrt(tot[2]));
       }
       outer += 1;
-      if (!(rnorm > P.rtol * bnorm)) { status = BC_OK; phase = PH_DONE; continue; }
+      if (!(rnorm > target)) { status = BC_OK; phase = PH_DONE; continue; }
       if (outer > P.max_outer || iters >= P.max_iter) { status = BC_ENOCONV; phase = PH_DONE; continue; }
       scale = 1.0 / rnorm;
-      // the inner solve need not go further than the outer tolerance asks
-      itol = fmax(P.inner_rtol, 0.3 * P.rtol * bnorm / rnorm);
+      // the inner solve need not go further than the outer target asks
+      itol = fmax(P.inner_rtol, 0.3 * target / rnorm);
       // inner start: r = r64 / ||r64||, u = M^-1 r, d = p = s = 0
       double pru = 0.0;
       for (int i = r0 + t; i < r1; i += kSolveWG) {
@@ -598,7 +661,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
         gamma = tot[0];
       }
       double pwu = 0.0;
-      half_product<MT, VT, VT, true, true>(V, vu, H, rpV, cpV, reinterpret_cast<VT *>(s_buf), pwu);
+      pwu = solver_product<MT, VT, VT, true, true>(V, vu, H, rpV, cpV, (lptr<VT>)s_buf);
       {
         const double v[1] = {pwu};
         double tot[1];
@@ -644,7 +707,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       inner += 1;
       if (!(sqrt(rr) > itol) || iters >= P.max_iter) { phase = PH_UPDATE; continue; }
       double pwu = 0.0;
-      half_product<MT, VT, VT, true, true>(V, vu, H, rpV, cpV, reinterpret_cast<VT *>(s_buf), pwu);
+      pwu = solver_product<MT, VT, VT, true, true>(V, vu, H, rpV, cpV, (lptr<VT>)s_buf);
       double delta;
       {
         const double v[1] = {pwu};
@@ -668,20 +731,24 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       continue;
     }
     // PH_DONE: sigma = x, Cap = (1/4pi) sum x_i |T_i|
-    double pc = 0.0;
+    double pc = 0.0, pxx = 0.0;
     for (int i = r0 + t; i < r1; i += kSolveWG) {
-      sigma[i] = x64[i];
-      pc = __builtin_fma(x64[i], b[i], pc);
+      const double xi = x64[i];
+      sigma[i] = xi;
+      pc = __builtin_fma(xi, b[i], pc);
+      pxx = __builtin_fma(xi, xi, pxx);
     }
-    double cap;
+    double cap, cap_bound;
     {
-      const double v[1] = {pc};
-      double tot[1];
-      if (!sys_sync<1>(bar, v, tot, s_red, &s_flag)) { aborted = true; break; }
+      const double v[2] = {pc, pxx};
+      double tot[2];
+      if (!sys_sync<2>(bar, v, tot, s_red, &s_flag)) { aborted = true; break; }
       cap = tot[0] * kInv4Pi;
+      cap_bound = tot[0] != 0.0 ? sqrt(tot[1]) * rnorm / fabs(tot[0]) : 0.0;
     }
     if (rank == 0 && t == 0) {
       result->cap = cap;
+      result->cap_bound = cap_bound;
       result->rel_residual = bnorm > 0.0 ? rnorm / bnorm : 0.0;
       result->iters = iters;
       result->outer = outer;
@@ -697,6 +764,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       result->outer = outer;
       result->status = BC_ETIMEOUT;
       result->precision = MIXED ? BC_MIXED : BC_FP64;
+      result->cap_bound = 0.0;
       ctl->phase = PH_DONE;
     } else {
       ctl->phase = phase; ctl->iters = iters; ctl->outer = outer; ctl->inner = inner; ctl->epoch = bar.epoch;
@@ -706,6 +774,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       result->outer = outer;
       result->status = BC_RUNNING;
       result->precision = MIXED ? BC_MIXED : BC_FP64;
+      result->cap_bound = 0.0;
     }
   }
 }
@@ -839,7 +908,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
   double unused = 0.0;
   half_product<MT, XT, XT, false, true, NR, L>(as_global(V), reinterpret_cast<gptr<const XT>>(w + Lay.xpad), H,
                                                reinterpret_cast<gptr<XT>>(w + Lay.rpart),
-                                               reinterpret_cast<gptr<XT>>(w + Lay.cpart), s_buf, unused);
+                                               reinterpret_cast<gptr<XT>>(w + Lay.cpart), (lptr<XT>)s_buf, unused);
 }
 
 template <typename MT, typename XT, int NR>

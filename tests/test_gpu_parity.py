@@ -211,6 +211,42 @@ def test_solve_mixed_capacity(api, name):
     assert err <= 1e-8, err
 
 
+@pytest.mark.parametrize("name", ["cube768", "voxel", "hull"])
+def test_capacity_tolerance_stop(api, name):
+    """Stopping on the capacity bound (bc_solve_opts.cap_rtol): for symmetric
+    V, 4pi (Cap* - Cap) = sigma*^T r exactly, so ||sigma|| ||r|| / |b^T sigma|
+    bounds the relative capacity error to first order.  The identity is
+    checked with the oracle's matrix and solution, the bound against the
+    oracle's capacity."""
+    _flush(f"capacity tolerance stop {name}")
+    m = MESHES[name]()
+    cap_ref, Vref, b, xref = _oracle_cap(name)
+    p = api.CapacityProblem(m.verts, m.tris, "fp64")
+    p.assemble()
+    tight = p.solve()
+    r = p.solve(rtol=0.0, cap_rtol=1e-6)
+    assert r.ok, r
+    assert 0.0 < r.cap_bound <= 1e-6, r
+    assert r.iters < tight.iters, (r.iters, tight.iters)
+    sig = p.sigma.cpu().numpy()
+    resid = b - Vref @ sig
+    lhs = 4 * math.pi * (cap_ref - r.cap)
+    rhs = float(xref @ resid)
+    assert abs(lhs - rhs) <= 1e-3 * abs(rhs) + 1e-13 * cap_ref, (lhs, rhs)
+    bound = np.linalg.norm(sig) * np.linalg.norm(resid) / abs(b @ sig)
+    assert abs(bound - r.cap_bound) <= 1e-6 * bound, (bound, r.cap_bound)
+    err = abs(r.cap - cap_ref) / cap_ref
+    assert err <= 1.001 * r.cap_bound, (err, r.cap_bound)
+    _flush(f"  iters {r.iters} (tight {tight.iters}) err {err:.2e} bound {r.cap_bound:.2e}")
+    # mixed precision at the capacity tolerance of the benchmark
+    pm = api.CapacityProblem(m.verts, m.tris, "mixed")
+    pm.assemble()
+    rm_tight = pm.solve()
+    rm = pm.solve(cap_rtol=1e-8)
+    assert rm.ok and rm.cap_bound <= 1e-8 and rm.iters <= rm_tight.iters, (rm, rm_tight)
+    assert abs(rm.cap - cap_ref) / cap_ref <= 1e-8
+
+
 def test_capacity_reduction(api):
     m = MESHES["cube768"]()
     p = api.CapacityProblem(m.verts, m.tris, "fp64")
