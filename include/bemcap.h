@@ -114,7 +114,13 @@ typedef struct bc_assembly_opts {
                          rules (coincident 6, edge 4, vertex 2 subdomains);
                          1..8, default 4 */
   int32_t precision;  /* bc_precision */
-  int32_t reserved;   /* must be 0 */
+  int32_t far_low;    /* BC_MIXED with far_order 4: 1 integrates pairs of
+                         64-element blocks whose bounding boxes are at least
+                         12 largest element diameters apart with the 3 x 3
+                         rule (81 instead of 256 point pairs).  There its
+                         relative error is at most 9e-10, below the FP32
+                         rounding of the stored entry (6e-8).  0: one far
+                         rule everywhere.  Must be 0 for BC_FP64. */
   double near_factor; /* BC_MIXED: pairs sharing no vertex with
                          |c_i - c_j|^2 < near_factor^2 max(diam_i, diam_j)^2
                          are computed in FP64 and corrected exactly; 0 = none.

@@ -30,7 +30,7 @@ BC_F32_F64 = 2
 
 class bc_assembly_opts(C.Structure):
     _fields_ = [("far_order", C.c_int32), ("ss_order", C.c_int32), ("precision", C.c_int32),
-                ("reserved", C.c_int32), ("near_factor", C.c_double)]
+                ("far_low", C.c_int32), ("near_factor", C.c_double)]
 
 
 class bc_pattern_info(C.Structure):

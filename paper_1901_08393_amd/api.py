@@ -79,7 +79,8 @@ class CapacityProblem:
     """A mesh on the GPU with everything the capacity computation needs."""
 
     def __init__(self, verts, tris, precision: str = "fp64", far_order: int = 4, ss_order: int = 4,
-                 near_factor: Optional[float] = None, device: str = "cuda", validate: bool = True, stream=None):
+                 near_factor: Optional[float] = None, device: str = "cuda", validate: bool = True, stream=None,
+                 far_low: Optional[bool] = None):
         if precision not in PRECISION:
             raise ValueError(f"precision must be one of {list(PRECISION)}")
         L = lib()
@@ -97,7 +98,9 @@ class CapacityProblem:
         self.device = torch.device(device)
         if near_factor is None:
             near_factor = 1.5 if precision == "mixed" else 0.0
-        self.opts = _lib.bc_assembly_opts(far_order, ss_order, self.prec, 0, float(near_factor))
+        if far_low is None:  # the 3 x 3 rule for distant blocks: mixed precision with the 4 x 4 far rule
+            far_low = precision == "mixed" and far_order == 4
+        self.opts = _lib.bc_assembly_opts(far_order, ss_order, self.prec, int(bool(far_low)), float(near_factor))
         self.d_verts = torch.from_numpy(verts).to(self.device)
         self.d_tris = torch.from_numpy(tris).to(self.device)
         nb = L.bc_mesh_workspace_bytes(self.N)

@@ -56,7 +56,8 @@ static bool opts_ok(const bc_assembly_opts *o) {
   if (o->far_order < 1 || o->far_order > 4) return false;
   if (o->ss_order < 1 || o->ss_order > kSSMax) return false;
   if (o->precision != BC_FP64 && o->precision != BC_MIXED) return false;
-  if (o->reserved != 0) return false;
+  if (o->far_low != 0 && o->far_low != 1) return false;
+  if (o->far_low == 1 && o->precision != BC_MIXED) return false;
   if (!(o->near_factor >= 0.0) || !std::isfinite(o->near_factor)) return false;
   if (o->precision == BC_FP64 && o->near_factor != 0.0) return false;
   return true;

@@ -252,6 +252,27 @@ __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, c
   }
 }
 
+// Tiles at least kSepFarLow largest element diameters apart (box distance of
+// the two 64-element blocks) are integrated in mixed precision with the
+// 3 x 3 collapsed rule (81 point pairs instead of 256).  For triangle pairs
+// at centroid distance d >= 12 diameters its relative error against a
+// high-order rule is at most 9e-10 (mean 2e-10) over random shapes and
+// orientations, and falls as d^-6; the FP32 rounding of the stored entry is
+// 6e-8.  The FP64 form keeps the one far rule everywhere.
+constexpr double kSepFarLow = 12.0;
+
+__device__ __forceinline__ bool far_low_order(const double *bbox, int I, int J) {
+  const double *bi = bbox + 8 * I, *bj = bbox + 8 * J;
+  return box_dist2(bi, bj) >= kSepFarLow * kSepFarLow * fmax(bi[6], bj[6]);
+}
+
+// The 3 x 3 collapsed rule on the reference triangle: points (s, t) and FP32
+// weights in the order of the far rule (a-major).
+struct FarRule9 {
+  double s[9], t[9];
+  float w[9];
+};
+
 // FP32 far field of separated tiles (I < J, at least kSepFar block diameters
 // apart) on the matrix cores.  A wavefront takes 16 x 16 element pairs; for
 // each pair of points (a, b) one v_mfma_f32_16x16x4f32 forms
@@ -263,16 +284,23 @@ __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, c
 // -r^2 for rows 4 (l / 16) .. + 3 and column l % 16, and only the inverse
 // square roots and the weighted sums remain on the vector ALU.  The sums,
 // weights, scale and bias correction are those of k_far32.
+// QP = 16: the far rule's points from the geometry tables, for separated
+// tiles (all of them, or with `split` those short of kSepFarLow).  QP = 9:
+// the 3 x 3 rule's points formed from the vertices, for the tiles at least
+// kSepFarLow apart.
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+template <int QP>
 __global__ __launch_bounds__(1024) void k_far32m(const double4 *__restrict__ qpA64, const double *__restrict__ qpS64,
-                                                 const float4 *__restrict__ qpA32, const double *__restrict__ area,
-                                                 const double *__restrict__ bbox, double scale, int N, int64_t ld,
-                                                 float *__restrict__ V) {
-  constexpr int Q = 16;
+                                                 const float4 *__restrict__ qpA32, const double *__restrict__ verts,
+                                                 const int4 *__restrict__ tri4, FarRule9 r9, int split,
+                                                 const double *__restrict__ area, const double *__restrict__ bbox,
+                                                 double scale, int N, int64_t ld, float *__restrict__ V) {
+  static_assert(QP == 16 || QP == 9, "far rule of 16 or 9 points");
   int I, J;
   tile_of(blockIdx.x, I, J);
   if (I == J || !far_separated(bbox, I, J)) return;  // k_far32 integrates it
+  if (QP == 16 ? (split && far_low_order(bbox, I, J)) : !far_low_order(bbox, I, J)) return;
   const int lane = (int)__lane_id();
   const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int i0 = I * 64 + 16 * (w >> 2), j0 = J * 64 + 16 * (w & 3);
@@ -281,27 +309,59 @@ __global__ __launch_bounds__(1024) void k_far32m(const double4 *__restrict__ qpA
   const int ia = min(i0 + (lane & 15), N - 1), jb = min(j0 + (lane & 15), N - 1);
   const double *bj = bbox + 8 * J;
   const double fx = 0.5 * (bj[0] + bj[3]), fy = 0.5 * (bj[1] + bj[4]), fz = 0.5 * (bj[2] + bj[5]);
-  float av[Q], wt[Q];
+  // a point's component for lane group k: 2 e_x, 2 e_y, 2 e_z or -|e|^2
+  auto acomp = [&](double ex, double ey, double ez) -> float {
+    return (float)(k == 0 ? 2.0 * ex : (k == 1 ? 2.0 * ey : (k == 2 ? 2.0 * ez : -(ex * ex + ey * ey + ez * ez))));
+  };
+  float av[QP], wt[QP];
+  // vertex 0 and the two edge vectors of the column element (QP = 9)
+  double q0x = 0, q0y = 0, q0z = 0, qux = 0, quy = 0, quz = 0, qvx = 0, qvy = 0, qvz = 0;
+  if constexpr (QP == 16) {
 #pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    const double4 p = qpA64[(size_t)ia * kQMax + a];
-    const double ex = p.x - fx, ey = p.y - fy, ez = p.z - fz;
-    const double comp = k == 0 ? 2.0 * ex : (k == 1 ? 2.0 * ey : (k == 2 ? 2.0 * ez : -(ex * ex + ey * ey + ez * ez)));
-    av[a] = (float)comp;
-    wt[a] = qpA32[a].w;  // reference weights (the same for every element)
+    for (int a = 0; a < QP; ++a) {
+      const double4 p = qpA64[(size_t)ia * kQMax + a];
+      av[a] = acomp(p.x - fx, p.y - fy, p.z - fz);
+      wt[a] = qpA32[a].w;  // reference weights (the same for every element)
+    }
+  } else {
+    const int4 ta = tri4[ia];
+    const double p0x = verts[3 * ta.x], p0y = verts[3 * ta.x + 1], p0z = verts[3 * ta.x + 2];
+    const double ux = verts[3 * ta.y] - p0x, uy = verts[3 * ta.y + 1] - p0y, uz = verts[3 * ta.y + 2] - p0z;
+    const double vx = verts[3 * ta.z] - p0x, vy = verts[3 * ta.z + 1] - p0y, vz = verts[3 * ta.z + 2] - p0z;
+#pragma unroll
+    for (int a = 0; a < QP; ++a) {
+      const double x = p0x + r9.s[a] * ux + r9.t[a] * vx;
+      const double y = p0y + r9.s[a] * uy + r9.t[a] * vy;
+      const double z = p0z + r9.s[a] * uz + r9.t[a] * vz;
+      av[a] = acomp(x - fx, y - fy, z - fz);
+      wt[a] = r9.w[a];
+    }
+    const int4 tb = tri4[jb];
+    q0x = verts[3 * tb.x]; q0y = verts[3 * tb.x + 1]; q0z = verts[3 * tb.x + 2];
+    qux = verts[3 * tb.y] - q0x; quy = verts[3 * tb.y + 1] - q0y; quz = verts[3 * tb.y + 2] - q0z;
+    qvx = verts[3 * tb.z] - q0x; qvy = verts[3 * tb.z + 1] - q0y; qvz = verts[3 * tb.z + 2] - q0z;
   }
   float S[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int b = 0; b < Q; ++b) {
-    const double yx = qpS64[(size_t)(b * 4 + 0) * N + jb] - fx;
-    const double yy = qpS64[(size_t)(b * 4 + 1) * N + jb] - fy;
-    const double yz = qpS64[(size_t)(b * 4 + 2) * N + jb] - fz;
+  for (int b = 0; b < QP; ++b) {
+    double yx, yy, yz;
+    float wb;
+    if constexpr (QP == 16) {
+      yx = qpS64[(size_t)(b * 4 + 0) * N + jb] - fx;
+      yy = qpS64[(size_t)(b * 4 + 1) * N + jb] - fy;
+      yz = qpS64[(size_t)(b * 4 + 2) * N + jb] - fz;
+      wb = qpA32[b].w;
+    } else {
+      yx = (q0x + r9.s[b] * qux + r9.t[b] * qvx) - fx;
+      yy = (q0y + r9.s[b] * quy + r9.t[b] * qvy) - fy;
+      yz = (q0z + r9.s[b] * quz + r9.t[b] * qvz) - fz;
+      wb = r9.w[b];
+    }
     const float bv = k == 0 ? (float)yx : (k == 1 ? (float)yy : (k == 2 ? (float)yz : 1.0f));
     const float yn = (float)(yx * yx + yy * yy + yz * yz);
-    const float wb = qpA32[b].w;
     const v4f C = {-yn, -yn, -yn, -yn};
     float Sb[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
+    for (int a = 0; a < QP; ++a) {
       const v4f D = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv, C, 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 4; ++r) Sb[r] = __builtin_fmaf(wt[a], __builtin_amdgcn_rsqf(-D[r]), Sb[r]);
@@ -491,18 +551,34 @@ __global__ __launch_bounds__(kWG) void k_pad(T *V, int N, int64_t ld) {
   V[i * ld + c] = T(0);
 }
 
+// (1/4pi) (sum_k w_k / sum_k fl32(w_k))^2 for the collapsed rule of order n
+static double far32_scale(int n);
+
 template <int Q>
-static void far_launch(bool mixed, const MeshView &m, int N, int64_t ld, void *V, int tiles, double scale,
-                       hipStream_t s) {
+static void far_launch(bool mixed, bool low_order, const MeshView &m, const double *verts, int N, int64_t ld,
+                       void *V, int tiles, double scale, hipStream_t s) {
   if (!mixed) {
     hipLaunchKernelGGL(k_far64<Q>, dim3(tiles), dim3(kWG), 0, s, m.qpA64, m.qpS64, m.cen4, m.bbox, N, ld,
                        static_cast<double *>(V));
   } else if (Q == 16) {
-    // separated tiles on the matrix cores, the others on the vector ALU
+    // separated tiles on the matrix cores (the distant ones with the 3 x 3
+    // rule), the others on the vector ALU
+    FarRule9 r9{};
+    double x[8], w[8];
+    gauss_legendre01(3, x, w);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        r9.s[3 * a + b] = x[a];
+        r9.t[3 * a + b] = x[b] * (1.0 - x[a]);
+        r9.w[3 * a + b] = (float)(w[a] * w[b] * (1.0 - x[a]));
+      }
     hipLaunchKernelGGL((k_far32<Q, true>), dim3(tiles), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox,
                        scale, N, ld, static_cast<float *>(V));
-    hipLaunchKernelGGL(k_far32m, dim3(tiles), dim3(1024), 0, s, m.qpA64, m.qpS64, m.qpA32, m.area, m.bbox, scale, N,
-                       ld, static_cast<float *>(V));
+    hipLaunchKernelGGL(k_far32m<16>, dim3(tiles), dim3(1024), 0, s, m.qpA64, m.qpS64, m.qpA32, verts, m.tri4, r9,
+                       low_order ? 1 : 0, m.area, m.bbox, scale, N, ld, static_cast<float *>(V));
+    if (low_order)
+      hipLaunchKernelGGL(k_far32m<9>, dim3(tiles), dim3(1024), 0, s, m.qpA64, m.qpS64, m.qpA32, verts, m.tri4, r9,
+                         1, m.area, m.bbox, far32_scale(3), N, ld, static_cast<float *>(V));
   } else {
     hipLaunchKernelGGL((k_far32<Q, false>), dim3(tiles), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox,
                        scale, N, ld, static_cast<float *>(V));
@@ -532,15 +608,16 @@ int launch_assemble(const void *mesh_ws, const int32_t *tris, const double *vert
   const int64_t T = (N + 63) / 64;
   const int tiles = (int)(T * (T + 1) / 2);
   const double scale = far32_scale(o.far_order);
+  const bool low = mixed && o.far_low == 1;
   if (mixed) {
     const int st = rsq_bias_ready(s);
     if (st != BC_OK) return st;
   }
   switch (o.far_order) {
-    case 1: far_launch<1>(mixed, m, (int)N, ld, V, tiles, scale, s); break;
-    case 2: far_launch<4>(mixed, m, (int)N, ld, V, tiles, scale, s); break;
-    case 3: far_launch<9>(mixed, m, (int)N, ld, V, tiles, scale, s); break;
-    case 4: far_launch<16>(mixed, m, (int)N, ld, V, tiles, scale, s); break;
+    case 1: far_launch<1>(mixed, low, m, verts, (int)N, ld, V, tiles, scale, s); break;
+    case 2: far_launch<4>(mixed, low, m, verts, (int)N, ld, V, tiles, scale, s); break;
+    case 3: far_launch<9>(mixed, low, m, verts, (int)N, ld, V, tiles, scale, s); break;
+    case 4: far_launch<16>(mixed, low, m, verts, (int)N, ld, V, tiles, scale, s); break;
     default: return BC_EINVAL;
   }
   if (hipGetLastError() != hipSuccess) return BC_EDEVICE;

@@ -169,6 +169,57 @@ def test_V_mixed_entrywise(api, name):
     assert abs(wbias) <= bound, (wbias, bound)
 
 
+def _two_spheres(D=6.5):
+    """Two level-2 icospheres of radius 1, centres D apart: every block pair
+    across the gap is at least 12 largest element diameters apart (box
+    distance D - 2 = 4.5 against 12 x 0.325)."""
+    m = synth.icosphere(2, 1.0)
+    verts = np.vstack([m.verts, m.verts + np.array([D, 0.0, 0.0])])
+    tris = np.vstack([m.tris, m.tris + m.verts.shape[0]]).astype(np.int32)
+    return verts, tris
+
+
+def test_far_low_order_rule(api):
+    """Mixed precision integrates distant block pairs with the 3 x 3 rule:
+    those entries match the oracle's 3 x 3 entries to FP32 rounding, differ
+    from its 4 x 4 entries by no more than that, carry no bias into the
+    capacity, and the capacity meets the 1e-8 bar."""
+    _flush("far low-order rule (two spheres)")
+    verts, tris = _two_spheres()
+    N = tris.shape[0]
+    half = N // 2
+    ref4 = oracle.assemble(verts, tris, 4, 4)
+    ref3 = oracle.assemble(verts, tris, 3, 4)
+    p = api.CapacityProblem(verts, tris, "mixed")
+    assert p.opts.far_low == 1
+    V32 = p.assemble()
+    torch.cuda.synchronize()
+    V32 = V32.cpu().numpy()[:, :N].astype(np.float64)
+    cross = np.s_[:half, half:]
+    r3 = (V32[cross] - ref3[cross]) / ref3[cross]
+    r4 = (V32[cross] - ref4[cross]) / ref4[cross]
+    _flush(f"  vs 3x3: max {np.abs(r3).max():.2e} mean {r3.mean():.2e}; "
+           f"vs 4x4: max {np.abs(r4).max():.2e} mean {r4.mean():.2e}")
+    # FP32 evaluation errors as for the other far entries, and no bias
+    for r in (r3, r4):
+        assert np.abs(r).max() <= 4e-6 and abs(r.mean()) <= 2e-9
+    assert np.array_equal(V32, V32.T)
+    # the same mesh with one far rule everywhere: only the distant entries change
+    q = api.CapacityProblem(verts, tris, "mixed", far_low=False)
+    W32 = q.assemble()
+    torch.cuda.synchronize()
+    W32 = W32.cpu().numpy()[:, :N].astype(np.float64)
+    assert np.array_equal(V32[:half, :half], W32[:half, :half]) and np.array_equal(V32[half:, half:], W32[half:, half:])
+    assert not np.array_equal(V32[cross], W32[cross])
+    b = oracle.rhs(verts, tris)
+    x = oracle.solve_direct(ref4, b)
+    cap_ref = oracle.capacity(x, b)
+    r = p.solve()
+    assert r.ok and abs(r.cap - cap_ref) / cap_ref <= 1e-8, (r.cap, cap_ref)
+    # capacity of two distant unit spheres: between one sphere's and two
+    assert 1.0 < cap_ref < 2.0
+
+
 # ----------------------------------------------------------------- solves
 
 def _oracle_cap(name):
