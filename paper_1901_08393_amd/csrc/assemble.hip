@@ -9,14 +9,18 @@
 //   the upper block triangle; lanes own columns j and keep that element's Q
 //   points in registers; the 16 rows of a wave are read with uniform
 //   (scalar) loads.  The value is stored at (i, j) and mirrored to (j, i).
-//   ALU-bound: no matrix cores (there is no dense contraction here, only
-//   a 1/r evaluation per point pair).
+//   ALU-bound.  In mixed precision with Q = 16 the tiles are split by class
+//   (lists built by bc_prepare): k_far32 takes the near and diagonal tiles,
+//   k_far32m the separated ones, where the squared distances of 16 x 16
+//   element pairs are one matrix-core product per point pair (the distant
+//   tiles, at least 12 element diameters apart, with the 3 x 3 rule).
 // k_sparse: one wavefront per pattern entry with j >= i: touching pairs with
 //   the Sauter-Schwab-type rules, near pairs (mixed precision) with the
 //   regular rule, both in FP64; overwrites the far-field value.  In mixed
 //   precision it also stores the FP64 correction V64 - (double)(float)V64 at
 //   both (i, j) and (j, i) of the pattern.
 // k_pad: zeros in the padding columns N..ld-1.
+#include <algorithm>
 #include <mutex>
 #include <type_traits>
 
@@ -25,24 +29,6 @@
 namespace bc {
 
 // ----------------------------------------------------------------- far field
-__device__ __forceinline__ void tile_of(int t, int &I, int &J) {
-  // tiles enumerated column-block first: t = J (J + 1) / 2 + I, 0 <= I <= J
-  int j = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-  while ((j + 1) * (j + 2) / 2 <= t) ++j;
-  while (j * (j + 1) / 2 > t) --j;
-  J = j;
-  I = t - j * (j + 1) / 2;
-}
-
-// Tiles whose 64-element blocks' bounding boxes are at least this many block
-// diameters apart use the expanded distance form in the far-field kernels.
-constexpr double kSepFar = 4.0;
-
-__device__ __forceinline__ bool far_separated(const double *bbox, int I, int J) {
-  const double *bi = bbox + 8 * I, *bj = bbox + 8 * J;
-  return box_dist2(bi, bj) >= kSepFar * kSepFar * fmax(bi[6], bj[6]);
-}
-
 // FP64 far field: V_ij = (1/4pi) sum_a sum_b W_a W_b / |x_a - y_b| over the
 // tensor rule's points (absolute coordinates, FP64), the inverse square root
 // refined by one Newton step (rsqrt64_far).  Tiles at least kSepFar block
@@ -181,14 +167,11 @@ static int rsq_bias_ready(hipStream_t s) {
   return BC_OK;
 }
 
-template <int Q, bool SKIP_SEP>
-__global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, const float *__restrict__ qpS,
-                                               const double4 *__restrict__ cen4, const double *__restrict__ area,
-                                               const double *__restrict__ bbox, double scale, int N, int64_t ld,
-                                               float *__restrict__ V) {
-  int I, J;
-  tile_of(blockIdx.x, I, J);
-  if (SKIP_SEP && I != J && far_separated(bbox, I, J)) return;  // k_far32m integrates it
+template <int Q>
+__device__ __forceinline__ void far32_tile(int I, int J, const float4 *__restrict__ qpA,
+                                           const float *__restrict__ qpS, const double4 *__restrict__ cen4,
+                                           const double *__restrict__ area, const double *__restrict__ bbox,
+                                           double scale, int N, int64_t ld, float *__restrict__ V) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int j = J * 64 + lane;
@@ -252,25 +235,32 @@ __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, c
   }
 }
 
-// Tiles at least kSepFarLow largest element diameters apart (box distance of
-// the two 64-element blocks) are integrated in mixed precision with the
-// 3 x 3 collapsed rule (81 point pairs instead of 256).  For triangle pairs
-// at centroid distance d >= 12 diameters its relative error against a
-// high-order rule is at most 9e-10 (mean 2e-10) over random shapes and
-// orientations, and falls as d^-6; the FP32 rounding of the stored entry is
-// 6e-8.  The FP64 form keeps the one far rule everywhere.
-constexpr double kSepFarLow = 12.0;
-
-__device__ __forceinline__ bool far_low_order(const double *bbox, int I, int J) {
-  const double *bi = bbox + 8 * I, *bj = bbox + 8 * J;
-  return box_dist2(bi, bj) >= kSepFarLow * kSepFarLow * fmax(bi[6], bj[6]);
+// One workgroup per tile of the upper block triangle, or (LIST) the tiles of
+// one list, visited grid-stride.
+template <int Q, bool LIST>
+__global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, const float *__restrict__ qpS,
+                                               const double4 *__restrict__ cen4, const double *__restrict__ area,
+                                               const double *__restrict__ bbox, const int32_t *__restrict__ cnt,
+                                               const int32_t *__restrict__ list, double scale, int N, int64_t ld,
+                                               float *__restrict__ V) {
+  int I, J;
+  if (!LIST) {
+    tile_of(blockIdx.x, I, J);
+    far32_tile<Q>(I, J, qpA, qpS, cen4, area, bbox, scale, N, ld, V);
+    return;
+  }
+  const int nt = (int)far_tiles(N), n = min(*cnt, nt);
+  for (int q = blockIdx.x; q < n; q += gridDim.x) {
+    const int t = list[q];
+    if (t < 0 || t >= nt) continue;  // lists from another mesh: nothing out of range
+    tile_of(t, I, J);
+    far32_tile<Q>(I, J, qpA, qpS, cen4, area, bbox, scale, N, ld, V);
+  }
 }
 
-// The 3 x 3 collapsed rule on the reference triangle: points (s, t) and FP32
-// weights in the order of the far rule (a-major).
-struct FarRule9 {
-  double s[9], t[9];
-  float w[9];
+// FP32 reference weights of a far rule (the same for every element).
+struct FarWeights {
+  float w[kQMax];
 };
 
 // FP32 far field of separated tiles (I < J, at least kSepFar block diameters
@@ -283,24 +273,17 @@ struct FarRule9 {
 // (formed in FP64 and rounded once, like the norms).  Lane l then holds
 // -r^2 for rows 4 (l / 16) .. + 3 and column l % 16, and only the inverse
 // square roots and the weighted sums remain on the vector ALU.  The sums,
-// weights, scale and bias correction are those of k_far32.
-// QP = 16: the far rule's points from the geometry tables, for separated
-// tiles (all of them, or with `split` those short of kSepFarLow).  QP = 9:
-// the 3 x 3 rule's points formed from the vertices, for the tiles at least
-// kSepFarLow apart.
+// weights, scale and bias correction are those of k_far32.  QP points per
+// element: the 4 x 4 rule (16) or the 3 x 3 rule of distant tiles (9), from
+// the geometry tables qpA (QP per element) and qpS (per point).
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <int QP>
-__global__ __launch_bounds__(1024) void k_far32m(const double4 *__restrict__ qpA64, const double *__restrict__ qpS64,
-                                                 const float4 *__restrict__ qpA32, const double *__restrict__ verts,
-                                                 const int4 *__restrict__ tri4, FarRule9 r9, int split,
-                                                 const double *__restrict__ area, const double *__restrict__ bbox,
-                                                 double scale, int N, int64_t ld, float *__restrict__ V) {
+__device__ __forceinline__ void far32m_tile(int I, int J, const double4 *__restrict__ qpA,
+                                            const double *__restrict__ qpS, const FarWeights &fw,
+                                            const double *__restrict__ area, const double *__restrict__ bbox,
+                                            double scale, int N, int64_t ld, float *__restrict__ V) {
   static_assert(QP == 16 || QP == 9, "far rule of 16 or 9 points");
-  int I, J;
-  tile_of(blockIdx.x, I, J);
-  if (I == J || !far_separated(bbox, I, J)) return;  // k_far32 integrates it
-  if (QP == 16 ? (split && far_low_order(bbox, I, J)) : !far_low_order(bbox, I, J)) return;
   const int lane = (int)__lane_id();
   const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int i0 = I * 64 + 16 * (w >> 2), j0 = J * 64 + 16 * (w & 3);
@@ -309,53 +292,20 @@ __global__ __launch_bounds__(1024) void k_far32m(const double4 *__restrict__ qpA
   const int ia = min(i0 + (lane & 15), N - 1), jb = min(j0 + (lane & 15), N - 1);
   const double *bj = bbox + 8 * J;
   const double fx = 0.5 * (bj[0] + bj[3]), fy = 0.5 * (bj[1] + bj[4]), fz = 0.5 * (bj[2] + bj[5]);
-  // a point's component for lane group k: 2 e_x, 2 e_y, 2 e_z or -|e|^2
-  auto acomp = [&](double ex, double ey, double ez) -> float {
-    return (float)(k == 0 ? 2.0 * ex : (k == 1 ? 2.0 * ey : (k == 2 ? 2.0 * ez : -(ex * ex + ey * ey + ez * ez))));
-  };
   float av[QP], wt[QP];
-  // vertex 0 and the two edge vectors of the column element (QP = 9)
-  double q0x = 0, q0y = 0, q0z = 0, qux = 0, quy = 0, quz = 0, qvx = 0, qvy = 0, qvz = 0;
-  if constexpr (QP == 16) {
 #pragma unroll
-    for (int a = 0; a < QP; ++a) {
-      const double4 p = qpA64[(size_t)ia * kQMax + a];
-      av[a] = acomp(p.x - fx, p.y - fy, p.z - fz);
-      wt[a] = qpA32[a].w;  // reference weights (the same for every element)
-    }
-  } else {
-    const int4 ta = tri4[ia];
-    const double p0x = verts[3 * ta.x], p0y = verts[3 * ta.x + 1], p0z = verts[3 * ta.x + 2];
-    const double ux = verts[3 * ta.y] - p0x, uy = verts[3 * ta.y + 1] - p0y, uz = verts[3 * ta.y + 2] - p0z;
-    const double vx = verts[3 * ta.z] - p0x, vy = verts[3 * ta.z + 1] - p0y, vz = verts[3 * ta.z + 2] - p0z;
-#pragma unroll
-    for (int a = 0; a < QP; ++a) {
-      const double x = p0x + r9.s[a] * ux + r9.t[a] * vx;
-      const double y = p0y + r9.s[a] * uy + r9.t[a] * vy;
-      const double z = p0z + r9.s[a] * uz + r9.t[a] * vz;
-      av[a] = acomp(x - fx, y - fy, z - fz);
-      wt[a] = r9.w[a];
-    }
-    const int4 tb = tri4[jb];
-    q0x = verts[3 * tb.x]; q0y = verts[3 * tb.x + 1]; q0z = verts[3 * tb.x + 2];
-    qux = verts[3 * tb.y] - q0x; quy = verts[3 * tb.y + 1] - q0y; quz = verts[3 * tb.y + 2] - q0z;
-    qvx = verts[3 * tb.z] - q0x; qvy = verts[3 * tb.z + 1] - q0y; qvz = verts[3 * tb.z + 2] - q0z;
+  for (int a = 0; a < QP; ++a) {
+    const double4 p = qpA[(size_t)ia * QP + a];
+    const double ex = p.x - fx, ey = p.y - fy, ez = p.z - fz;
+    av[a] = (float)(k == 0 ? 2.0 * ex : (k == 1 ? 2.0 * ey : (k == 2 ? 2.0 * ez : -(ex * ex + ey * ey + ez * ez))));
+    wt[a] = fw.w[a];
   }
   float S[4] = {0.f, 0.f, 0.f, 0.f};
   for (int b = 0; b < QP; ++b) {
-    double yx, yy, yz;
-    float wb;
-    if constexpr (QP == 16) {
-      yx = qpS64[(size_t)(b * 4 + 0) * N + jb] - fx;
-      yy = qpS64[(size_t)(b * 4 + 1) * N + jb] - fy;
-      yz = qpS64[(size_t)(b * 4 + 2) * N + jb] - fz;
-      wb = qpA32[b].w;
-    } else {
-      yx = (q0x + r9.s[b] * qux + r9.t[b] * qvx) - fx;
-      yy = (q0y + r9.s[b] * quy + r9.t[b] * qvy) - fy;
-      yz = (q0z + r9.s[b] * quz + r9.t[b] * qvz) - fz;
-      wb = r9.w[b];
-    }
+    const double yx = qpS[(size_t)(b * 4 + 0) * N + jb] - fx;
+    const double yy = qpS[(size_t)(b * 4 + 1) * N + jb] - fy;
+    const double yz = qpS[(size_t)(b * 4 + 2) * N + jb] - fz;
+    const float wb = fw.w[b];
     const float bv = k == 0 ? (float)yx : (k == 1 ? (float)yy : (k == 2 ? (float)yz : 1.0f));
     const float yn = (float)(yx * yx + yy * yy + yz * yz);
     const v4f C = {-yn, -yn, -yn, -yn};
@@ -384,6 +334,24 @@ __global__ __launch_bounds__(1024) void k_far32m(const double4 *__restrict__ qpA
   } else {
     for (int r = 0; r < 4; ++r)
       if (ib + r < N) V[(size_t)j * ld + ib + r] = v[r];
+  }
+}
+
+// The tiles of one list, grid-stride (no workgroup barrier: a wavefront
+// that has nothing to do in a tile goes on to the next).
+template <int QP>
+__global__ __launch_bounds__(1024) void k_far32m(const double4 *__restrict__ qpA, const double *__restrict__ qpS,
+                                                 FarWeights fw, const double *__restrict__ area,
+                                                 const double *__restrict__ bbox, const int32_t *__restrict__ cnt,
+                                                 const int32_t *__restrict__ list, double scale, int N, int64_t ld,
+                                                 float *__restrict__ V) {
+  const int nt = (int)far_tiles(N), n = min(*cnt, nt);
+  for (int q = blockIdx.x; q < n; q += gridDim.x) {
+    const int t = list[q];
+    if (t < 0 || t >= nt) continue;  // lists from another mesh: nothing out of range
+    int I, J;
+    tile_of(t, I, J);
+    far32m_tile<QP>(I, J, qpA, qpS, fw, area, bbox, scale, N, ld, V);
   }
 }
 
@@ -555,33 +523,46 @@ __global__ __launch_bounds__(kWG) void k_pad(T *V, int N, int64_t ld) {
 static double far32_scale(int n);
 
 template <int Q>
-static void far_launch(bool mixed, bool low_order, const MeshView &m, const double *verts, int N, int64_t ld,
-                       void *V, int tiles, double scale, hipStream_t s) {
+static void far_launch(bool mixed, bool low_order, const MeshView &m, int N, int64_t ld, void *V, int tiles,
+                       double scale, hipStream_t s) {
   if (!mixed) {
     hipLaunchKernelGGL(k_far64<Q>, dim3(tiles), dim3(kWG), 0, s, m.qpA64, m.qpS64, m.cen4, m.bbox, N, ld,
                        static_cast<double *>(V));
   } else if (Q == 16) {
-    // separated tiles on the matrix cores (the distant ones with the 3 x 3
-    // rule), the others on the vector ALU
-    FarRule9 r9{};
+    // Each tile class on its own kernel, over the tile lists of bc_prepare:
+    // near and diagonal tiles on the vector ALU, separated ones on the
+    // matrix cores (those at least kSepFarLow apart with the 3 x 3 rule when
+    // low_order).  The matrix-core kernels run as many workgroups as fit on
+    // the chip at once (two per CU) and take the tiles grid-stride.
+    int cus = 256;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+        hipSuccess || cus < 1)
+      cus = 256;
+    const int nt = (int)far_tiles(N);
+    const int32_t *cnt = m.tile_cnt, *list = m.tile_list;
+    FarWeights w16{}, w9{};
     double x[8], w[8];
+    gauss_legendre01(4, x, w);
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) w16.w[4 * a + b] = (float)(w[a] * w[b] * (1.0 - x[a]));
     gauss_legendre01(3, x, w);
     for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) {
-        r9.s[3 * a + b] = x[a];
-        r9.t[3 * a + b] = x[b] * (1.0 - x[a]);
-        r9.w[3 * a + b] = (float)(w[a] * w[b] * (1.0 - x[a]));
-      }
-    hipLaunchKernelGGL((k_far32<Q, true>), dim3(tiles), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox,
-                       scale, N, ld, static_cast<float *>(V));
-    hipLaunchKernelGGL(k_far32m<16>, dim3(tiles), dim3(1024), 0, s, m.qpA64, m.qpS64, m.qpA32, verts, m.tri4, r9,
-                       low_order ? 1 : 0, m.area, m.bbox, scale, N, ld, static_cast<float *>(V));
+      for (int b = 0; b < 3; ++b) w9.w[3 * a + b] = (float)(w[a] * w[b] * (1.0 - x[a]));
+    const int gv = std::min(nt, 4 * cus), gm = std::min(nt, 2 * cus);
+    hipLaunchKernelGGL((k_far32<Q, true>), dim3(gv), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox, cnt,
+                       list, scale, N, ld, static_cast<float *>(V));
+    hipLaunchKernelGGL(k_far32m<16>, dim3(gm), dim3(1024), 0, s, m.qpA64, m.qpS64, w16, m.area, m.bbox, cnt + 1,
+                       list + (size_t)nt, scale, N, ld, static_cast<float *>(V));
     if (low_order)
-      hipLaunchKernelGGL(k_far32m<9>, dim3(tiles), dim3(1024), 0, s, m.qpA64, m.qpS64, m.qpA32, verts, m.tri4, r9,
-                         1, m.area, m.bbox, far32_scale(3), N, ld, static_cast<float *>(V));
+      hipLaunchKernelGGL(k_far32m<9>, dim3(gm), dim3(1024), 0, s, m.qp9A64, m.qp9S64, w9, m.area, m.bbox, cnt + 2,
+                         list + 2 * (size_t)nt, far32_scale(3), N, ld, static_cast<float *>(V));
+    else
+      hipLaunchKernelGGL(k_far32m<16>, dim3(gm), dim3(1024), 0, s, m.qpA64, m.qpS64, w16, m.area, m.bbox, cnt + 2,
+                         list + 2 * (size_t)nt, scale, N, ld, static_cast<float *>(V));
   } else {
     hipLaunchKernelGGL((k_far32<Q, false>), dim3(tiles), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox,
-                       scale, N, ld, static_cast<float *>(V));
+                       (const int32_t *)nullptr, (const int32_t *)nullptr, scale, N, ld, static_cast<float *>(V));
   }
 }
 
@@ -614,10 +595,10 @@ int launch_assemble(const void *mesh_ws, const int32_t *tris, const double *vert
     if (st != BC_OK) return st;
   }
   switch (o.far_order) {
-    case 1: far_launch<1>(mixed, low, m, verts, (int)N, ld, V, tiles, scale, s); break;
-    case 2: far_launch<4>(mixed, low, m, verts, (int)N, ld, V, tiles, scale, s); break;
-    case 3: far_launch<9>(mixed, low, m, verts, (int)N, ld, V, tiles, scale, s); break;
-    case 4: far_launch<16>(mixed, low, m, verts, (int)N, ld, V, tiles, scale, s); break;
+    case 1: far_launch<1>(mixed, low, m, (int)N, ld, V, tiles, scale, s); break;
+    case 2: far_launch<4>(mixed, low, m, (int)N, ld, V, tiles, scale, s); break;
+    case 3: far_launch<9>(mixed, low, m, (int)N, ld, V, tiles, scale, s); break;
+    case 4: far_launch<16>(mixed, low, m, (int)N, ld, V, tiles, scale, s); break;
     default: return BC_EINVAL;
   }
   if (hipGetLastError() != hipSuccess) return BC_EDEVICE;

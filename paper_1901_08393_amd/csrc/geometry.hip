@@ -26,8 +26,9 @@ struct FarRule {
 
 __global__ __launch_bounds__(kWG) void k_geometry(const double *__restrict__ verts, int64_t M,
                                                   const int32_t *__restrict__ tris, int N, FarRule rule,
-                                                  int4 *tri4, double4 *cen4, double *area, double4 *qpA64,
-                                                  double *qpS64, float4 *qpA32, float *qpS32) {
+                                                  FarRule rule9, int4 *tri4, double4 *cen4, double *area,
+                                                  double4 *qpA64, double *qpS64, float4 *qpA32, float *qpS32,
+                                                  double4 *qp9A64, double *qp9S64) {
 #pragma clang fp contract(off)
   int e = blockIdx.x * kWG + threadIdx.x;
   if (e >= N) return;
@@ -74,6 +75,18 @@ __global__ __launch_bounds__(kWG) void k_geometry(const double *__restrict__ ver
     qpS32[(size_t)(k * 4 + 1) * N + e] = ry;
     qpS32[(size_t)(k * 4 + 2) * N + e] = rz;
     qpS32[(size_t)(k * 4 + 3) * N + e] = rw;
+  }
+  // the 3 x 3 rule of the distant tiles in mixed precision
+  for (int k = 0; k < 9; ++k) {
+    const double x = p0x + rule9.s[k] * ux + rule9.t[k] * vx;
+    const double y = p0y + rule9.s[k] * uy + rule9.t[k] * vy;
+    const double z = p0z + rule9.s[k] * uz + rule9.t[k] * vz;
+    const double W = 2.0 * A * rule9.w[k];
+    qp9A64[(size_t)e * 9 + k] = make_double4(x, y, z, W);
+    qp9S64[(size_t)(k * 4 + 0) * N + e] = x;
+    qp9S64[(size_t)(k * 4 + 1) * N + e] = y;
+    qp9S64[(size_t)(k * 4 + 2) * N + e] = z;
+    qp9S64[(size_t)(k * 4 + 3) * N + e] = W;
   }
 }
 
@@ -128,6 +141,76 @@ __global__ __launch_bounds__(64) void k_blockbox(const double *__restrict__ vert
   }
 }
 
+
+// Far-field tile lists: the tiles of the upper block triangle of each class
+// (kTileClasses), in tile order, so that each far-field kernel runs over its
+// own tiles only and neighbouring workgroups share column blocks in the
+// cache.  Two passes over chunks of kTileChunk tiles: counts per chunk, then
+// each chunk's offsets (the counts of the chunks before it) and its tiles'
+// ranks (a scan over the workgroup's threads, 16 consecutive tiles each).
+constexpr int kTilesPerThread = 16;
+constexpr int kTileChunk = kWG * kTilesPerThread;
+static_assert(kTileChunk == 4096, "MeshLayout sizes the per-chunk counts for chunks of 4096 tiles");
+
+__device__ __forceinline__ int tile_class(const double *bbox, int t) {
+  int I, J;
+  tile_of(t, I, J);
+  return (I == J || !far_separated(bbox, I, J)) ? 0 : (far_low_order(bbox, I, J) ? 2 : 1);
+}
+
+__global__ __launch_bounds__(kWG) void k_tile_count(const double *__restrict__ bbox, int ntiles,
+                                                    int32_t *__restrict__ chunk_cnt) {
+  __shared__ int part[kTileClasses][kWG];
+  int c3[kTileClasses] = {0, 0, 0};
+  const int t0 = blockIdx.x * kTileChunk + (int)threadIdx.x * kTilesPerThread;
+  for (int k = 0; k < kTilesPerThread; ++k)
+    if (t0 + k < ntiles) ++c3[tile_class(bbox, t0 + k)];
+  for (int c = 0; c < kTileClasses; ++c) part[c][threadIdx.x] = c3[c];
+  __syncthreads();
+  for (int h = kWG / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int c = 0; c < kTileClasses; ++c) part[c][threadIdx.x] += part[c][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < kTileClasses) chunk_cnt[blockIdx.x * kTileClasses + threadIdx.x] = part[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kWG) void k_tile_emit(const double *__restrict__ bbox, int ntiles,
+                                                   const int32_t *__restrict__ chunk_cnt, int32_t *__restrict__ tile_cnt,
+                                                   int32_t *__restrict__ tile_list) {
+  __shared__ int pre[kTileClasses][kWG];
+  __shared__ int off[kTileClasses];
+  const int tid = (int)threadIdx.x;
+  if (tid < kTileClasses) {
+    int o = 0;
+    for (int q = 0; q < (int)blockIdx.x; ++q) o += chunk_cnt[q * kTileClasses + tid];
+    off[tid] = o;
+  }
+  int cls[kTilesPerThread];
+  int c3[kTileClasses] = {0, 0, 0};
+  const int t0 = blockIdx.x * kTileChunk + tid * kTilesPerThread;
+  for (int k = 0; k < kTilesPerThread; ++k) {
+    cls[k] = t0 + k < ntiles ? tile_class(bbox, t0 + k) : -1;
+    if (cls[k] >= 0) ++c3[cls[k]];
+  }
+  for (int c = 0; c < kTileClasses; ++c) pre[c][tid] = c3[c];
+  __syncthreads();
+  if (tid < kTileClasses) {  // exclusive scan over the threads, one class per thread
+    int run = off[tid];
+    for (int q = 0; q < kWG; ++q) {
+      const int v = pre[tid][q];
+      pre[tid][q] = run;
+      run += v;
+    }
+    if ((int)blockIdx.x == (int)gridDim.x - 1) tile_cnt[tid] = run;
+  }
+  __syncthreads();
+  int pos[kTileClasses] = {pre[0][tid], pre[1][tid], pre[2][tid]};
+  for (int k = 0; k < kTilesPerThread; ++k) {
+    const int c = cls[k];
+    if (c >= 0) tile_list[(size_t)c * ntiles + pos[c]++] = t0 + k;
+  }
+}
 
 // One workgroup per block of 64 rows (16 rows per wave); lanes sweep the
 // columns 64 at a time.  Row data are staged in LDS (broadcast reads).
@@ -273,14 +356,24 @@ int launch_geometry(const double *verts, int64_t M, const int32_t *tris, int64_t
       r.t[k] = x[b] * (1.0 - x[a]);
       r.w[k] = w[a] * w[b] * (1.0 - x[a]);
     }
+  FarRule r9{};
+  gauss_legendre01(3, x, w);
+  r9.Q = 9;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      r9.s[3 * a + b] = x[a];
+      r9.t[3 * a + b] = x[b] * (1.0 - x[a]);
+      r9.w[3 * a + b] = w[a] * w[b] * (1.0 - x[a]);
+    }
   MeshLayout L(N);
   char *base = static_cast<char *>(mesh_ws);
   int grid = (int)((N + kWG - 1) / kWG);
-  hipLaunchKernelGGL(k_geometry, dim3(grid), dim3(kWG), 0, s, verts, M, tris, (int)N, r,
+  hipLaunchKernelGGL(k_geometry, dim3(grid), dim3(kWG), 0, s, verts, M, tris, (int)N, r, r9,
                      reinterpret_cast<int4 *>(base + L.tri4), reinterpret_cast<double4 *>(base + L.cen4),
                      reinterpret_cast<double *>(base + L.area), reinterpret_cast<double4 *>(base + L.qpA64),
                      reinterpret_cast<double *>(base + L.qpS64), reinterpret_cast<float4 *>(base + L.qpA32),
-                     reinterpret_cast<float *>(base + L.qpS32));
+                     reinterpret_cast<float *>(base + L.qpS32), reinterpret_cast<double4 *>(base + L.qp9A64),
+                     reinterpret_cast<double *>(base + L.qp9S64));
   return hipGetLastError() == hipSuccess ? BC_OK : BC_EDEVICE;
 }
 
@@ -299,6 +392,15 @@ int launch_pattern(const double *verts, const int32_t *tris, int64_t N, double n
   const double *bbox = reinterpret_cast<const double *>(base + L.blockbox);
   if (!emit) {
     hipLaunchKernelGGL(k_blockbox, dim3(grid), dim3(64), 0, s, verts, tri4, cen4, (int)N, const_cast<double *>(bbox));
+    if (hipGetLastError() != hipSuccess) return BC_EDEVICE;
+    const int64_t ntiles = far_tiles(N);
+    const unsigned nchunk = (unsigned)((ntiles + kTileChunk - 1) / kTileChunk);
+    int32_t *tile_cnt = reinterpret_cast<int32_t *>(base + L.tiles);
+    int32_t *tile_list = tile_cnt + 16;
+    int32_t *chunk_cnt = tile_list + kTileClasses * ntiles;
+    hipLaunchKernelGGL(k_tile_count, dim3(nchunk), dim3(kWG), 0, s, bbox, (int)ntiles, chunk_cnt);
+    hipLaunchKernelGGL(k_tile_emit, dim3(nchunk), dim3(kWG), 0, s, bbox, (int)ntiles, (const int32_t *)chunk_cnt,
+                       tile_cnt, tile_list);
     if (hipGetLastError() != hipSuccess) return BC_EDEVICE;
     hipLaunchKernelGGL(k_pattern<false>, dim3(grid), dim3(kWG), 0, s, tri4, cen4, bbox, (int)N, nf2, rowcnt, kindcnt,
                        (const int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr);
