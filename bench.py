@@ -229,7 +229,8 @@ def serve_mode(a):
     out = {"mode": "serve", "requests": len(reqs), "seed": 5}
     caps = {}
     for prec in ("mixed", "fp64"):
-        srv = CapacityServer(prec)
+        # the mixed form at the capacity tolerance; the FP64 form at its tight default, the reference
+        srv = CapacityServer(prec, solve_opts={"cap_rtol": a.cap_rtol} if prec == "mixed" else None)
         srv.run(reqs[:8], meshes[:8], realtime=False)  # warm-up
         recs = srv.run(reqs, meshes, realtime=False)
         sat = summarize(recs)
