@@ -323,34 +323,35 @@ def test_zz_indicators(api, name):
 
 # ---------------------------------------------------------------- batching
 
-def test_batched_equals_alone_bitwise(api):
-    _flush("batched vs alone")
+@pytest.mark.parametrize("cap_rtol", [0.0, 1e-8])
+def test_batched_equals_alone_bitwise(api, cap_rtol):
+    _flush(f"batched vs alone (cap_rtol {cap_rtol})")
     meshes = [MESHES["hull"](), MESHES["voxel"](), MESHES["cube768"]()]
     for prec in ("fp64", "mixed"):
         alone = []
         for m in meshes:
             p = api.CapacityProblem(m.verts, m.tris, prec)
             p.assemble()
-            r = p.solve()
+            r = p.solve(cap_rtol=cap_rtol)
             alone.append((r, p.sigma.cpu().numpy().copy()))
         probs = []
         for m in meshes:
             p = api.CapacityProblem(m.verts, m.tris, prec)
             p.assemble()
             probs.append(p)
-        keep = api.solve_batched(probs, prec)
+        keep = api.solve_batched(probs, prec, cap_rtol=cap_rtol)
         torch.cuda.synchronize()
         del keep
         for (ra, sa), p in zip(alone, probs):
             rb = p.result()
-            assert rb.ok and rb.cap == ra.cap and rb.iters == ra.iters
+            assert rb.ok and rb.cap == ra.cap and rb.iters == ra.iters and rb.cap_bound == ra.cap_bound
             assert np.array_equal(p.sigma.cpu().numpy(), sa)
         # chunked continuous batching: resume until every system is done
         for p in probs:
             p.sigma.zero_()
         start = [1] * len(probs)
         for _ in range(10000):
-            keep = api.solve_batched(probs, prec, iter_budget=7, start=start)
+            keep = api.solve_batched(probs, prec, iter_budget=7, start=start, cap_rtol=cap_rtol)
             torch.cuda.synchronize()
             del keep
             res = [p.result() for p in probs]
@@ -358,7 +359,7 @@ def test_batched_equals_alone_bitwise(api):
                 break
             start = [0] * len(probs)
         for (ra, sa), p, rb in zip(alone, probs, res):
-            assert rb.ok and rb.cap == ra.cap
+            assert rb.ok and rb.cap == ra.cap and rb.cap_bound == ra.cap_bound
             assert np.array_equal(p.sigma.cpu().numpy(), sa)
 
 
