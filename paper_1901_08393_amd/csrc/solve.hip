@@ -64,7 +64,8 @@ struct SysBar {
 };
 
 template <int K>
-__device__ __noinline__ bool sys_sync(SysBar &B, const double (&v)[K], double (&tot)[K], double *lds, int *flag) {
+__device__ __forceinline__ bool sys_sync_body(SysBar &B, const double (&v)[K], double (&tot)[K], lptr<double> lds,
+                                              lptr<int> flag) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -156,6 +157,14 @@ __device__ __noinline__ bool sys_sync(SysBar &B, const double (&v)[K], double (&
   const int r = *flag;
   __syncthreads();
   return r != 0;
+}
+
+// The barrier as a call of its own, for the phases of the state machine
+// other than the CG iteration (which inlines it).
+template <int K>
+__device__ __noinline__ bool sys_sync(SysBar &B, const double (&v)[K], double (&tot)[K], lptr<double> lds,
+                                      lptr<int> flag) {
+  return sys_sync_body<K>(B, v, tot, lds, flag);
 }
 
 // ------------------------------------------------------- matrix product
@@ -420,8 +429,8 @@ __device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x,
 // S wavefront sums of a row are added in wavefront order.  The order depends
 // on N and the workgroup count only.
 template <typename AT>
-__device__ __noinline__ void half_gather(const HalfPlan &H, int r0, int r1, gptr<const AT> rpart,
-                                         gptr<const AT> cpart, AT *lpart, AT *band) {
+__device__ __forceinline__ void half_gather_body(const HalfPlan &H, int r0, int r1, gptr<const AT> rpart,
+                                                 gptr<const AT> cpart, lptr<AT> lpart, lptr<AT> band) {
   constexpr int NB = 16;  // loads in flight per wavefront
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int ngr = (r1 - r0 + 63) >> 6;  // groups of 64 rows
@@ -483,6 +492,12 @@ __device__ __noinline__ void half_gather(const HalfPlan &H, int r0, int r1, gptr
   }
 }
 
+template <typename AT>
+__device__ __noinline__ void half_gather(const HalfPlan &H, int r0, int r1, gptr<const AT> rpart,
+                                         gptr<const AT> cpart, lptr<AT> lpart, lptr<AT> band) {
+  half_gather_body<AT>(H, r0, r1, rpart, cpart, lpart, band);
+}
+
 // The solver's products as a call of their own.  Inlined into k_solve, the
 // product loop shares the kernel's 128 registers with the state of the
 // whole state machine and spills inside the loop; as a call it has the
@@ -499,24 +514,146 @@ __device__ __forceinline__ gptr<T> uniform_ptr(gptr<T> p) {
   return (gptr<T>)uniform64((int64_t)(uintptr_t)p);
 }
 
-template <typename MT, typename XT, typename AT, bool DELTA, bool LDS2>
-__device__ __noinline__ double solver_product(gptr<const MT> V, gptr<const XT> x, HalfPlan H, gptr<AT> rpart,
-                                              gptr<AT> cpart, lptr<AT> lbuf) {
+__device__ __forceinline__ double uniform_f64(double v) {
+  return __builtin_bit_cast(double, uniform64(__builtin_bit_cast(int64_t, v)));
+}
+__device__ __forceinline__ int uniform32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename T>
+__device__ __forceinline__ lptr<T> uniform_lptr(lptr<T> p) {
+  return (lptr<T>)(uintptr_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(uintptr_t)p);
+}
+template <typename HP>
+__device__ __forceinline__ HalfPlan uniform_plan(const HP &H) {
   HalfPlan U;
   U.ld = uniform64(H.ld);
   U.m64 = uniform64(H.m64);
   U.T = uniform64(H.T);
-  U.N = __builtin_amdgcn_readfirstlane(H.N);
-  U.nB = __builtin_amdgcn_readfirstlane(H.nB);
-  U.k = __builtin_amdgcn_readfirstlane(H.k);
-  U.G = __builtin_amdgcn_readfirstlane(H.G);
+  U.N = uniform32(H.N);
+  U.nB = uniform32(H.nB);
+  U.k = uniform32(H.k);
+  U.G = uniform32(H.G);
   U.u0 = uniform64(H.u0);
   U.u1 = uniform64(H.u1);
-  lbuf = (lptr<AT>)(uintptr_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(uintptr_t)lbuf);
+  return U;
+}
+
+template <typename MT, typename XT, typename AT, bool DELTA, bool LDS2>
+__device__ __noinline__ double solver_product(gptr<const MT> V, gptr<const XT> x, HalfPlan H, gptr<AT> rpart,
+                                              gptr<AT> cpart, lptr<AT> lbuf) {
   double delta = 0.0;
-  half_product<MT, XT, AT, DELTA, LDS2>(uniform_ptr(V), uniform_ptr(x), U, uniform_ptr(rpart), uniform_ptr(cpart),
-                                        lbuf, delta);
+  half_product<MT, XT, AT, DELTA, LDS2>(uniform_ptr(V), uniform_ptr(x), uniform_plan(H), uniform_ptr(rpart),
+                                        uniform_ptr(cpart), uniform_lptr(lbuf), delta);
   return delta;
+}
+
+// ---------------------------------------------------------- CG iterations
+// The CG phase of one system as a call of its own that runs iterations until
+// the inner tolerance, the iteration cap, the launch's budget, a breakdown
+// or an abort ends it.  Its product, gather and barriers are inlined, and
+// its state (pointers and scalars, the same in every lane) is read from LDS
+// at entry and written back at exit, so that nothing of the state machine
+// stays live across the iterations' inner calls; inlined into k_solve the
+// iteration spilled registers and saved them around every call, and the
+// barriers' fences sent that scratch traffic to HBM.
+template <typename MT>
+struct CGCtx {
+  gptr<const MT> V;
+  gptr<MT> vr, vu, vp, vs, vd, idg, rp, cp;
+  gptr<BarSlot> slots;
+  gptr<BarRel> rel;
+  HalfPlan H;
+  int r0, r1, G, rank;
+  uint32_t spin_limit;
+  int32_t max_iter;
+};
+struct CGState {
+  double alpha, beta, gamma, eta, itol;
+  int32_t iters, inner, budget;
+  uint32_t epoch;
+  int32_t exit;  // 0 budget used up, 1 inner solve done, 2 breakdown, 3 aborted
+};
+
+template <typename MT>
+__device__ __noinline__ void cg_loop(lptr<CGCtx<MT>> Cp, lptr<CGState> Sp, lptr<MT> lbuf, lptr<MT> lpart,
+                                     lptr<MT> band, lptr<double> lred, lptr<int> lflag) {
+  using VT = MT;
+  Cp = uniform_lptr(Cp);
+  Sp = uniform_lptr(Sp);
+  lbuf = uniform_lptr(lbuf);
+  lpart = uniform_lptr(lpart);
+  band = uniform_lptr(band);
+  lred = uniform_lptr(lred);
+  lflag = uniform_lptr(lflag);
+  const gptr<const MT> V = uniform_ptr(Cp->V);
+  const gptr<VT> vr = uniform_ptr(Cp->vr), vu = uniform_ptr(Cp->vu), vp = uniform_ptr(Cp->vp);
+  const gptr<VT> vs = uniform_ptr(Cp->vs), vd = uniform_ptr(Cp->vd), idg = uniform_ptr(Cp->idg);
+  const gptr<VT> rp = uniform_ptr(Cp->rp), cp = uniform_ptr(Cp->cp);
+  const HalfPlan H = uniform_plan(Cp->H);
+  const int r0 = uniform32(Cp->r0), r1 = uniform32(Cp->r1), max_iter = uniform32(Cp->max_iter);
+  SysBar bar{uniform_ptr(Cp->slots), uniform_ptr(Cp->rel), uniform32(Cp->G), uniform32(Cp->rank),
+             (unsigned)uniform32((int)Sp->epoch), (uint32_t)uniform32((int)Cp->spin_limit)};
+  double alpha = uniform_f64(Sp->alpha), beta = uniform_f64(Sp->beta), gamma = uniform_f64(Sp->gamma);
+  double eta = uniform_f64(Sp->eta);
+  const double itol = uniform_f64(Sp->itol);
+  int iters = uniform32(Sp->iters), inner = uniform32(Sp->inner), budget = uniform32(Sp->budget);
+  const int t = threadIdx.x;
+  int ex = 0;
+  while (true) {
+    if (budget <= 0) { ex = 0; break; }
+    budget -= 1;
+    // w = V u of the last product
+    half_gather_body<VT>(H, r0, r1, rp, cp, lpart, band);
+    const VT a = (VT)alpha, bt = (VT)beta;
+    double pru = 0.0, prr = 0.0;
+    // the lane's first row, formed anew in every iteration: kept across the
+    // product instead, the vectors' addresses would be spilled
+    int i0 = r0 + t;
+    asm volatile("" : "+v"(i0));
+    for (int i = i0; i < r1; i += kSolveWG) {
+      const VT pi = vu[i] + bt * vp[i];
+      const VT si = band[i - r0] + bt * vs[i];
+      vp[i] = pi;
+      vs[i] = si;
+      vd[i] = vd[i] + a * pi;
+      const VT ri = vr[i] - a * si;
+      vr[i] = ri;
+      const VT ui = idg[i] * ri;
+      vu[i] = ui;
+      pru += (double)ri * (double)ui;
+      prr += (double)ri * (double)ri;
+    }
+    double gnew, rr;
+    {
+      const double v[2] = {pru, prr};
+      double tot[2];
+      if (!sys_sync_body<2>(bar, v, tot, lred, lflag)) { ex = 3; break; }
+      gnew = tot[0];
+      rr = tot[1];
+    }
+    inner += 1;
+    if (!(sqrt(rr) > itol) || iters >= max_iter) { ex = 1; break; }
+    double pwu = 0.0;
+    half_product<MT, VT, VT, true, true>(V, vu, H, rp, cp, lbuf, pwu);
+    double delta;
+    {
+      const double v[1] = {pwu};
+      double tot[1];
+      if (!sys_sync_body<1>(bar, v, tot, lred, lflag)) { ex = 3; break; }
+      delta = tot[0];
+    }
+    iters += 1;
+    beta = gnew / gamma;
+    eta = delta - beta * gnew / alpha;
+    if (!(eta > 0.0)) { ex = 2; break; }
+    alpha = gnew / eta;
+    gamma = gnew;
+  }
+  __syncthreads();  // every lane has read the state before it is rewritten
+  if (t == 0) {
+    Sp->alpha = alpha; Sp->beta = beta; Sp->gamma = gamma; Sp->eta = eta;
+    Sp->iters = iters; Sp->inner = inner; Sp->budget = budget; Sp->epoch = bar.epoch; Sp->exit = ex;
+  }
+  __syncthreads();
 }
 
 // At most 128 VGPRs, so that one 1024-thread workgroup fits on every CU.
@@ -530,6 +667,10 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
   __shared__ double s_buf[4096];       // column sums of the symmetric product (32 KB)
   __shared__ double s_part[16 * 64];   // per-wavefront sums of half_gather
   __shared__ double s_band[kMaxBand];  // V x on this workgroup's rows
+  __shared__ CGCtx<MT> s_cg;
+  __shared__ CGState s_st;
+  const lptr<double> l_red = (lptr<double>)s_red;
+  const lptr<int> l_flag = (lptr<int>)&s_flag;
 
   // system of this workgroup: last descriptor with wg_begin <= blockIdx.x
   int lo = 0, hi = P.n_sys - 1;
@@ -585,6 +726,17 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
   int budget = S.budget > 0 ? S.budget : (P.iter_budget > 0 ? P.iter_budget : INT_MAX);
   bool aborted = false;
   const double none[1] = {0.0};
+  if (t == 0) {
+    s_cg.V = V;
+    s_cg.vr = vr; s_cg.vu = vu; s_cg.vp = vp; s_cg.vs = vs; s_cg.vd = vd; s_cg.idg = idg;
+    s_cg.rp = rpV; s_cg.cp = cpV;
+    s_cg.slots = bar.slots; s_cg.rel = bar.rel;
+    s_cg.H = H;
+    s_cg.r0 = r0; s_cg.r1 = r1; s_cg.G = G; s_cg.rank = rank;
+    s_cg.spin_limit = P.spin_limit;
+    s_cg.max_iter = P.max_iter;
+  }
+  __syncthreads();
 
   while (true) {
     if (phase == PH_INIT) {
@@ -599,7 +751,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
           idg[i] = VT(0);
         }
       double dummy[1];
-      if (!sys_sync<1>(bar, none, dummy, s_red, &s_flag)) { aborted = true; break; }
+      if (!sys_sync<1>(bar, none, dummy, l_red, l_flag)) { aborted = true; break; }
       phase = PH_RESID;
       continue;
     }
@@ -611,8 +763,8 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       if (!zero_x) {
         double unused = 0.0, dummy[1];
         unused = solver_product<MT, double, double, false, false>(V, x64, H, rpD, cpD, (lptr<double>)s_buf);
-        if (!sys_sync<1>(bar, none, dummy, s_red, &s_flag)) { aborted = true; break; }
-        half_gather<double>(H, r0, r1, rpD, cpD, s_part, s_band);
+        if (!sys_sync<1>(bar, none, dummy, l_red, l_flag)) { aborted = true; break; }
+        half_gather<double>(H, r0, r1, rpD, cpD, (lptr<double>)s_part, (lptr<double>)s_band);
       }
       double pr = 0.0, pb = 0.0, pxx = 0.0, pbx = 0.0;
       for (int i = r0 + t; i < r1; i += kSolveWG) {
@@ -634,7 +786,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       {
         const double v[4] = {pr, pb, pxx, pbx};
         double tot[4];
-        if (!sys_sync<4>(bar, v, tot, s_red, &s_flag)) { aborted = true; break; }
+        if (!sys_sync<4>(bar, v, tot, l_red, l_flag)) { aborted = true; break; }
         if (outer == 0) bnorm = sqrt(tot[1]);
         rnorm = sqrt(tot[0]);
         target = P.rtol * bnorm;
@@ -657,7 +809,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       {
         const double v[1] = {pru};
         double tot[1];
-        if (!sys_sync<1>(bar, v, tot, s_red, &s_flag)) { aborted = true; break; }
+        if (!sys_sync<1>(bar, v, tot, l_red, l_flag)) { aborted = true; break; }
         gamma = tot[0];
       }
       double pwu = 0.0;
@@ -665,7 +817,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       {
         const double v[1] = {pwu};
         double tot[1];
-        if (!sys_sync<1>(bar, v, tot, s_red, &s_flag)) { aborted = true; break; }
+        if (!sys_sync<1>(bar, v, tot, l_red, l_flag)) { aborted = true; break; }
         eta = tot[0];
       }
       iters += 1;
@@ -677,56 +829,29 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       continue;
     }
     if (phase == PH_CG) {
-      if (budget <= 0) break;
-      budget -= 1;
-      // w = V u of the last product
-      half_gather<VT>(H, r0, r1, rpV, cpV, reinterpret_cast<VT *>(s_part), bandV);
-      const VT a = (VT)alpha, bt = (VT)beta;
-      double pru = 0.0, prr = 0.0;
-      for (int i = r0 + t; i < r1; i += kSolveWG) {
-        const VT pi = vu[i] + bt * vp[i];
-        const VT si = bandV[i - r0] + bt * vs[i];
-        vp[i] = pi;
-        vs[i] = si;
-        vd[i] = vd[i] + a * pi;
-        const VT ri = vr[i] - a * si;
-        vr[i] = ri;
-        const VT ui = idg[i] * ri;
-        vu[i] = ui;
-        pru += (double)ri * (double)ui;
-        prr += (double)ri * (double)ri;
+      if (t == 0) {
+        s_st.alpha = alpha; s_st.beta = beta; s_st.gamma = gamma; s_st.eta = eta; s_st.itol = itol;
+        s_st.iters = iters; s_st.inner = inner; s_st.budget = budget; s_st.epoch = bar.epoch;
       }
-      double gnew, rr;
-      {
-        const double v[2] = {pru, prr};
-        double tot[2];
-        if (!sys_sync<2>(bar, v, tot, s_red, &s_flag)) { aborted = true; break; }
-        gnew = tot[0];
-        rr = tot[1];
-      }
-      inner += 1;
-      if (!(sqrt(rr) > itol) || iters >= P.max_iter) { phase = PH_UPDATE; continue; }
-      double pwu = 0.0;
-      pwu = solver_product<MT, VT, VT, true, true>(V, vu, H, rpV, cpV, (lptr<VT>)s_buf);
-      double delta;
-      {
-        const double v[1] = {pwu};
-        double tot[1];
-        if (!sys_sync<1>(bar, v, tot, s_red, &s_flag)) { aborted = true; break; }
-        delta = tot[0];
-      }
-      iters += 1;
-      beta = gnew / gamma;
-      eta = delta - beta * gnew / alpha;
-      if (!(eta > 0.0)) { status = BC_EBREAKDOWN; phase = PH_DONE; continue; }
-      alpha = gnew / eta;
-      gamma = gnew;
+      __syncthreads();
+      cg_loop<MT>((lptr<CGCtx<MT>>)&s_cg, (lptr<CGState>)&s_st, (lptr<VT>)s_buf, (lptr<VT>)s_part, (lptr<VT>)s_band,
+                  l_red, l_flag);
+      alpha = uniform_f64(s_st.alpha); beta = uniform_f64(s_st.beta); gamma = uniform_f64(s_st.gamma);
+      eta = uniform_f64(s_st.eta);
+      iters = uniform32(s_st.iters); inner = uniform32(s_st.inner); budget = uniform32(s_st.budget);
+      bar.epoch = (unsigned)uniform32((int)s_st.epoch);
+      const int ex = uniform32(s_st.exit);
+      __syncthreads();  // the state is read before a later phase writes it again
+      if (ex == 0) break;  // this launch's budget is used up; the next one resumes here
+      if (ex == 3) { aborted = true; break; }
+      if (ex == 2) { status = BC_EBREAKDOWN; phase = PH_DONE; continue; }
+      phase = PH_UPDATE;
       continue;
     }
     if (phase == PH_UPDATE) {
       for (int i = r0 + t; i < r1; i += kSolveWG) x64[i] = __builtin_fma((double)vd[i], rnorm, x64[i]);
       double dummy[1];
-      if (!sys_sync<1>(bar, none, dummy, s_red, &s_flag)) { aborted = true; break; }
+      if (!sys_sync<1>(bar, none, dummy, l_red, l_flag)) { aborted = true; break; }
       phase = PH_RESID;
       continue;
     }
@@ -742,7 +867,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
     {
       const double v[2] = {pc, pxx};
       double tot[2];
-      if (!sys_sync<2>(bar, v, tot, s_red, &s_flag)) { aborted = true; break; }
+      if (!sys_sync<2>(bar, v, tot, l_red, l_flag)) { aborted = true; break; }
       cap = tot[0] * kInv4Pi;
       cap_bound = tot[0] != 0.0 ? sqrt(tot[1]) * rnorm / fabs(tot[0]) : 0.0;
     }
@@ -924,7 +1049,7 @@ __global__ __launch_bounds__(kSolveWG) void k_matvec_gather(int64_t N, const cha
   for (int m = 0; m < NR; ++m) {
     half_gather<XT>(H, r0, r1, reinterpret_cast<gptr<const XT>>(w + Lay.rpart) + (size_t)m * kRB * Lay.T,
                     reinterpret_cast<gptr<const XT>>(w + Lay.cpart) + (size_t)m * Lay.nB * Lay.ld,
-                    reinterpret_cast<XT *>(s_part), band);
+                    (lptr<XT>)s_part, (lptr<XT>)s_band);
     for (int i = r0 + (int)threadIdx.x; i < r1; i += kSolveWG) y[m * N + i] = band[i - r0];
     __syncthreads();  // band is rewritten by the next vector's gather
   }
