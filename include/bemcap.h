@@ -120,7 +120,10 @@ typedef struct bc_assembly_opts {
                          rule (81 instead of 256 point pairs).  There its
                          relative error is at most 9e-10, below the FP32
                          rounding of the stored entry (6e-8).  0: one far
-                         rule everywhere.  Must be 0 for BC_FP64. */
+                         rule everywhere.  Ignored for far_order < 4; must
+                         be 0 for BC_FP64.  The tile lists it uses are built
+                         by bc_prepare, so bc_prepare must have run on the
+                         mesh workspace before bc_assemble. */
   double near_factor; /* BC_MIXED: pairs sharing no vertex with
                          |c_i - c_j|^2 < near_factor^2 max(diam_i, diam_j)^2
                          are computed in FP64 and corrected exactly; 0 = none.
@@ -138,16 +141,20 @@ typedef struct bc_pattern_info {
   int64_t n_near;       /* unordered near pairs (BC_MIXED) */
 } bc_pattern_info;
 
-/* Workspace for the mesh tables (geometry, quadrature points, row pointers
- * of the pattern).  Depends on N only. */
+/* Workspace for the mesh tables (geometry, quadrature points of the 4 x 4
+ * and 3 x 3 rules, row pointers of the pattern, and the far-field tile lists:
+ * the 64 x 64 element tiles of the upper block triangle by class, near or
+ * diagonal / separated / at least 12 element diameters apart).  Depends on
+ * N only. */
 size_t bc_mesh_workspace_bytes(int64_t N);
 
 /* Workspace for the pattern itself (row pointers, and column, class and row
  * of each entry, plus the FP64 correction values for BC_MIXED). */
 size_t bc_pattern_bytes(int64_t N, int64_t nnz, int32_t precision);
 
-/* Element geometry and pair classification (Section 2.1: pairs are told apart
- * by shared vertex indices of the conforming mesh).  Fills d_mesh_ws and
+/* Element geometry, pair classification (Section 2.1: pairs are told apart
+ * by shared vertex indices of the conforming mesh) and the far-field tile
+ * lists.  Fills d_mesh_ws and
  * writes the pattern sizes to *h_info.  SYNCHRONOUS (waits for `stream`),
  * because the caller needs nnz to size the pattern buffer.  d_verts, d_tris
  * must stay unchanged until bc_assemble and bc_zz_indicators have run. */
@@ -159,7 +166,7 @@ int32_t bc_prepare(const double *d_verts, int64_t M, const int32_t *d_tris,
 /* Dense Galerkin matrix (Appendix A, eq. "discreteform:residual"; kernel of
  * eq. "strongform").  Pairs sharing no vertex use the collapsed Gauss rule
  * (FP64 for BC_FP64, FP32 with FP64-formed centroid differences for
- * BC_MIXED); touching pairs use the Sauter-Schwab-type rules in FP64; in
+ * BC_MIXED, the 3 x 3 rule on distant tiles with opts->far_low); touching pairs use the Sauter-Schwab-type rules in FP64; in
  * BC_MIXED near pairs are recomputed in FP64 too and d_pattern receives the
  * FP64 correction V64 - (double)(float)V64 of every pattern entry.  Only
  * i <= j is integrated; V[j][i] = V[i][j] exactly.  d_V: N x ld, double
