@@ -246,37 +246,60 @@ __global__ __launch_bounds__(kWG) void k_pattern(const int4 *__restrict__ tri4, 
     base[k] = (EMIT && i < N) ? rowptr[i] : 0;
   }
   const double *rb = bbox + 8 * blockIdx.x;
-  for (int J0 = 0; J0 < N; J0 += 64) {
-    {
-      const double *cb = bbox + 8 * (J0 / 64);
+  const int nblk = (N + 63) / 64;
+  // Column blocks in rounds of kWG: the box tests of a round run in parallel
+  // and the blocks that pass are listed in LDS in increasing order (wave
+  // ballots, then the waves' counts in wave order), then swept.
+  __shared__ int s_cand[kWG];
+  __shared__ int s_wcnt[kWG / 64];
+  for (int R0 = 0; R0 < nblk; R0 += kWG) {
+    const int Jb = R0 + (int)threadIdx.x;
+    bool keep = false;
+    if (Jb < nblk) {
+      const double *cb = bbox + 8 * Jb;
       const double thr = nf2 * fmax(rb[6], cb[6]);
-      if (box_dist2(rb, cb) > thr * (1.0 + 1e-9)) continue;  // uniform over the workgroup
+      keep = !(box_dist2(rb, cb) > thr * (1.0 + 1e-9));
     }
-    const int j = J0 + lane;
-    const bool jv = j < N;
-    int4 tj = tri4[jv ? j : N - 1];
-    double4 cj = cen4[jv ? j : N - 1];
+    const uint64_t km = __ballot(keep);
+    if (lane == 0) s_wcnt[w] = __popcll(km);
+    __syncthreads();
+    int off = 0, ncand = 0;
+    for (int q = 0; q < kWG / 64; ++q) {
+      if (q < w) off += s_wcnt[q];
+      ncand += s_wcnt[q];
+    }
+    if (keep) s_cand[off + __popcll(km & ((1ull << lane) - 1ull))] = Jb;
+    __syncthreads();
+    ncand = __builtin_amdgcn_readfirstlane(ncand);
+    for (int c = 0; c < ncand; ++c) {
+      const int J0 = 64 * __builtin_amdgcn_readfirstlane(s_cand[c]);
+      const int j = J0 + lane;
+      const bool jv = j < N;
+      int4 tj = tri4[jv ? j : N - 1];
+      double4 cj = cen4[jv ? j : N - 1];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int i = I0 + w * 16 + k;
-      if (i < N) {  // uniform
-        int cls = jv ? pair_class(s_tri[w * 16 + k], s_cen[w * 16 + k], tj, cj, nf2) : -1;
-        uint64_t m = __ballot(cls >= 0);
-        if (!EMIT) {
-          cnt[k] += __popcll(m);
+      for (int k = 0; k < 16; ++k) {
+        const int i = I0 + w * 16 + k;
+        if (i < N) {  // uniform
+          int cls = jv ? pair_class(s_tri[w * 16 + k], s_cen[w * 16 + k], tj, cj, nf2) : -1;
+          uint64_t m = __ballot(cls >= 0);
+          if (!EMIT) {
+            cnt[k] += __popcll(m);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) kc[k][q] += __popcll(__ballot(cls == q && j >= i));
-        } else {
-          if (cls >= 0) {
-            int pos = base[k] + __popcll(m & ((1ull << lane) - 1ull));
-            pcol[pos] = j;
-            prow[pos] = i;
-            pkind[pos] = cls;
+            for (int q = 0; q < 4; ++q) kc[k][q] += __popcll(__ballot(cls == q && j >= i));
+          } else {
+            if (cls >= 0) {
+              int pos = base[k] + __popcll(m & ((1ull << lane) - 1ull));
+              pcol[pos] = j;
+              prow[pos] = i;
+              pkind[pos] = cls;
+            }
+            base[k] += __popcll(m);
           }
-          base[k] += __popcll(m);
         }
       }
     }
+    __syncthreads();  // s_cand and s_wcnt are rewritten by the next round
   }
   if (!EMIT && lane == 0) {
 #pragma unroll
@@ -291,51 +314,57 @@ __global__ __launch_bounds__(kWG) void k_pattern(const int4 *__restrict__ tri4, 
 }
 
 // Exclusive scan of the row counts (one workgroup of 1024 threads, each
-// owning a contiguous chunk) and the totals by class.  info[0] = nnz,
-// info[1..4] = coincident, edge, vertex, near pairs (i <= j); info[5] = 1 if
-// nnz overflows int32.
+// owning a contiguous chunk: chunk sums, an exclusive scan of them by wave
+// scans and the waves' totals in wave order, then the chunk's row pointers)
+// and the totals by class (integers: any summation order gives the same).
+// info[0] = nnz, info[1..4] = coincident, edge, vertex, near pairs (i <= j);
+// info[5] = 1 if nnz overflows int32.
 __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ rowcnt,
                                                const int32_t *__restrict__ kindcnt, int N,
                                                int32_t *rowptr, int64_t *info) {
-  __shared__ int64_t s_sum[1024];
-  __shared__ int64_t s_kind[4][1024];
-  const int t = threadIdx.x;
+  __shared__ int64_t s_w[16];
+  __shared__ int64_t s_wk[4][16];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int chunk = (N + 1023) / 1024;
   const int b = min(N, t * chunk), e = min(N, b + chunk);
-  int64_t s = 0, k0 = 0, k1 = 0, k2 = 0, k3 = 0;
+  int64_t s = 0, k[4] = {0, 0, 0, 0};
+#pragma unroll 4
   for (int i = b; i < e; ++i) {
     s += rowcnt[i];
-    k0 += kindcnt[4 * i + 0];
-    k1 += kindcnt[4 * i + 1];
-    k2 += kindcnt[4 * i + 2];
-    k3 += kindcnt[4 * i + 3];
+    const int4 kc = *reinterpret_cast<const int4 *>(kindcnt + 4 * i);
+    k[0] += kc.x;
+    k[1] += kc.y;
+    k[2] += kc.z;
+    k[3] += kc.w;
   }
-  s_sum[t] = s;
-  s_kind[0][t] = k0;
-  s_kind[1][t] = k1;
-  s_kind[2][t] = k2;
-  s_kind[3][t] = k3;
+  int64_t inc = s;  // inclusive scan over the wavefront's lanes
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t v = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += v;
+  }
+  for (int q = 0; q < 4; ++q)
+    for (int off = 32; off >= 1; off >>= 1) k[q] += __shfl_xor(k[q], off, 64);
+  if (lane == 63) s_w[w] = inc;
+  if (lane == 0)
+    for (int q = 0; q < 4; ++q) s_wk[q][w] = k[q];
   __syncthreads();
+  int64_t woff = 0, tot = 0;
+  for (int q = 0; q < 16; ++q) {
+    if (q < w) woff += s_w[q];
+    tot += s_w[q];
+  }
   if (t == 0) {
-    int64_t acc = 0, q0 = 0, q1 = 0, q2 = 0, q3 = 0;
-    for (int k = 0; k < 1024; ++k) {
-      int64_t v = s_sum[k];
-      s_sum[k] = acc;
-      acc += v;
-      q0 += s_kind[0][k];
-      q1 += s_kind[1][k];
-      q2 += s_kind[2][k];
-      q3 += s_kind[3][k];
-    }
-    info[0] = acc;
-    info[1] = q3;
-    info[2] = q2;
-    info[3] = q1;
-    info[4] = q0;
-    info[5] = acc > 2147483647ll ? 1 : 0;
+    int64_t kt[4] = {0, 0, 0, 0};
+    for (int q = 0; q < 4; ++q)
+      for (int v = 0; v < 16; ++v) kt[q] += s_wk[q][v];
+    info[0] = tot;
+    info[1] = kt[3];
+    info[2] = kt[2];
+    info[3] = kt[1];
+    info[4] = kt[0];
+    info[5] = tot > 2147483647ll ? 1 : 0;
   }
-  __syncthreads();
-  int64_t acc = s_sum[t];
+  int64_t acc = woff + inc - s;
   for (int i = b; i < e; ++i) {
     rowptr[i] = (int32_t)acc;
     acc += rowcnt[i];
