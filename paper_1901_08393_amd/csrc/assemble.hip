@@ -408,15 +408,13 @@ __device__ __forceinline__ double ss_map(int kind, int reg, double xi, double e1
 }
 
 template <bool MIXED>
-__global__ __launch_bounds__(kWG) void k_sparse(const double *__restrict__ verts, const int4 *__restrict__ tri4,
-                                                const double *__restrict__ area, const double4 *__restrict__ qpA,
-                                                int Q, SSRule ss, const int32_t *__restrict__ prowptr,
-                                                const int32_t *__restrict__ pcol, const int32_t *__restrict__ prow,
-                                                const int32_t *__restrict__ pkind, double *__restrict__ pcorr,
-                                                int64_t nnz, int64_t ld, void *__restrict__ Vout) {
+__device__ __forceinline__ void sparse_entry(int64_t e, const double *__restrict__ verts,
+                                             const int4 *__restrict__ tri4, const double *__restrict__ area,
+                                             const double4 *__restrict__ qpA, int Q, const SSRule &ss,
+                                             const int32_t *__restrict__ prowptr, const int32_t *__restrict__ pcol,
+                                             const int32_t *__restrict__ prow, const int32_t *__restrict__ pkind,
+                                             double *__restrict__ pcorr, int64_t ld, void *__restrict__ Vout) {
   const int lane = threadIdx.x & 63;
-  const int64_t e = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (e >= nnz) return;
   const int i = prow[e], j = pcol[e];
   if (j < i) return;
   const int kind = pkind[e];
@@ -510,6 +508,20 @@ __global__ __launch_bounds__(kWG) void k_sparse(const double *__restrict__ verts
   }
 }
 
+// One wavefront per pattern entry.  (Fewer wavefronts taking the entries
+// grid-stride were slower: an entry's chain of dependent loads is then
+// waited for one entry after another.)
+template <bool MIXED>
+__global__ __launch_bounds__(kWG) void k_sparse(const double *__restrict__ verts, const int4 *__restrict__ tri4,
+                                                const double *__restrict__ area, const double4 *__restrict__ qpA,
+                                                int Q, SSRule ss, const int32_t *__restrict__ prowptr,
+                                                const int32_t *__restrict__ pcol, const int32_t *__restrict__ prow,
+                                                const int32_t *__restrict__ pkind, double *__restrict__ pcorr,
+                                                int64_t nnz, int64_t ld, void *__restrict__ Vout) {
+  const int64_t e = (int64_t)blockIdx.x * (kWG / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (e < nnz) sparse_entry<MIXED>(e, verts, tri4, area, qpA, Q, ss, prowptr, pcol, prow, pkind, pcorr, ld, Vout);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_pad(T *V, int N, int64_t ld) {
   const int64_t pad = ld - N;
@@ -521,6 +533,16 @@ __global__ __launch_bounds__(kWG) void k_pad(T *V, int N, int64_t ld) {
 
 // (1/4pi) (sum_k w_k / sum_k fl32(w_k))^2 for the collapsed rule of order n
 static double far32_scale(int n);
+
+// Compute units of the current device (256 on MI355X), for launches sized to
+// what fits on the chip at once.
+static int device_cus() {
+  int cus = 256, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+      hipSuccess || cus < 1)
+    cus = 256;
+  return cus;
+}
 
 template <int Q>
 static void far_launch(bool mixed, bool low_order, const MeshView &m, int N, int64_t ld, void *V, int tiles,
@@ -534,11 +556,7 @@ static void far_launch(bool mixed, bool low_order, const MeshView &m, int N, int
     // matrix cores (those at least kSepFarLow apart with the 3 x 3 rule when
     // low_order).  The matrix-core kernels run as many workgroups as fit on
     // the chip at once (two per CU) and take the tiles grid-stride.
-    int cus = 256;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-        hipSuccess || cus < 1)
-      cus = 256;
+    const int cus = device_cus();
     const int nt = (int)far_tiles(N);
     const int32_t *cnt = m.tile_cnt, *list = m.tile_list;
     FarWeights w16{}, w9{};
