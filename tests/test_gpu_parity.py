@@ -450,6 +450,10 @@ def test_warm_start_same_answer(api):
     r1 = p.solve(x0=x0)
     assert r1.ok and abs(r1.cap - r0.cap) <= 1e-12 * r0.cap
     assert r1.iters < r0.iters
+    # started from the converged solution, the capacity stop needs no product
+    r2 = p.solve(x0=p.sigma.clone(), rtol=0.0, cap_rtol=1e-8)
+    assert r2.ok and r2.iters == 0 and r2.outer == 1 and r2.cap_bound <= 1e-8
+    assert r2.cap == r1.cap  # the same sigma, the same fixed-order sum
 
 
 # ------------------------------------------------- full-size sampled checks
