@@ -274,13 +274,15 @@ struct FarWeights {
 // -r^2 for rows 4 (l / 16) .. + 3 and column l % 16, and only the inverse
 // square roots and the weighted sums remain on the vector ALU.  The sums,
 // weights, scale and bias correction are those of k_far32.  QP points per
-// element: the 4 x 4 rule (16) or the 3 x 3 rule of distant tiles (9), from
-// the geometry tables qpA (QP per element) and qpS (per point).
+// element: the 4 x 4 rule (16) or the 3 x 3 rule of distant tiles (9); the
+// row points from the FP64 table qpA (QP per element), the column operands
+// from qpB (per point, relative to the column element's own block, which is
+// the column block; tabulated by bc_prepare).
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <int QP>
 __device__ __forceinline__ void far32m_tile(int I, int J, const double4 *__restrict__ qpA,
-                                            const double *__restrict__ qpS, const FarWeights &fw,
+                                            const float *__restrict__ qpB, const FarWeights &fw,
                                             const double *__restrict__ area, const double *__restrict__ bbox,
                                             double scale, int N, int64_t ld, float *__restrict__ V) {
   static_assert(QP == 16 || QP == 9, "far rule of 16 or 9 points");
@@ -302,12 +304,11 @@ __device__ __forceinline__ void far32m_tile(int I, int J, const double4 *__restr
   }
   float S[4] = {0.f, 0.f, 0.f, 0.f};
   for (int b = 0; b < QP; ++b) {
-    const double yx = qpS[(size_t)(b * 4 + 0) * N + jb] - fx;
-    const double yy = qpS[(size_t)(b * 4 + 1) * N + jb] - fy;
-    const double yz = qpS[(size_t)(b * 4 + 2) * N + jb] - fz;
+    // the column point relative to the column block's box centre, and its
+    // squared norm (tabulated by bc_prepare)
+    const float bv = k < 3 ? qpB[(size_t)(b * 4 + k) * N + jb] : 1.0f;
+    const float yn = qpB[(size_t)(b * 4 + 3) * N + jb];
     const float wb = fw.w[b];
-    const float bv = k == 0 ? (float)yx : (k == 1 ? (float)yy : (k == 2 ? (float)yz : 1.0f));
-    const float yn = (float)(yx * yx + yy * yy + yz * yz);
     const v4f C = {-yn, -yn, -yn, -yn};
     float Sb[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -340,7 +341,7 @@ __device__ __forceinline__ void far32m_tile(int I, int J, const double4 *__restr
 // The tiles of one list, grid-stride (no workgroup barrier: a wavefront
 // that has nothing to do in a tile goes on to the next).
 template <int QP>
-__global__ __launch_bounds__(1024) void k_far32m(const double4 *__restrict__ qpA, const double *__restrict__ qpS,
+__global__ __launch_bounds__(1024) void k_far32m(const double4 *__restrict__ qpA, const float *__restrict__ qpB,
                                                  FarWeights fw, const double *__restrict__ area,
                                                  const double *__restrict__ bbox, const int32_t *__restrict__ cnt,
                                                  const int32_t *__restrict__ list, double scale, int N, int64_t ld,
@@ -351,7 +352,7 @@ __global__ __launch_bounds__(1024) void k_far32m(const double4 *__restrict__ qpA
     if (t < 0 || t >= nt) continue;  // lists from another mesh: nothing out of range
     int I, J;
     tile_of(t, I, J);
-    far32m_tile<QP>(I, J, qpA, qpS, fw, area, bbox, scale, N, ld, V);
+    far32m_tile<QP>(I, J, qpA, qpB, fw, area, bbox, scale, N, ld, V);
   }
 }
 
@@ -570,13 +571,13 @@ static void far_launch(bool mixed, bool low_order, const MeshView &m, int N, int
     const int gv = std::min(nt, 4 * cus), gm = std::min(nt, 2 * cus);
     hipLaunchKernelGGL((k_far32<Q, true>), dim3(gv), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox, cnt,
                        list, scale, N, ld, static_cast<float *>(V));
-    hipLaunchKernelGGL(k_far32m<16>, dim3(gm), dim3(1024), 0, s, m.qpA64, m.qpS64, w16, m.area, m.bbox, cnt + 1,
+    hipLaunchKernelGGL(k_far32m<16>, dim3(gm), dim3(1024), 0, s, m.qpA64, m.qpB16, w16, m.area, m.bbox, cnt + 1,
                        list + (size_t)nt, scale, N, ld, static_cast<float *>(V));
     if (low_order)
-      hipLaunchKernelGGL(k_far32m<9>, dim3(gm), dim3(1024), 0, s, m.qp9A64, m.qp9S64, w9, m.area, m.bbox, cnt + 2,
+      hipLaunchKernelGGL(k_far32m<9>, dim3(gm), dim3(1024), 0, s, m.qp9A64, m.qpB9, w9, m.area, m.bbox, cnt + 2,
                          list + 2 * (size_t)nt, far32_scale(3), N, ld, static_cast<float *>(V));
     else
-      hipLaunchKernelGGL(k_far32m<16>, dim3(gm), dim3(1024), 0, s, m.qpA64, m.qpS64, w16, m.area, m.bbox, cnt + 2,
+      hipLaunchKernelGGL(k_far32m<16>, dim3(gm), dim3(1024), 0, s, m.qpA64, m.qpB16, w16, m.area, m.bbox, cnt + 2,
                          list + 2 * (size_t)nt, scale, N, ld, static_cast<float *>(V));
   } else {
     hipLaunchKernelGGL((k_far32<Q, false>), dim3(tiles), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox,

@@ -31,8 +31,8 @@ __host__ __device__ inline int64_t far_tiles(int64_t N) {
 }
 
 struct MeshLayout {
-  size_t tri4, cen4, area, qpA64, qpS64, qpA32, qpS32, qp9A64, qp9S64, rowcnt, rowptr, kindcnt, info, blockbox,
-      tiles, total;
+  size_t tri4, cen4, area, qpA64, qpS64, qpA32, qpS32, qp9A64, qp9S64, qpB16, qpB9, rowcnt, rowptr, kindcnt, info,
+      blockbox, tiles, total;
   explicit MeshLayout(int64_t N) {
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
@@ -45,6 +45,12 @@ struct MeshLayout {
     qpS32 = take(sizeof(float) * 4 * kQMax * N);
     qp9A64 = take(sizeof(double) * 4 * 9 * N);  // the 3 x 3 rule, same layouts as qpA64 / qpS64
     qp9S64 = take(sizeof(double) * 4 * 9 * N);
+    // column operands of the matrix-core far field, per point [(b*4+c)][N]:
+    // the point relative to the centre of its own 64-element block's box,
+    // rounded once to FP32 (c = 0..2), and the squared norm of that FP64
+    // offset rounded once (c = 3); for the 4 x 4 and the 3 x 3 rule
+    qpB16 = take(sizeof(float) * 4 * kQMax * N);
+    qpB9 = take(sizeof(float) * 4 * 9 * N);
     rowcnt = take(sizeof(int32_t) * N);
     rowptr = take(sizeof(int32_t) * (N + 1));
     kindcnt = take(sizeof(int32_t) * 4 * N);
@@ -71,6 +77,8 @@ struct MeshView {
   const double *bbox;    // per 64 elements: min xyz, max xyz, max diam^2, 0
   const double4 *qp9A64; // [N][9], the 3 x 3 rule
   const double *qp9S64;  // [(b*4+c)][N]
+  const float *qpB16;    // [(b*4+c)][N], see MeshLayout
+  const float *qpB9;
   const int32_t *tile_cnt;   // kTileClasses counts
   const int32_t *tile_list;  // [kTileClasses][far_tiles(N)]
 };
@@ -90,6 +98,8 @@ inline MeshView mesh_view(const void *ws, int64_t N) {
   v.bbox = reinterpret_cast<const double *>(b + L.blockbox);
   v.qp9A64 = reinterpret_cast<const double4 *>(b + L.qp9A64);
   v.qp9S64 = reinterpret_cast<const double *>(b + L.qp9S64);
+  v.qpB16 = reinterpret_cast<const float *>(b + L.qpB16);
+  v.qpB9 = reinterpret_cast<const float *>(b + L.qpB9);
   v.tile_cnt = reinterpret_cast<const int32_t *>(b + L.tiles);
   v.tile_list = v.tile_cnt + 16;
   return v;

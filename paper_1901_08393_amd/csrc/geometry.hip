@@ -142,6 +142,33 @@ __global__ __launch_bounds__(64) void k_blockbox(const double *__restrict__ vert
 }
 
 
+// Column operands of the matrix-core far field (MeshLayout::qpB16, qpB9):
+// each point of the 4 x 4 and 3 x 3 rules relative to the centre of its own
+// element block's box (FP64, rounded once) and the squared norm of that
+// offset.  The kernel takes the frame of the column block, which is the
+// column element's own block, so these are per element.
+__global__ __launch_bounds__(kWG) void k_colpoints(const double *__restrict__ qpS64, const double *__restrict__ qp9S64,
+                                                   const double *__restrict__ bbox, int N, float *__restrict__ qpB16,
+                                                   float *__restrict__ qpB9) {
+  const int e = blockIdx.x * kWG + threadIdx.x;
+  if (e >= N) return;
+  const double *bx = bbox + 8 * (e / 64);
+  const double fx = 0.5 * (bx[0] + bx[3]), fy = 0.5 * (bx[1] + bx[4]), fz = 0.5 * (bx[2] + bx[5]);
+  auto put = [&](const double *S, float *B, int nq) {
+    for (int b = 0; b < nq; ++b) {
+      const double yx = S[(size_t)(b * 4 + 0) * N + e] - fx;
+      const double yy = S[(size_t)(b * 4 + 1) * N + e] - fy;
+      const double yz = S[(size_t)(b * 4 + 2) * N + e] - fz;
+      B[(size_t)(b * 4 + 0) * N + e] = (float)yx;
+      B[(size_t)(b * 4 + 1) * N + e] = (float)yy;
+      B[(size_t)(b * 4 + 2) * N + e] = (float)yz;
+      B[(size_t)(b * 4 + 3) * N + e] = (float)(yx * yx + yy * yy + yz * yz);
+    }
+  };
+  put(qpS64, qpB16, kQMax);
+  put(qp9S64, qpB9, 9);
+}
+
 // Far-field tile lists: the tiles of the upper block triangle of each class
 // (kTileClasses), in tile order, so that each far-field kernel runs over its
 // own tiles only and neighbouring workgroups share column blocks in the
@@ -427,6 +454,9 @@ int launch_pattern(const double *verts, const int32_t *tris, int64_t N, double n
     int32_t *tile_cnt = reinterpret_cast<int32_t *>(base + L.tiles);
     int32_t *tile_list = tile_cnt + 16;
     int32_t *chunk_cnt = tile_list + kTileClasses * ntiles;
+    hipLaunchKernelGGL(k_colpoints, dim3((unsigned)((N + kWG - 1) / kWG)), dim3(kWG), 0, s,
+                       reinterpret_cast<const double *>(base + L.qpS64), reinterpret_cast<const double *>(base + L.qp9S64),
+                       bbox, (int)N, reinterpret_cast<float *>(base + L.qpB16), reinterpret_cast<float *>(base + L.qpB9));
     hipLaunchKernelGGL(k_tile_count, dim3(nchunk), dim3(kWG), 0, s, bbox, (int)ntiles, chunk_cnt);
     hipLaunchKernelGGL(k_tile_emit, dim3(nchunk), dim3(kWG), 0, s, bbox, (int)ntiles, (const int32_t *)chunk_cnt,
                        tile_cnt, tile_list);
