@@ -267,7 +267,6 @@ __device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x,
   // recomputed where needed instead of being kept in registers
   const int lane = (int)__lane_id();
   const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  const int tid = 64 * w + lane;
   const int N = H.N;
   const int ld = (int)H.ld;
   // with NR right-hand sides, vector m and its partial sums sit at these
@@ -378,8 +377,13 @@ __device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x,
     const bool same = u + 1 < SE;
     if (more) load(same ? B : B + 1, same ? c + 1 : 0);
     __syncthreads();
-    if (tid < NR * CW) {
-      const int m = NR == 1 ? 0 : tid / CW, t = tid - m * CW;
+    // the NR CW column sums of the unit, shared out evenly over the sixteen
+    // wavefronts (a few lanes each), so that no wavefront lags behind the
+    // others at the next barrier
+    constexpr int kPer = NR * CW / 16;
+    if (lane < kPer) {
+      const int item = w * kPer + lane;
+      const int m = NR == 1 ? 0 : item / CW, t = item - m * CW;
       const int ct = kRB * B + CW * c + t;
       if (ct >= diag_end && ct < ld) {
         AT sum = AT(0);
