@@ -185,7 +185,10 @@ struct SolveLayout {
     x64 = take(sizeof(double) * ld);
     r64 = take(sizeof(double) * ld);
     vec = take((precision == BC_FP64 ? 8 : 4) * ld * 7);
-    rpart = take(sizeof(double) * kRB * (size_t)T);
+    // FP64 row sums; in mixed precision those of the residual product,
+    // whose units are 128 columns wide (k = 2: two FP32 columns per lane
+    // with the FP64 vector), more than the CG product's
+    rpart = take(sizeof(double) * kRB * (size_t)half_units_before(nB, ld / 64, 2));
     cpart = take(sizeof(double) * (size_t)ld * (size_t)nB);
     total = o;
   }

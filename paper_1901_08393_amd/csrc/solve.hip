@@ -541,13 +541,35 @@ __device__ __forceinline__ HalfPlan uniform_plan(const HP &H) {
   return U;
 }
 
-template <typename MT, typename XT, typename AT, bool DELTA, bool LDS2>
+template <typename MT, typename XT, typename AT, bool DELTA, bool LDS2, typename L = Load16<MT, XT>>
 __device__ __noinline__ double solver_product(gptr<const MT> V, gptr<const XT> x, HalfPlan H, gptr<AT> rpart,
                                               gptr<AT> cpart, lptr<AT> lbuf) {
   double delta = 0.0;
-  half_product<MT, XT, AT, DELTA, LDS2>(uniform_ptr(V), uniform_ptr(x), uniform_plan(H), uniform_ptr(rpart),
-                                        uniform_ptr(cpart), uniform_lptr(lbuf), delta);
+  half_product<MT, XT, AT, DELTA, LDS2, 1, L>(uniform_ptr(V), uniform_ptr(x), uniform_plan(H), uniform_ptr(rpart),
+                                              uniform_ptr(cpart), uniform_lptr(lbuf), delta);
   return delta;
+}
+
+// Residual products: the FP64 iterate with the stored matrix.  An FP32
+// matrix is read two columns per lane (units of 128 columns, k = 2), which
+// leaves the FP64 row and column sums their registers; with the CG
+// product's 16-byte loads they spilled and the product took twice as long.
+template <typename MT>
+struct ResidLoad {
+  using type = Load16<MT, double>;
+};
+template <>
+struct ResidLoad<float> {
+  using type = LoadF2D;
+};
+__device__ __forceinline__ HalfPlan resid_plan(const HalfPlan &H, bool mixed, int rank) {
+  if (!mixed) return H;
+  HalfPlan R = H;
+  R.k = 2;
+  R.T = half_units_before(H.nB, H.m64, 2);
+  R.u0 = R.T * rank / H.G;
+  R.u1 = R.T * (rank + 1) / H.G;
+  return R;
 }
 
 // ---------------------------------------------------------- CG iterations
@@ -766,9 +788,11 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       const bool zero_x = outer == 0 && !P.x0_given;
       if (!zero_x) {
         double unused = 0.0, dummy[1];
-        unused = solver_product<MT, double, double, false, false>(V, x64, H, rpD, cpD, (lptr<double>)s_buf);
+        const HalfPlan HR = resid_plan(H, MIXED, rank);
+        unused = solver_product<MT, double, double, false, false, typename ResidLoad<MT>::type>(V, x64, HR, rpD, cpD,
+                                                                                              (lptr<double>)s_buf);
         if (!sys_sync<1>(bar, none, dummy, l_red, l_flag)) { aborted = true; break; }
-        half_gather<double>(H, r0, r1, rpD, cpD, (lptr<double>)s_part, (lptr<double>)s_band);
+        half_gather<double>(HR, r0, r1, rpD, cpD, (lptr<double>)s_part, (lptr<double>)s_band);
       }
       double pr = 0.0, pb = 0.0, pxx = 0.0, pbx = 0.0;
       for (int i = r0 + t; i < r1; i += kSolveWG) {
