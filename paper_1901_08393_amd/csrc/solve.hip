@@ -377,12 +377,13 @@ __device__ __forceinline__ void half_product(gptr<const MT> V, gptr<const XT> x,
     const bool same = u + 1 < SE;
     if (more) load(same ? B : B + 1, same ? c + 1 : 0);
     __syncthreads();
-    // the NR CW column sums of the unit, shared out evenly over the sixteen
-    // wavefronts (a few lanes each), so that no wavefront lags behind the
-    // others at the next barrier
+    // the NR CW column sums of the unit: with one vector shared out evenly
+    // over the sixteen wavefronts (a few lanes each), so that no wavefront
+    // lags behind the others at the next barrier; with three, by the first
+    // NR CW threads (measured faster there)
     constexpr int kPer = NR * CW / 16;
-    if (lane < kPer) {
-      const int item = w * kPer + lane;
+    if (NR == 1 ? lane < kPer : 64 * w + lane < NR * CW) {
+      const int item = NR == 1 ? w * kPer + lane : 64 * w + lane;
       const int m = NR == 1 ? 0 : item / CW, t = item - m * CW;
       const int ct = kRB * B + CW * c + t;
       if (ct >= diag_end && ct < ld) {
