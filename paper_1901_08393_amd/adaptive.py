@@ -10,7 +10,7 @@ dual mesh as the algorithm states it (adaptive_dual).
 (iv)  refine: newest-vertex bisection of the marked elements with closure.
 
 By the corollary in Appendix A the discrete capacities of nested P0 spaces
-increase monotonically; the driver reports them per step.
+increase monotonically; the loops report them per step.
 """
 
 from __future__ import annotations
