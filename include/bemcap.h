@@ -205,7 +205,11 @@ typedef struct bc_solve_opts {
                          Section 2.7's Proposition), so the left side bounds
                          Cap's relative algebraic error to first order;
                          solving to a capacity tolerance needs no tighter
-                         residual than this.  Must be finite and < 1. */
+                         residual than this.  The first inner solve from a
+                         zero start, where no such target exists yet, stops
+                         once the same bound, estimated from its recurrence
+                         residual, is below 0.3 cap_rtol.  Must be finite
+                         and < 1. */
 } bc_solve_opts;
 
 /* Device-side result, written when a system finishes. */

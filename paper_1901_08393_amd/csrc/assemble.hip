@@ -408,7 +408,9 @@ __device__ __forceinline__ double ss_map(int kind, int reg, double xi, double e1
   return J;
 }
 
-template <bool MIXED>
+// NSS > 0: the singular rules' order as a compile-time constant (4, 8), so
+// that the point index splits into Gauss indices by shifts, not divisions.
+template <bool MIXED, int NSS>
 __device__ __forceinline__ void sparse_entry(int64_t e, const double *__restrict__ verts,
                                              const int4 *__restrict__ tri4, const double *__restrict__ area,
                                              const double4 *__restrict__ qpA, int Q, const SSRule &ss,
@@ -465,7 +467,7 @@ __device__ __forceinline__ void sparse_entry(int64_t e, const double *__restrict
     const double e1x = verts[3 * D1] - dx0, e1y = verts[3 * D1 + 1] - dy0, e1z = verts[3 * D1 + 2] - dz0;
     const double e2x = verts[3 * D2] - verts[3 * D1], e2y = verts[3 * D2 + 1] - verts[3 * D1 + 1],
                  e2z = verts[3 * D2 + 2] - verts[3 * D1 + 2];
-    const int n = ss.n, n2 = n * n, n4 = n2 * n2;
+    const int n = NSS > 0 ? NSS : ss.n, n2 = n * n, n4 = n2 * n2;
     const int nreg = kind == kCoincident ? 6 : (kind == kEdge ? 4 : 2);
     for (int p = lane; p < nreg * n4; p += 64) {
       const int reg = p / n4;
@@ -512,7 +514,7 @@ __device__ __forceinline__ void sparse_entry(int64_t e, const double *__restrict
 // One wavefront per pattern entry.  (Fewer wavefronts taking the entries
 // grid-stride were slower: an entry's chain of dependent loads is then
 // waited for one entry after another.)
-template <bool MIXED>
+template <bool MIXED, int NSS>
 __global__ __launch_bounds__(kWG) void k_sparse(const double *__restrict__ verts, const int4 *__restrict__ tri4,
                                                 const double *__restrict__ area, const double4 *__restrict__ qpA,
                                                 int Q, SSRule ss, const int32_t *__restrict__ prowptr,
@@ -520,7 +522,7 @@ __global__ __launch_bounds__(kWG) void k_sparse(const double *__restrict__ verts
                                                 const int32_t *__restrict__ pkind, double *__restrict__ pcorr,
                                                 int64_t nnz, int64_t ld, void *__restrict__ Vout) {
   const int64_t e = (int64_t)blockIdx.x * (kWG / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (e < nnz) sparse_entry<MIXED>(e, verts, tri4, area, qpA, Q, ss, prowptr, pcol, prow, pkind, pcorr, ld, Vout);
+  if (e < nnz) sparse_entry<MIXED, NSS>(e, verts, tri4, area, qpA, Q, ss, prowptr, pcol, prow, pkind, pcorr, ld, Vout);
 }
 
 template <typename T>
@@ -634,12 +636,10 @@ int launch_assemble(const void *mesh_ws, const int32_t *tris, const double *vert
     double *pcorr = mixed ? reinterpret_cast<double *>(pb + P.corr) : nullptr;
     const int grid = (int)((nnz + 3) / 4);
     const int Q = o.far_order * o.far_order;
-    if (!mixed)
-      hipLaunchKernelGGL(k_sparse<false>, dim3(grid), dim3(kWG), 0, s, verts, m.tri4, m.area, m.qpA64, Q, ss,
-                         prowptr, pcol, prow, pkind, pcorr, nnz, ld, V);
-    else
-      hipLaunchKernelGGL(k_sparse<true>, dim3(grid), dim3(kWG), 0, s, verts, m.tri4, m.area, m.qpA64, Q, ss, prowptr,
-                         pcol, prow, pkind, pcorr, nnz, ld, V);
+    auto kern = mixed ? (ss.n == 4 ? k_sparse<true, 4> : ss.n == 8 ? k_sparse<true, 8> : k_sparse<true, 0>)
+                      : (ss.n == 4 ? k_sparse<false, 4> : ss.n == 8 ? k_sparse<false, 8> : k_sparse<false, 0>);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWG), 0, s, verts, m.tri4, m.area, m.qpA64, Q, ss, prowptr, pcol, prow,
+                       pkind, pcorr, nnz, ld, V);
     if (hipGetLastError() != hipSuccess) return BC_EDEVICE;
   }
   if (ld > N) {

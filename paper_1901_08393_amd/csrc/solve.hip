@@ -13,7 +13,8 @@
 //          ||x|| ||r|| <= cap_rtol |b^T x| (for symmetric A,
 //          4pi (Cap* - Cap) = x*^T r, the algebraic form of the identity
 //          in the proof of Section 2.7's Proposition); else start an
-//          inner CG on A d = r / ||r||.
+//          inner CG on A d = r / ||r||.  The first inner CG from x = 0
+//          also stops on that bound, estimated from its own recurrence.
 //   CG     preconditioned CG in the Chronopoulos-Gear arrangement: the two
 //          inner products of an iteration are reduced together, so an
 //          iteration costs one product with V and two cross-workgroup
@@ -588,6 +589,7 @@ struct CGCtx {
   gptr<MT> vr, vu, vp, vs, vd, idg, rp, cp;
   gptr<BarSlot> slots;
   gptr<BarRel> rel;
+  gptr<const double> b;
   HalfPlan H;
   int r0, r1, G, rank;
   uint32_t spin_limit;
@@ -595,12 +597,19 @@ struct CGCtx {
 };
 struct CGState {
   double alpha, beta, gamma, eta, itol;
+  double capt;  // capacity stop of a first inner solve (CAP): 0.3 cap_rtol / ||b||
   int32_t iters, inner, budget;
   uint32_t epoch;
   int32_t exit;  // 0 budget used up, 1 inner solve done, 2 breakdown, 3 aborted
 };
 
-template <typename MT>
+// CAP: the first inner solve from x = 0 with a capacity tolerance, which the
+// outer residual cannot turn into a residual target (x = 0 gives no Cap).
+// Then x = ||b|| d and r = ||b|| r_inner, so the first-order bound
+// ||x|| ||r|| / |b^T x| is ||b|| ||d|| ||r_inner|| / |b^T d|, formed from
+// two more sums per iteration; the solve stops once it is below 0.3 cap_rtol
+// (the outer step checks it again with the true residual).
+template <typename MT, bool CAP>
 __device__ __noinline__ void cg_loop(lptr<CGCtx<MT>> Cp, lptr<CGState> Sp, lptr<MT> lbuf, lptr<MT> lpart,
                                      lptr<MT> band, lptr<double> lred, lptr<int> lflag) {
   using VT = MT;
@@ -622,6 +631,8 @@ __device__ __noinline__ void cg_loop(lptr<CGCtx<MT>> Cp, lptr<CGState> Sp, lptr<
   double alpha = uniform_f64(Sp->alpha), beta = uniform_f64(Sp->beta), gamma = uniform_f64(Sp->gamma);
   double eta = uniform_f64(Sp->eta);
   const double itol = uniform_f64(Sp->itol);
+  const double capt = CAP ? uniform_f64(Sp->capt) : 0.0;
+  const gptr<const double> b = CAP ? uniform_ptr(Cp->b) : nullptr;
   int iters = uniform32(Sp->iters), inner = uniform32(Sp->inner), budget = uniform32(Sp->budget);
   const int t = threadIdx.x;
   int ex = 0;
@@ -631,7 +642,7 @@ __device__ __noinline__ void cg_loop(lptr<CGCtx<MT>> Cp, lptr<CGState> Sp, lptr<
     // w = V u of the last product
     half_gather_body<VT>(H, r0, r1, rp, cp, lpart, band);
     const VT a = (VT)alpha, bt = (VT)beta;
-    double pru = 0.0, prr = 0.0;
+    double pru = 0.0, prr = 0.0, pdd = 0.0, pbd = 0.0;
     // the lane's first row, formed anew in every iteration: kept across the
     // product instead, the vectors' addresses would be spilled
     int i0 = r0 + t;
@@ -641,7 +652,12 @@ __device__ __noinline__ void cg_loop(lptr<CGCtx<MT>> Cp, lptr<CGState> Sp, lptr<
       const VT si = band[i - r0] + bt * vs[i];
       vp[i] = pi;
       vs[i] = si;
-      vd[i] = vd[i] + a * pi;
+      const VT di = vd[i] + a * pi;
+      vd[i] = di;
+      if (CAP) {
+        pdd += (double)di * (double)di;
+        pbd += b[i] * (double)di;
+      }
       const VT ri = vr[i] - a * si;
       vr[i] = ri;
       const VT ui = idg[i] * ri;
@@ -650,7 +666,15 @@ __device__ __noinline__ void cg_loop(lptr<CGCtx<MT>> Cp, lptr<CGState> Sp, lptr<
       prr += (double)ri * (double)ri;
     }
     double gnew, rr;
-    {
+    bool cap_met = false;
+    if (CAP) {
+      const double v[4] = {pru, prr, pdd, pbd};
+      double tot[4];
+      if (!sys_sync_body<4>(bar, v, tot, lred, lflag)) { ex = 3; break; }
+      gnew = tot[0];
+      rr = tot[1];
+      cap_met = sqrt(rr * tot[2]) <= capt * fabs(tot[3]);
+    } else {
       const double v[2] = {pru, prr};
       double tot[2];
       if (!sys_sync_body<2>(bar, v, tot, lred, lflag)) { ex = 3; break; }
@@ -658,7 +682,7 @@ __device__ __noinline__ void cg_loop(lptr<CGCtx<MT>> Cp, lptr<CGState> Sp, lptr<
       rr = tot[1];
     }
     inner += 1;
-    if (!(sqrt(rr) > itol) || iters >= max_iter) { ex = 1; break; }
+    if (!(sqrt(rr) > itol) || cap_met || iters >= max_iter) { ex = 1; break; }
     double pwu = 0.0;
     half_product<MT, VT, VT, true, true>(V, vu, H, rp, cp, lbuf, pwu);
     double delta;
@@ -758,6 +782,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
     s_cg.vr = vr; s_cg.vu = vu; s_cg.vp = vp; s_cg.vs = vs; s_cg.vd = vd; s_cg.idg = idg;
     s_cg.rp = rpV; s_cg.cp = cpV;
     s_cg.slots = bar.slots; s_cg.rel = bar.rel;
+    s_cg.b = b;
     s_cg.H = H;
     s_cg.r0 = r0; s_cg.r1 = r1; s_cg.G = G; s_cg.rank = rank;
     s_cg.spin_limit = P.spin_limit;
@@ -858,13 +883,22 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       continue;
     }
     if (phase == PH_CG) {
+      // the first inner solve from x = 0 also stops on the capacity bound,
+      // when that can come before the residual target (everything here is
+      // kept in the control block, so a resumed launch decides the same)
+      const bool cap_first = outer == 1 && !P.x0_given && P.cap_rtol > 0.0 && 0.3 * P.cap_rtol > itol;
       if (t == 0) {
         s_st.alpha = alpha; s_st.beta = beta; s_st.gamma = gamma; s_st.eta = eta; s_st.itol = itol;
+        s_st.capt = cap_first ? 0.3 * P.cap_rtol / rnorm : 0.0;
         s_st.iters = iters; s_st.inner = inner; s_st.budget = budget; s_st.epoch = bar.epoch;
       }
       __syncthreads();
-      cg_loop<MT>((lptr<CGCtx<MT>>)&s_cg, (lptr<CGState>)&s_st, (lptr<VT>)s_buf, (lptr<VT>)s_part, (lptr<VT>)s_band,
-                  l_red, l_flag);
+      if (cap_first)
+        cg_loop<MT, true>((lptr<CGCtx<MT>>)&s_cg, (lptr<CGState>)&s_st, (lptr<VT>)s_buf, (lptr<VT>)s_part,
+                          (lptr<VT>)s_band, l_red, l_flag);
+      else
+        cg_loop<MT, false>((lptr<CGCtx<MT>>)&s_cg, (lptr<CGState>)&s_st, (lptr<VT>)s_buf, (lptr<VT>)s_part,
+                           (lptr<VT>)s_band, l_red, l_flag);
       alpha = uniform_f64(s_st.alpha); beta = uniform_f64(s_st.beta); gamma = uniform_f64(s_st.gamma);
       eta = uniform_f64(s_st.eta);
       iters = uniform32(s_st.iters); inner = uniform32(s_st.inner); budget = uniform32(s_st.budget);

@@ -279,6 +279,9 @@ def test_capacity_tolerance_stop(api, name):
     assert r.ok, r
     assert 0.0 < r.cap_bound <= 1e-6, r
     assert r.iters < tight.iters, (r.iters, tight.iters)
+    # the first inner solve (from x = 0) stops on the bound estimated from
+    # its recurrence, so one FP64 residual after it confirms the stop
+    assert r.outer == 2, r
     sig = p.sigma.cpu().numpy()
     resid = b - Vref @ sig
     lhs = 4 * math.pi * (cap_ref - r.cap)
