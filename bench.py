@@ -176,9 +176,10 @@ def half_matrix_bytes(N: int, elem: int) -> int:
 
 def far_point_pairs(verts, tris, low: bool) -> float:
     """Point pairs the far-field kernels evaluate for one assembly: 256 per
-    unique pair, and 81 (the 3 x 3 rule) in tiles of 64-element blocks whose
-    vertex boxes are at least 12 largest element diameters apart when that
-    rule is on (mixed precision, bc_assembly_opts.far_low)."""
+    unique pair, and 49 (Radon's 7-point rule on both triangles) in tiles of
+    64-element blocks whose vertex boxes are at least 8 largest element
+    diameters apart when that rule is on (mixed precision,
+    bc_assembly_opts.far_low)."""
     N = len(tris)
     total = N * (N + 1) / 2 * POINT_PAIRS_PER_PAIR
     if not low:
@@ -191,10 +192,10 @@ def far_point_pairs(verts, tris, low: bool) -> float:
     bd2 = np.array([d2[64 * b: 64 * b + 64].max() for b in range(nb)])
     cnt = np.array([min(64, N - 64 * b) for b in range(nb)], dtype=np.float64)
     gap = np.maximum(0.0, np.maximum(lo[:, None, :] - hi[None, :, :], lo[None, :, :] - hi[:, None, :]))
-    far = (np.sum(gap ** 2, axis=2) >= 144.0 * np.maximum(bd2[:, None], bd2[None, :]))
+    far = (np.sum(gap ** 2, axis=2) >= 64.0 * np.maximum(bd2[:, None], bd2[None, :]))
     far &= np.triu(np.ones((nb, nb), dtype=bool), 1)
     low_pairs = float((cnt[:, None] * cnt[None, :])[far].sum())
-    return total - low_pairs * (POINT_PAIRS_PER_PAIR - 81)
+    return total - low_pairs * (POINT_PAIRS_PER_PAIR - 49)
 
 
 def pct(xs, q):

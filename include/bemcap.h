@@ -116,10 +116,11 @@ typedef struct bc_assembly_opts {
   int32_t precision;  /* bc_precision */
   int32_t far_low;    /* BC_MIXED with far_order 4: 1 integrates pairs of
                          64-element blocks whose bounding boxes are at least
-                         12 largest element diameters apart with the 3 x 3
-                         rule (81 instead of 256 point pairs).  There its
-                         relative error is at most 9e-10, below the FP32
-                         rounding of the stored entry (6e-8).  0: one far
+                         8 largest element diameters apart with Radon's
+                         7-point rule of degree 5 on each triangle (49
+                         instead of 256 point pairs).  There its relative
+                         error is at most 6e-10, below the FP32 rounding of
+                         the stored entry (6e-8).  0: one far
                          rule everywhere.  Ignored for far_order < 4; must
                          be 0 for BC_FP64.  The tile lists it uses are built
                          by bc_prepare, so bc_prepare must have run on the
@@ -142,9 +143,9 @@ typedef struct bc_pattern_info {
 } bc_pattern_info;
 
 /* Workspace for the mesh tables (geometry, quadrature points of the 4 x 4
- * and 3 x 3 rules, row pointers of the pattern, and the far-field tile lists:
+ * rule and the distant tiles' 7-point rule, row pointers of the pattern, and the far-field tile lists:
  * the 64 x 64 element tiles of the upper block triangle by class, near or
- * diagonal / separated / at least 12 element diameters apart).  Depends on
+ * diagonal / separated / at least 8 element diameters apart).  Depends on
  * N only. */
 size_t bc_mesh_workspace_bytes(int64_t N);
 
@@ -166,7 +167,7 @@ int32_t bc_prepare(const double *d_verts, int64_t M, const int32_t *d_tris,
 /* Dense Galerkin matrix (Appendix A, eq. "discreteform:residual"; kernel of
  * eq. "strongform").  Pairs sharing no vertex use the collapsed Gauss rule
  * (FP64 for BC_FP64, FP32 with FP64-formed centroid differences for
- * BC_MIXED, the 3 x 3 rule on distant tiles with opts->far_low); touching pairs use the Sauter-Schwab-type rules in FP64; in
+ * BC_MIXED, Radon's 7-point rule on distant tiles with opts->far_low); touching pairs use the Sauter-Schwab-type rules in FP64; in
  * BC_MIXED near pairs are recomputed in FP64 too and d_pattern receives the
  * FP64 correction V64 - (double)(float)V64 of every pattern entry.  Only
  * i <= j is integrated; V[j][i] = V[i][j] exactly.  d_V: N x ld, double

@@ -30,7 +30,7 @@ Parity pins are in tests/test_oracle_*.py.  Functions without an independent
 pin say "parity unpinned" in their docstring.
 """
 
-from .quadrature import gauss_legendre01, triangle_rule, ss_rule  # noqa: F401
+from .quadrature import gauss_legendre01, triangle_rule, ss_rule, radon7  # noqa: F401
 from .operator import (  # noqa: F401
     element_geometry,
     quad_points,

@@ -67,6 +67,27 @@ def triangle_rule(n: int):
     return s, t, wt
 
 
+def radon7():
+    """Radon's 7-point rule of degree 5 on the reference triangle
+    {s, t >= 0, s + t <= 1} (Stroud, Approximate Calculation of Multiple
+    Integrals, formula T2:5-1): the centroid with weight 9/40, and two orbits
+    of three points whose barycentric coordinates are (1 - 2b, b, b) in every
+    order, b = (6 - sqrt(15)) / 21 with weight (155 - sqrt(15)) / 1200 and
+    b = (6 + sqrt(15)) / 21 with weight (155 + sqrt(15)) / 1200; the weights
+    are then scaled by the reference area 1/2.  Returns (s, t, w) with s, t the second and third barycentric
+    coordinates.  Used by the mixed-precision far field on distant blocks (an
+    implementation choice of quadrature order by distance, not the paper's)."""
+    r = math.sqrt(15.0)
+    bary = [(1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0, 9.0 / 40.0)]
+    for sign in (-1.0, 1.0):
+        b = (6.0 + sign * r) / 21.0
+        a = 1.0 - 2.0 * b
+        wo = (155.0 + sign * r) / 1200.0
+        bary += [(a, b, b, wo), (b, a, b, wo), (b, b, a, wo)]
+    B = np.array(bary)
+    return B[:, 1].copy(), B[:, 2].copy(), 0.5 * B[:, 3]
+
+
 def _grid4(n: int):
     x, w = gauss_legendre01(n)
     idx = np.array(list(itertools.product(range(n), repeat=4)))

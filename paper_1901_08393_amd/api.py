@@ -98,7 +98,7 @@ class CapacityProblem:
         self.device = torch.device(device)
         if near_factor is None:
             near_factor = 1.5 if precision == "mixed" else 0.0
-        if far_low is None:  # the 3 x 3 rule for distant blocks: mixed precision with the 4 x 4 far rule
+        if far_low is None:  # Radon's 7-point rule for distant blocks: mixed precision with the 4 x 4 far rule
             far_low = precision == "mixed" and far_order == 4
         self.opts = _lib.bc_assembly_opts(far_order, ss_order, self.prec, int(bool(far_low)), float(near_factor))
         self.d_verts = torch.from_numpy(verts).to(self.device)

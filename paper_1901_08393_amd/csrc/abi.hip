@@ -10,6 +10,27 @@
 
 namespace bc {
 
+// Radon's 7-point rule of degree 5 on the reference triangle {s, t >= 0,
+// s + t <= 1} (Stroud's T2:5-1): the centroid, and two orbits of three points
+// with barycentric coordinates (1 - 2 b, b, b), b = (6 -+ sqrt 15) / 21, of
+// weights (155 -+ sqrt 15) / 1200 and 9/40 at the centroid, all times the
+// reference area 1/2.  A point is P0 + s (P1 - P0) + t (P2 - P0).
+void radon7(double *s, double *t, double *w) {
+  const double r = std::sqrt(15.0);
+  s[0] = t[0] = 1.0 / 3.0;
+  w[0] = 0.5 * 9.0 / 40.0;
+  for (int o = 0; o < 2; ++o) {
+    const double b = o == 0 ? (6.0 - r) / 21.0 : (6.0 + r) / 21.0, a = 1.0 - 2.0 * b;
+    const double wo = 0.5 * (o == 0 ? (155.0 - r) : (155.0 + r)) / 1200.0;
+    const double l1[3] = {b, a, b}, l2[3] = {b, b, a};
+    for (int k = 0; k < 3; ++k) {
+      s[1 + 3 * o + k] = l1[k];
+      t[1 + 3 * o + k] = l2[k];
+      w[1 + 3 * o + k] = wo;
+    }
+  }
+}
+
 // Gauss-Legendre nodes (ascending) and weights on [0, 1]: Newton's method
 // on the Legendre polynomial P_n, evaluated by its three-term recurrence,
 // started from cos(pi (k - 1/4) / (n + 1/2)).

@@ -13,7 +13,7 @@
 //   (lists built by bc_prepare): k_far32 takes the near and diagonal tiles,
 //   k_far32m the separated ones, where the squared distances of 16 x 16
 //   element pairs are one matrix-core product per point pair (the distant
-//   tiles, at least 12 element diameters apart, with the 3 x 3 rule).
+//   tiles, at least 8 element diameters apart, with Radon's 7-point rule).
 // k_sparse: one wavefront per pattern entry with j >= i: touching pairs with
 //   the Sauter-Schwab-type rules, near pairs (mixed precision) with the
 //   regular rule, both in FP64; overwrites the far-field value.  In mixed
@@ -274,7 +274,7 @@ struct FarWeights {
 // -r^2 for rows 4 (l / 16) .. + 3 and column l % 16, and only the inverse
 // square roots and the weighted sums remain on the vector ALU.  The sums,
 // weights, scale and bias correction are those of k_far32.  QP points per
-// element: the 4 x 4 rule (16) or the 3 x 3 rule of distant tiles (9); the
+// element: the 4 x 4 rule (16) or Radon's rule of distant tiles (kQLow); the
 // row points from the FP64 table qpA (QP per element), the column operands
 // from qpB (per point, relative to the column element's own block, which is
 // the column block; tabulated by bc_prepare).
@@ -285,7 +285,7 @@ __device__ __forceinline__ void far32m_tile(int I, int J, const double4 *__restr
                                             const float *__restrict__ qpB, const FarWeights &fw,
                                             const double *__restrict__ area, const double *__restrict__ bbox,
                                             double scale, int N, int64_t ld, float *__restrict__ V) {
-  static_assert(QP == 16 || QP == 9, "far rule of 16 or 9 points");
+  static_assert(QP == 16 || QP == kQLow, "far rule of 16 or kQLow points");
   const int lane = (int)__lane_id();
   const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int i0 = I * 64 + 16 * (w >> 2), j0 = J * 64 + 16 * (w & 3);
@@ -536,6 +536,8 @@ __global__ __launch_bounds__(kWG) void k_pad(T *V, int N, int64_t ld) {
 
 // (1/4pi) (sum_k w_k / sum_k fl32(w_k))^2 for the collapsed rule of order n
 static double far32_scale(int n);
+// the same for the weights w[0 .. n)
+static double far32_scale_w(const double *w, int n);
 
 // Compute units of the current device (256 on MI355X), for launches sized to
 // what fits on the chip at once.
@@ -556,28 +558,29 @@ static void far_launch(bool mixed, bool low_order, const MeshView &m, int N, int
   } else if (Q == 16) {
     // Each tile class on its own kernel, over the tile lists of bc_prepare:
     // near and diagonal tiles on the vector ALU, separated ones on the
-    // matrix cores (those at least kSepFarLow apart with the 3 x 3 rule when
+    // matrix cores (those at least kSepFarLow apart with Radon's rule when
     // low_order).  The matrix-core kernels run as many workgroups as fit on
     // the chip at once (two per CU) and take the tiles grid-stride.
     const int cus = device_cus();
     const int nt = (int)far_tiles(N);
     const int32_t *cnt = m.tile_cnt, *list = m.tile_list;
-    FarWeights w16{}, w9{};
+    FarWeights w16{}, wL{};
     double x[8], w[8];
     gauss_legendre01(4, x, w);
     for (int a = 0; a < 4; ++a)
       for (int b = 0; b < 4; ++b) w16.w[4 * a + b] = (float)(w[a] * w[b] * (1.0 - x[a]));
-    gauss_legendre01(3, x, w);
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) w9.w[3 * a + b] = (float)(w[a] * w[b] * (1.0 - x[a]));
+    double rs[kQLow], rt[kQLow], rw[kQLow];
+    radon7(rs, rt, rw);
+    for (int a = 0; a < kQLow; ++a) wL.w[a] = (float)rw[a];
     const int gv = std::min(nt, 4 * cus), gm = std::min(nt, 2 * cus);
     hipLaunchKernelGGL((k_far32<Q, true>), dim3(gv), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox, cnt,
                        list, scale, N, ld, static_cast<float *>(V));
     hipLaunchKernelGGL(k_far32m<16>, dim3(gm), dim3(1024), 0, s, m.qpA64, m.qpB16, w16, m.area, m.bbox, cnt + 1,
                        list + (size_t)nt, scale, N, ld, static_cast<float *>(V));
     if (low_order)
-      hipLaunchKernelGGL(k_far32m<9>, dim3(gm), dim3(1024), 0, s, m.qp9A64, m.qpB9, w9, m.area, m.bbox, cnt + 2,
-                         list + 2 * (size_t)nt, far32_scale(3), N, ld, static_cast<float *>(V));
+      hipLaunchKernelGGL(k_far32m<kQLow>, dim3(gm), dim3(1024), 0, s, m.qpLA64, m.qpBL, wL, m.area, m.bbox,
+                         cnt + 2, list + 2 * (size_t)nt, far32_scale_w(rw, kQLow), N, ld,
+                         static_cast<float *>(V));
     else
       hipLaunchKernelGGL(k_far32m<16>, dim3(gm), dim3(1024), 0, s, m.qpA64, m.qpB16, w16, m.area, m.bbox, cnt + 2,
                          list + 2 * (size_t)nt, scale, N, ld, static_cast<float *>(V));
@@ -598,6 +601,15 @@ static double far32_scale(int n) {
       sw += wk;
       sf += (double)(float)wk;
     }
+  return kInv4Pi * (sw / sf) * (sw / sf);
+}
+
+static double far32_scale_w(const double *w, int n) {
+  double sw = 0.0, sf = 0.0;
+  for (int k = 0; k < n; ++k) {
+    sw += w[k];
+    sf += (double)(float)w[k];
+  }
   return kInv4Pi * (sw / sf) * (sw / sf);
 }
 

@@ -14,6 +14,7 @@ namespace bc {
 constexpr int kWG = 256;            // threads per workgroup (4 wave64)
 constexpr int kQMax = 16;           // far-field points per triangle (order <= 4)
 constexpr int kTileClasses = 3;     // far-field tiles: 0 near or diagonal, 1 separated, 2 distant
+constexpr int kQLow = 7;            // points per triangle of the distant tiles' rule (mixed precision)
 constexpr int kSSMax = 8;           // Gauss points per coordinate, singular rules
 constexpr int kGMax = 256;          // workgroups per system in the solver
 constexpr int kSolveWG = 1024;      // threads per solver workgroup (16 wave64)
@@ -31,7 +32,7 @@ __host__ __device__ inline int64_t far_tiles(int64_t N) {
 }
 
 struct MeshLayout {
-  size_t tri4, cen4, area, qpA64, qpS64, qpA32, qpS32, qp9A64, qp9S64, qpB16, qpB9, rowcnt, rowptr, kindcnt, info,
+  size_t tri4, cen4, area, qpA64, qpS64, qpA32, qpS32, qpLA64, qpLS64, qpB16, qpBL, rowcnt, rowptr, kindcnt, info,
       blockbox, tiles, total;
   explicit MeshLayout(int64_t N) {
     size_t o = 0;
@@ -43,14 +44,14 @@ struct MeshLayout {
     qpS64 = take(sizeof(double) * 4 * kQMax * N);
     qpA32 = take(sizeof(float) * 4 * kQMax * N);
     qpS32 = take(sizeof(float) * 4 * kQMax * N);
-    qp9A64 = take(sizeof(double) * 4 * 9 * N);  // the 3 x 3 rule, same layouts as qpA64 / qpS64
-    qp9S64 = take(sizeof(double) * 4 * 9 * N);
+    qpLA64 = take(sizeof(double) * 4 * kQLow * N);  // the distant tiles' rule, same layouts as qpA64 / qpS64
+    qpLS64 = take(sizeof(double) * 4 * kQLow * N);
     // column operands of the matrix-core far field, per point [(b*4+c)][N]:
     // the point relative to the centre of its own 64-element block's box,
     // rounded once to FP32 (c = 0..2), and the squared norm of that FP64
-    // offset rounded once (c = 3); for the 4 x 4 and the 3 x 3 rule
+    // offset rounded once (c = 3); for the 4 x 4 and the distant tiles' rule
     qpB16 = take(sizeof(float) * 4 * kQMax * N);
-    qpB9 = take(sizeof(float) * 4 * 9 * N);
+    qpBL = take(sizeof(float) * 4 * kQLow * N);
     rowcnt = take(sizeof(int32_t) * N);
     rowptr = take(sizeof(int32_t) * (N + 1));
     kindcnt = take(sizeof(int32_t) * 4 * N);
@@ -75,10 +76,10 @@ struct MeshView {
   const float *qpS32;    // [(b*4+c)][N]
   const int32_t *rowptr; // N + 1
   const double *bbox;    // per 64 elements: min xyz, max xyz, max diam^2, 0
-  const double4 *qp9A64; // [N][9], the 3 x 3 rule
-  const double *qp9S64;  // [(b*4+c)][N]
+  const double4 *qpLA64; // [N][kQLow], the distant tiles' rule
+  const double *qpLS64;  // [(b*4+c)][N]
   const float *qpB16;    // [(b*4+c)][N], see MeshLayout
-  const float *qpB9;
+  const float *qpBL;
   const int32_t *tile_cnt;   // kTileClasses counts
   const int32_t *tile_list;  // [kTileClasses][far_tiles(N)]
 };
@@ -96,10 +97,10 @@ inline MeshView mesh_view(const void *ws, int64_t N) {
   v.qpS32 = reinterpret_cast<const float *>(b + L.qpS32);
   v.rowptr = reinterpret_cast<const int32_t *>(b + L.rowptr);
   v.bbox = reinterpret_cast<const double *>(b + L.blockbox);
-  v.qp9A64 = reinterpret_cast<const double4 *>(b + L.qp9A64);
-  v.qp9S64 = reinterpret_cast<const double *>(b + L.qp9S64);
+  v.qpLA64 = reinterpret_cast<const double4 *>(b + L.qpLA64);
+  v.qpLS64 = reinterpret_cast<const double *>(b + L.qpLS64);
   v.qpB16 = reinterpret_cast<const float *>(b + L.qpB16);
-  v.qpB9 = reinterpret_cast<const float *>(b + L.qpB9);
+  v.qpBL = reinterpret_cast<const float *>(b + L.qpBL);
   v.tile_cnt = reinterpret_cast<const int32_t *>(b + L.tiles);
   v.tile_list = v.tile_cnt + 16;
   return v;
@@ -328,13 +329,13 @@ __device__ __forceinline__ bool far_separated(const double *bbox, int I, int J) 
   return box_dist2(bi, bj) >= kSepFar * kSepFar * fmax(bi[6], bj[6]);
 }
 
-// Tiles at least kSepFarLow largest element diameters apart may take the
-// 3 x 3 collapsed rule in mixed precision (81 point pairs instead of 256).
-// For triangle pairs at centroid distance d >= 12 diameters its relative
-// error against a high-order rule is at most 9e-10 (mean 2e-10) over random
-// shapes and orientations, and falls as d^-6; the FP32 rounding of the
-// stored entry is 6e-8.
-constexpr double kSepFarLow = 12.0;
+// Tiles at least kSepFarLow largest element diameters apart may take, in
+// mixed precision, Radon's 7-point rule of degree 5 on each triangle (49
+// point pairs instead of 256).  For triangle pairs at centroid distance
+// d >= 8 diameters its relative error against a high-order rule is at most
+// 6e-10 (mean 1e-10) over random shapes and orientations, falling as d^-6;
+// the FP32 rounding of the stored entry is 6e-8.
+constexpr double kSepFarLow = 8.0;
 
 __device__ __forceinline__ bool far_low_order(const double *bbox, int I, int J) {
   const double *bi = bbox + 8 * I, *bj = bbox + 8 * J;
@@ -421,4 +422,5 @@ int launch_dual_zz(const void *ws, const int32_t *tris, int64_t N, int64_t M, in
 int solve_workgroups(int64_t N);
 int launch_set_desc(const SysDesc *h, int n, SysDesc *d, hipStream_t s);
 void gauss_legendre01(int n, double *x, double *w);
+void radon7(double *s, double *t, double *w);
 }  // namespace bc

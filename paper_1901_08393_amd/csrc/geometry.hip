@@ -26,9 +26,9 @@ struct FarRule {
 
 __global__ __launch_bounds__(kWG) void k_geometry(const double *__restrict__ verts, int64_t M,
                                                   const int32_t *__restrict__ tris, int N, FarRule rule,
-                                                  FarRule rule9, int4 *tri4, double4 *cen4, double *area,
+                                                  FarRule ruleL, int4 *tri4, double4 *cen4, double *area,
                                                   double4 *qpA64, double *qpS64, float4 *qpA32, float *qpS32,
-                                                  double4 *qp9A64, double *qp9S64) {
+                                                  double4 *qpLA64, double *qpLS64) {
 #pragma clang fp contract(off)
   int e = blockIdx.x * kWG + threadIdx.x;
   if (e >= N) return;
@@ -76,17 +76,17 @@ __global__ __launch_bounds__(kWG) void k_geometry(const double *__restrict__ ver
     qpS32[(size_t)(k * 4 + 2) * N + e] = rz;
     qpS32[(size_t)(k * 4 + 3) * N + e] = rw;
   }
-  // the 3 x 3 rule of the distant tiles in mixed precision
-  for (int k = 0; k < 9; ++k) {
-    const double x = p0x + rule9.s[k] * ux + rule9.t[k] * vx;
-    const double y = p0y + rule9.s[k] * uy + rule9.t[k] * vy;
-    const double z = p0z + rule9.s[k] * uz + rule9.t[k] * vz;
-    const double W = 2.0 * A * rule9.w[k];
-    qp9A64[(size_t)e * 9 + k] = make_double4(x, y, z, W);
-    qp9S64[(size_t)(k * 4 + 0) * N + e] = x;
-    qp9S64[(size_t)(k * 4 + 1) * N + e] = y;
-    qp9S64[(size_t)(k * 4 + 2) * N + e] = z;
-    qp9S64[(size_t)(k * 4 + 3) * N + e] = W;
+  // the rule of the distant tiles in mixed precision
+  for (int k = 0; k < kQLow; ++k) {
+    const double x = p0x + ruleL.s[k] * ux + ruleL.t[k] * vx;
+    const double y = p0y + ruleL.s[k] * uy + ruleL.t[k] * vy;
+    const double z = p0z + ruleL.s[k] * uz + ruleL.t[k] * vz;
+    const double W = 2.0 * A * ruleL.w[k];
+    qpLA64[(size_t)e * kQLow + k] = make_double4(x, y, z, W);
+    qpLS64[(size_t)(k * 4 + 0) * N + e] = x;
+    qpLS64[(size_t)(k * 4 + 1) * N + e] = y;
+    qpLS64[(size_t)(k * 4 + 2) * N + e] = z;
+    qpLS64[(size_t)(k * 4 + 3) * N + e] = W;
   }
 }
 
@@ -142,14 +142,14 @@ __global__ __launch_bounds__(64) void k_blockbox(const double *__restrict__ vert
 }
 
 
-// Column operands of the matrix-core far field (MeshLayout::qpB16, qpB9):
-// each point of the 4 x 4 and 3 x 3 rules relative to the centre of its own
+// Column operands of the matrix-core far field (MeshLayout::qpB16, qpBL):
+// each point of the 4 x 4 and the distant tiles' rules relative to the centre of its own
 // element block's box (FP64, rounded once) and the squared norm of that
 // offset.  The kernel takes the frame of the column block, which is the
 // column element's own block, so these are per element.
-__global__ __launch_bounds__(kWG) void k_colpoints(const double *__restrict__ qpS64, const double *__restrict__ qp9S64,
+__global__ __launch_bounds__(kWG) void k_colpoints(const double *__restrict__ qpS64, const double *__restrict__ qpLS64,
                                                    const double *__restrict__ bbox, int N, float *__restrict__ qpB16,
-                                                   float *__restrict__ qpB9) {
+                                                   float *__restrict__ qpBL) {
   const int e = blockIdx.x * kWG + threadIdx.x;
   if (e >= N) return;
   const double *bx = bbox + 8 * (e / 64);
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(kWG) void k_colpoints(const double *__restrict__ qp
     }
   };
   put(qpS64, qpB16, kQMax);
-  put(qp9S64, qpB9, 9);
+  put(qpLS64, qpBL, kQLow);
 }
 
 // Far-field tile lists: the tiles of the upper block triangle of each class
@@ -412,24 +412,18 @@ int launch_geometry(const double *verts, int64_t M, const int32_t *tris, int64_t
       r.t[k] = x[b] * (1.0 - x[a]);
       r.w[k] = w[a] * w[b] * (1.0 - x[a]);
     }
-  FarRule r9{};
-  gauss_legendre01(3, x, w);
-  r9.Q = 9;
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) {
-      r9.s[3 * a + b] = x[a];
-      r9.t[3 * a + b] = x[b] * (1.0 - x[a]);
-      r9.w[3 * a + b] = w[a] * w[b] * (1.0 - x[a]);
-    }
+  FarRule rL{};
+  rL.Q = kQLow;
+  radon7(rL.s, rL.t, rL.w);
   MeshLayout L(N);
   char *base = static_cast<char *>(mesh_ws);
   int grid = (int)((N + kWG - 1) / kWG);
-  hipLaunchKernelGGL(k_geometry, dim3(grid), dim3(kWG), 0, s, verts, M, tris, (int)N, r, r9,
+  hipLaunchKernelGGL(k_geometry, dim3(grid), dim3(kWG), 0, s, verts, M, tris, (int)N, r, rL,
                      reinterpret_cast<int4 *>(base + L.tri4), reinterpret_cast<double4 *>(base + L.cen4),
                      reinterpret_cast<double *>(base + L.area), reinterpret_cast<double4 *>(base + L.qpA64),
                      reinterpret_cast<double *>(base + L.qpS64), reinterpret_cast<float4 *>(base + L.qpA32),
-                     reinterpret_cast<float *>(base + L.qpS32), reinterpret_cast<double4 *>(base + L.qp9A64),
-                     reinterpret_cast<double *>(base + L.qp9S64));
+                     reinterpret_cast<float *>(base + L.qpS32), reinterpret_cast<double4 *>(base + L.qpLA64),
+                     reinterpret_cast<double *>(base + L.qpLS64));
   return hipGetLastError() == hipSuccess ? BC_OK : BC_EDEVICE;
 }
 
@@ -455,8 +449,8 @@ int launch_pattern(const double *verts, const int32_t *tris, int64_t N, double n
     int32_t *tile_list = tile_cnt + 16;
     int32_t *chunk_cnt = tile_list + kTileClasses * ntiles;
     hipLaunchKernelGGL(k_colpoints, dim3((unsigned)((N + kWG - 1) / kWG)), dim3(kWG), 0, s,
-                       reinterpret_cast<const double *>(base + L.qpS64), reinterpret_cast<const double *>(base + L.qp9S64),
-                       bbox, (int)N, reinterpret_cast<float *>(base + L.qpB16), reinterpret_cast<float *>(base + L.qpB9));
+                       reinterpret_cast<const double *>(base + L.qpS64), reinterpret_cast<const double *>(base + L.qpLS64),
+                       bbox, (int)N, reinterpret_cast<float *>(base + L.qpB16), reinterpret_cast<float *>(base + L.qpBL));
     hipLaunchKernelGGL(k_tile_count, dim3(nchunk), dim3(kWG), 0, s, bbox, (int)ntiles, chunk_cnt);
     hipLaunchKernelGGL(k_tile_emit, dim3(nchunk), dim3(kWG), 0, s, bbox, (int)ntiles, (const int32_t *)chunk_cnt,
                        tile_cnt, tile_list);

@@ -171,37 +171,50 @@ def test_V_mixed_entrywise(api, name):
 
 def _two_spheres(D=6.5):
     """Two level-2 icospheres of radius 1, centres D apart: every block pair
-    across the gap is at least 12 largest element diameters apart (box
-    distance D - 2 = 4.5 against 12 x 0.325)."""
+    across the gap is at least 8 largest element diameters apart (box
+    distance D - 2 = 4.5 against 8 x 0.325), no pair within a sphere is
+    (at most 2 apart)."""
     m = synth.icosphere(2, 1.0)
     verts = np.vstack([m.verts, m.verts + np.array([D, 0.0, 0.0])])
     tris = np.vstack([m.tris, m.tris + m.verts.shape[0]]).astype(np.int32)
     return verts, tris
 
 
+def _radon_cross(verts, tris, half):
+    """The oracle's entries (i < half <= j) with Radon's 7-point rule on both
+    triangles: (1/4pi) sum_a sum_b W_a W_b / |x_a - y_b|."""
+    s7, t7, w7 = oracle.radon7()
+    P = np.asarray(verts, dtype=np.float64)[np.asarray(tris)]
+    X = (P[:, 0, None, :] + s7[None, :, None] * (P[:, 1] - P[:, 0])[:, None, :]
+         + t7[None, :, None] * (P[:, 2] - P[:, 0])[:, None, :])
+    W = 2.0 * oracle.element_geometry(verts, tris)["area"][:, None] * w7[None, :]
+    r = np.linalg.norm(X[:half, None, :, None, :] - X[None, half:, None, :, :], axis=-1)
+    return np.einsum("ia,jb,ijab->ij", W[:half], W[half:], 1.0 / r) / (4.0 * math.pi)
+
+
 def test_far_low_order_rule(api):
-    """Mixed precision integrates distant block pairs with the 3 x 3 rule:
-    those entries match the oracle's 3 x 3 entries to FP32 rounding, differ
-    from its 4 x 4 entries by no more than that, carry no bias into the
-    capacity, and the capacity meets the 1e-8 bar."""
+    """Mixed precision integrates distant block pairs with Radon's 7-point
+    rule: those entries match the oracle's entries with that rule to FP32
+    rounding, differ from its 4 x 4 entries by no more than that, carry no
+    bias into the capacity, and the capacity meets the 1e-8 bar."""
     _flush("far low-order rule (two spheres)")
     verts, tris = _two_spheres()
     N = tris.shape[0]
     half = N // 2
     ref4 = oracle.assemble(verts, tris, 4, 4)
-    ref3 = oracle.assemble(verts, tris, 3, 4)
     p = api.CapacityProblem(verts, tris, "mixed")
     assert p.opts.far_low == 1
     V32 = p.assemble()
     torch.cuda.synchronize()
     V32 = V32.cpu().numpy()[:, :N].astype(np.float64)
     cross = np.s_[:half, half:]
-    r3 = (V32[cross] - ref3[cross]) / ref3[cross]
+    ref7 = _radon_cross(verts, tris, half)
+    r7 = (V32[cross] - ref7) / ref7
     r4 = (V32[cross] - ref4[cross]) / ref4[cross]
-    _flush(f"  vs 3x3: max {np.abs(r3).max():.2e} mean {r3.mean():.2e}; "
+    _flush(f"  vs Radon 7: max {np.abs(r7).max():.2e} mean {r7.mean():.2e}; "
            f"vs 4x4: max {np.abs(r4).max():.2e} mean {r4.mean():.2e}")
     # FP32 evaluation errors as for the other far entries, and no bias
-    for r in (r3, r4):
+    for r in (r7, r4):
         assert np.abs(r).max() <= 4e-6 and abs(r.mean()) <= 2e-9
     assert np.array_equal(V32, V32.T)
     # the same mesh with one far rule everywhere: only the distant entries change

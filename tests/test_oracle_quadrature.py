@@ -209,6 +209,50 @@ def semi_analytic(Ti, Tj, n=120):
     return np.sum(2 * _area(A, B, C) * w * triangle_potential(*Tj, xs))
 
 
+def test_radon7_degree_five():
+    """Radon's rule integrates every monomial s^i t^j of total degree <= 5
+    exactly over the reference triangle (i! j! / (i + j + 2)!), has positive
+    weights and interior points, and is not exact at degree 6."""
+    s, t, w = oracle.radon7()
+    assert s.shape == t.shape == w.shape == (7,)
+    assert np.all(w > 0) and np.all(s > 0) and np.all(t > 0) and np.all(s + t < 1)
+    for i in range(6):
+        for j in range(6 - i):
+            exact = math.factorial(i) * math.factorial(j) / math.factorial(i + j + 2)
+            assert abs(np.sum(w * s**i * t**j) - exact) <= 1e-15, (i, j)
+    worst = max(abs(np.sum(w * s**i * t**(6 - i)) - math.factorial(i) * math.factorial(6 - i) / math.factorial(8))
+                for i in range(7))
+    assert worst > 1e-6
+
+
+def test_radon7_far_pair_accuracy():
+    """On triangle pairs at least 8 diameters apart the 7 x 7 product of
+    Radon's rule matches a 12 x 12 collapsed Gauss reference to 1e-9."""
+    rng = np.random.default_rng(3)
+    s7, t7, w7 = oracle.radon7()
+    s12, t12, w12 = oracle.triangle_rule(12)
+
+    def pts(T, s, t, w):
+        return T[0] + s[:, None] * (T[1] - T[0]) + t[:, None] * (T[2] - T[0]), 2 * w
+
+    def pair(Ta, Tb, rule):
+        Xa, Wa = pts(Ta, *rule)
+        Xb, Wb = pts(Tb, *rule)
+        r = np.linalg.norm(Xa[:, None, :] - Xb[None, :, :], axis=2)
+        return np.sum(Wa[:, None] * Wb[None, :] / r)
+
+    worst = 0.0
+    for _ in range(200):
+        Ta, Tb = rng.normal(size=(3, 3)), rng.normal(size=(3, 3))
+        d = max(np.linalg.norm(T[i] - T[k]) for T in (Ta, Tb) for i in range(3) for k in range(i))
+        Ta, Tb = Ta / d, Tb / d
+        u = rng.normal(size=3)
+        Tb = Tb - Tb.mean(0) + Ta.mean(0) + 8.0 * u / np.linalg.norm(u)
+        ref = pair(Ta, Tb, (s12, t12, w12))
+        worst = max(worst, abs(pair(Ta, Tb, (s7, t7, w7)) / ref - 1))
+    assert worst <= 1e-9, worst
+
+
 def test_triangle_potential_far_point():
     A, B, D = P(0, 0, 0), P(1, 0, 0), P(0.5, 0, 0.7)
     x = P(0.2, 0.3, 1.5)[None]
