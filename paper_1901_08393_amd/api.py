@@ -135,6 +135,15 @@ class CapacityProblem:
     def matrix_bytes(self) -> int:
         return int(lib().bc_matrix_bytes(self.N, self.prec))
 
+    def allocate(self):
+        """Device memory of the matrix and of the solver, allocated once;
+        assemble() and solve() allocate whatever is missing themselves.
+        Calling this first keeps allocation (which may release cached blocks
+        and wait for the device) out of a timed assemble or solve."""
+        if self.V is None:
+            self.V = torch.empty((self.N, self.ld), dtype=self.matrix_dtype, device=self.device)
+        self._ensure_solve_ws()
+
     def assemble(self, stream=None) -> torch.Tensor:
         if self.V is None:
             self.V = torch.empty((self.N, self.ld), dtype=self.matrix_dtype, device=self.device)
