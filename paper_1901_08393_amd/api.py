@@ -303,6 +303,13 @@ class DualProblem:
                                                self.restart, _stream(stream)))
         self.x = torch.zeros(self.M, dtype=torch.float64, device=self.device)
 
+    def allocate(self):
+        """Device memory of V_bary, allocated once (assemble() allocates it
+        itself when missing); keeps allocation out of a timed assembly."""
+        b = self.bary
+        if b.V is None:
+            b.V = torch.empty((b.N, b.ld), dtype=b.matrix_dtype, device=b.device)
+
     def assemble(self, stream=None) -> torch.Tensor:
         """V_bary (6N x 6N, FP64)."""
         return self.bary.assemble(stream)
