@@ -19,12 +19,20 @@ def rhs(verts, tris):
     return element_geometry(verts, tris)["area"].copy()
 
 
-def solve_direct(V, b):
+def solve_direct(V, b, overwrite: bool = False):
     """x = V^{-1} b by a dense Cholesky factorisation (the paper notes the
     system can be solved by a dense direct method for smaller sizes,
     Section 2.5).  A failed factorisation means V is not SPD, which
-    contradicts eq. "laplace_system", and raises."""
-    c = scipy.linalg.cho_factor(V, lower=False, check_finite=True)
+    contradicts eq. "laplace_system", and raises.  overwrite=True factors V
+    in place (its transpose, the same symmetric matrix in column-major
+    order, so LAPACK needs no copy): for matrices of tens of GB; V is
+    destroyed."""
+    if overwrite:
+        c = scipy.linalg.cho_factor(V.T, lower=False, overwrite_a=True, check_finite=False)
+        if not np.all(np.isfinite(np.diag(c[0]))):
+            raise np.linalg.LinAlgError("non-finite Cholesky factor")
+    else:
+        c = scipy.linalg.cho_factor(V, lower=False, check_finite=True)
     return scipy.linalg.cho_solve(c, b)
 
 

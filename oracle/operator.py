@@ -178,15 +178,28 @@ def _classify_one(tris, i, j):
 
 
 def _rows_worker(args):
+    """Rows i >= j part of V for the rows of one block: V[i, i:] with the
+    regular rule (the coincident entry, where r = 0, is replaced later by the
+    singular rule).  Columns are taken in chunks and the three coordinates as
+    separate arrays only to bound the temporaries (a row of N = 60000 would
+    otherwise hold 0.4 GB); every entry is the same sum
+    (1 / 4 pi) sum_a sum_b W_a W_b / |x_a - y_b| over the 16 x 16 points."""
     verts, tris, rows, far_order = args
     X, W = quad_points(verts, tris, far_order)
+    Xc = [np.ascontiguousarray(X[:, :, k]) for k in range(3)]
+    N = X.shape[0]
+    chunk = 512
     out = []
     for i in rows:
-        d = X[i][None, :, None, :] - X[i:][:, None, :, :]
-        r = np.sqrt(np.sum(d * d, axis=-1))
-        # the coincident entry (r = 0) is replaced by the singular rule
-        with np.errstate(divide="ignore", invalid="ignore"):
-            vals = np.sum((W[i][None, :, None] * W[i:][:, None, :]) / r, axis=(1, 2)) / FOUR_PI
+        vals = np.empty(N - i)
+        for c0 in range(i, N, chunk):
+            c1 = min(N, c0 + chunk)
+            dx = Xc[0][i][None, :, None] - Xc[0][c0:c1][:, None, :]
+            dy = Xc[1][i][None, :, None] - Xc[1][c0:c1][:, None, :]
+            dz = Xc[2][i][None, :, None] - Xc[2][c0:c1][:, None, :]
+            r = np.sqrt(dx * dx + dy * dy + dz * dz)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                vals[c0 - i:c1 - i] = np.sum((W[i][None, :, None] * W[c0:c1][:, None, :]) / r, axis=(1, 2)) / FOUR_PI
         out.append((i, vals))
     return out
 
@@ -210,6 +223,20 @@ def assemble_rows(verts, tris, rows, far_order: int = 4, ss_order: int = 4):
             for (_, _, kind, Ti, Tj) in _classify_one(tris, a, b):
                 out[k, j] = singular_entry(verts, kind, Ti, Tj, ss_order)
     return out
+
+
+def mirror_upper(V, block: int = 2048):
+    """V[j, i] = V[i, j] for i < j, in square blocks (no index arrays of
+    N^2 / 2 entries, so that N = 60000 fits next to the 28.8 GB matrix)."""
+    N = V.shape[0]
+    for r0 in range(0, N, block):
+        r1 = min(N, r0 + block)
+        D = V[r0:r1, r0:r1]
+        iu = np.triu_indices(r1 - r0, 1)
+        D[(iu[1], iu[0])] = D[iu]
+        for c0 in range(r1, N, block):
+            c1 = min(N, c0 + block)
+            V[c0:c1, r0:r1] = V[r0:r1, c0:c1].T
 
 
 def assemble(verts, tris, far_order: int = 4, ss_order: int = 4, workers: int | None = None):
@@ -236,6 +263,5 @@ def assemble(verts, tris, far_order: int = 4, ss_order: int = 4, workers: int | 
             V[i, i:] = vals
     for (i, j, kind, Ti, Tj) in classify_pairs(tris):
         V[i, j] = singular_entry(verts, kind, Ti, Tj, ss_order)
-    iu = np.triu_indices(N, 1)
-    V[(iu[1], iu[0])] = V[iu]
+    mirror_upper(V)
     return V
