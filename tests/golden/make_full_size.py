@@ -1,0 +1,106 @@
+"""Writes tests/golden/full_size.json: FP64 oracle results of the full-size
+workloads, for the GPU tests that check the benchmark configurations.
+
+Calls only ``oracle`` (the CPU FP64 reference) and ``synth`` (the seeded mesh
+generators); nothing here touches the GPU library.  Run on the CPU:
+
+    python tests/golden/make_full_size.py [--only sphere_L5|voxel_60k]
+
+Workloads (each recorded with a SHA-256 of its mesh arrays, so that a test
+can tell whether ``synth`` still builds the same mesh):
+
+* ``sphere_L5``: the sphere of radius r ~ U[0.5, 2] (numpy default_rng(2)) as
+  a level-5 icosphere, N = 20480 (the headline workload);
+* ``voxel_60k``: the voxel union of 26 unit voxels in a 4^3 lattice
+  (seed 4), NVB-refined uniformly and then by bisection of the largest
+  elements until N >= 60000 (``synth.refine_to_size``), N = 60000.
+
+For each: the capacity of the FP64 Galerkin solution (eq. "cap:ell"; 4 x 4
+regular rule, order-4 singular rules, dense Cholesky), the sum of all
+entries 1^T V 1, and the row sums (V 1)_i at 64 seeded rows.  The voxel case
+holds a 28.8 GB matrix and takes about half an hour on 8 cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "full_size.json")
+
+
+def mesh_sha(verts, tris) -> str:
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(verts, dtype=np.float64).tobytes())
+    h.update(np.ascontiguousarray(tris, dtype=np.int32).tobytes())
+    return h.hexdigest()[:16]
+
+
+def sphere_L5():
+    r = float(np.random.default_rng(2).uniform(0.5, 2.0))
+    m = synth.icosphere(5, r)
+    return m.verts, m.tris, {"recipe": "icosphere(5, r), r = default_rng(2).uniform(0.5, 2)", "r": r}
+
+
+def voxel_60k():
+    m = synth.voxel_union(4, 0.4, 4)
+    t0 = synth.init_reference_edges(m.verts, m.tris)
+    v, t = synth.refine_to_size(m.verts, t0, 60000)
+    return v, t, {"recipe": "refine_to_size(voxel_union(4, 0.4, 4) with longest-edge references, 60000)",
+                  "voxels": int(m.meta["voxels"])}
+
+
+WORKLOADS = {"sphere_L5": sphere_L5, "voxel_60k": voxel_60k}
+
+
+def run(name: str) -> dict:
+    verts, tris, meta = WORKLOADS[name]()
+    N = len(tris)
+    t0 = time.perf_counter()
+    V = oracle.assemble(verts, tris, 4, 4)
+    t_asm = time.perf_counter() - t0
+    rows = np.sort(np.random.default_rng(7).choice(N, size=64, replace=False))
+    rowsum = [math.fsum(V[i].tolist()) for i in rows.tolist()]
+    total = float(np.sum(V))  # pairwise summation
+    b = oracle.rhs(verts, tris)
+    t0 = time.perf_counter()
+    x = oracle.solve_direct(V, b, overwrite=True)
+    t_chol = time.perf_counter() - t0
+    del V
+    cap = oracle.capacity(x, b)
+    print(f"{name}: N={N} cap={cap!r} assemble {t_asm:.0f} s cholesky {t_chol:.0f} s", flush=True)
+    return dict(meta, N=N, mesh_sha=mesh_sha(verts, tris), far_order=4, ss_order=4, cap=cap, one_V_one=total,
+                rows=rows.tolist(), rowsum=rowsum, x_rows=[float(x[i]) for i in rows.tolist()],
+                oracle_seconds={"assemble": round(t_asm, 1), "cholesky": round(t_chol, 1)},
+                cores=os.cpu_count())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--only", choices=sorted(WORKLOADS), default=None)
+    a = ap.parse_args()
+    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    for name in ([a.only] if a.only else sorted(WORKLOADS)):
+        data[name] = run(name)
+        data["_about"] = ("FP64 oracle results (tests/golden/make_full_size.py; oracle/ and synth/ only): "
+                          "Cap, 1^T V 1 and sampled row sums of V")
+        with open(OUT, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+            f.write("\n")
+
+
+if __name__ == "__main__":
+    main()

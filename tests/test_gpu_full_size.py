@@ -1,0 +1,169 @@
+"""The benchmark's full-size workloads against the FP64 oracle.
+
+The oracle's results for the level-5 sphere (N = 20480, the headline
+workload) and for a voxel union refined to N = 60000 (28.8 GB in FP64) take
+minutes to half an hour on the CPU, so they are stored in
+tests/golden/full_size.json by tests/golden/make_full_size.py, which calls
+only the oracle and the mesh generators.  At these sizes every solver
+launch has 256 workgroups and bands of more than 80 rows.
+
+Bars: the FP64 capacity within a relative 1e-12 of the oracle's and the
+mixed one within 1e-8 (the two forms' stated accuracies); the FP64 product
+V 1 within 1e-12 of the oracle's row sums at 64 seeded rows and in its total
+1^T V 1.  The symmetric product (bc_matvec) is also compared with a host
+product of the same stored matrix, at N = 60000 and on the barycentric mesh
+of the Fichera cube refined to N = 12288 (N_bary = 73728): each entry within
+1e-13 of sum_j |V_ij x_j| (FP64 rounding of sums of up to 73728 terms).
+"""
+
+import importlib.util
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_GOLD = {}
+
+
+def gold():
+    if not _GOLD:
+        _GOLD.update(json.load(open(os.path.join(HERE, "golden", "full_size.json"))))
+    return _GOLD
+
+
+def _maker():
+    spec = importlib.util.spec_from_file_location("make_full_size", os.path.join(HERE, "golden", "make_full_size.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+MAKER = _maker()
+_MESH = {}
+
+
+def workload(name):
+    if name not in _MESH:
+        v, t, _ = MAKER.WORKLOADS[name]()
+        assert MAKER.mesh_sha(v, t) == gold()[name]["mesh_sha"], "synth no longer builds the stored mesh"
+        _MESH[name] = (np.asarray(v), np.asarray(t, dtype=np.int32))
+    return _MESH[name]
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1901_08393_amd import api as _api
+
+    return _api
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+def host_product(V, N, x, rows=4096):
+    """y = V x and sum_j |V_ij x_j| on the host, FP64, copying row blocks."""
+    y = np.empty((x.shape[0], N))
+    a = np.empty((x.shape[0], N))
+    for r0 in range(0, N, rows):
+        r1 = min(N, r0 + rows)
+        B = V[r0:r1, :N].cpu().numpy().astype(np.float64)
+        y[:, r0:r1] = (B @ x.T).T
+        a[:, r0:r1] = (np.abs(B) @ np.abs(x).T).T
+    return y, a
+
+
+@pytest.mark.parametrize("name", ["sphere_L5", "voxel_60k"])
+def test_full_size_capacity_vs_oracle(api, name):
+    """Cap of the FP64 and of the mixed GPU forms (the benchmark's options:
+    Radon's rule on distant tiles, stop on the capacity bound 1e-8) against
+    the oracle's dense Cholesky solution."""
+    g = gold()[name]
+    v, t = workload(name)
+    _flush(f"full size {name} N={len(t)} fp64")
+    p = api.CapacityProblem(v, t, "fp64")
+    p.assemble()
+    r = p.solve()
+    assert r.ok, r
+    err64 = abs(r.cap - g["cap"]) / g["cap"]
+    _flush(f"  fp64 cap {r.cap!r} oracle {g['cap']!r} rel {err64:.2e} iters {r.iters}")
+    assert err64 <= 1e-12
+    # V 1 with the stored FP64 matrix against the oracle's row sums
+    ones = torch.ones(p.N, dtype=torch.float64, device="cuda")
+    y = api.matvec(p, ones).cpu().numpy()
+    rows = np.asarray(g["rows"])
+    rs = np.asarray(g["rowsum"])
+    assert np.max(np.abs(y[rows] - rs) / np.abs(rs)) <= 1e-12
+    assert abs(float(np.sum(y)) - g["one_V_one"]) / g["one_V_one"] <= 1e-12
+    p.release_matrix()
+    del p
+    torch.cuda.empty_cache()
+
+    _flush(f"full size {name} mixed")
+    q = api.CapacityProblem(v, t, "mixed")
+    q.assemble()
+    rm = q.solve(cap_rtol=1e-8)
+    assert rm.ok and rm.cap_bound <= 1e-8, rm
+    errm = abs(rm.cap - g["cap"]) / g["cap"]
+    _flush(f"  mixed cap {rm.cap!r} rel {errm:.2e} bound {rm.cap_bound:.2e} iters {rm.iters}")
+    assert errm <= 1e-8
+    rt = q.solve(rtol=1e-10)
+    assert rt.ok
+    assert abs(rt.cap - g["cap"]) / g["cap"] <= 1e-8
+    q.release_matrix()
+    del q
+    torch.cuda.empty_cache()
+
+
+def test_product_60k_against_host(api):
+    """bc_matvec with the FP64 and the FP32 matrix of N = 60000 against a
+    host product of the stored matrix (one and three FP64 vectors)."""
+    v, t = workload("voxel_60k")
+    rng = np.random.default_rng(11)
+    for prec in ("fp64", "mixed"):
+        _flush(f"product 60k {prec}")
+        p = api.CapacityProblem(v, t, prec)
+        p.assemble()
+        for nr in ((1, 3) if prec == "fp64" else (1, 3)):
+            x = rng.standard_normal((nr, p.N))
+            xd = torch.from_numpy(x if nr > 1 else x[0]).to("cuda")
+            y = api.matvec(p, xd).cpu().numpy().reshape(nr, p.N)
+            ref, mag = host_product(p.V, p.N, x)
+            err = np.max(np.abs(y - ref) / mag)
+            _flush(f"  nrhs {nr}: max |y - V x| / sum |V x| = {err:.2e}")
+            assert err <= 1e-13
+        p.release_matrix()
+        del p
+        torch.cuda.empty_cache()
+
+
+def test_product_bary_73k_against_host(api):
+    """The dual system's product on V_bary of the Fichera cube refined to
+    N = 12288 (N_bary = 73728, FP64): one and three vectors against a host
+    product."""
+    f = synth.fichera48()
+    v, t, _ = synth.refine_uniform(f.verts, f.tris, 4)
+    b, _, _ = synth.barycentric(v, t)
+    _flush(f"product bary N_bary={len(b.tris)}")
+    p = api.CapacityProblem(b.verts, b.tris, "fp64", validate=False)
+    p.assemble()
+    rng = np.random.default_rng(12)
+    for nr in (1, 3):
+        x = rng.standard_normal((nr, p.N))
+        xd = torch.from_numpy(x if nr > 1 else x[0]).to("cuda")
+        y = api.matvec(p, xd).cpu().numpy().reshape(nr, p.N)
+        ref, mag = host_product(p.V, p.N, x)
+        err = np.max(np.abs(y - ref) / mag)
+        _flush(f"  nrhs {nr}: {err:.2e}")
+        assert err <= 1e-13
+    p.release_matrix()
+    del p
+    torch.cuda.empty_cache()
