@@ -18,9 +18,7 @@
  *
  * Conventions shared by every call
  *   - All functions are extern "C" and reentrant, and keep no state between
- *     calls other than one constant per device: the mean error of the
- *     hardware FP32 inverse square root, measured by the first mixed
- *     assembly on that device (a fixed computation on fixed inputs).
+ *     calls: everything a later call needs lives in caller-owned buffers.
  *   - The library never allocates device memory: the caller passes device
  *     buffers (inputs, outputs and a workspace whose size the matching
  *     *_bytes function returns) and owns all of them.
@@ -155,7 +153,9 @@ size_t bc_pattern_bytes(int64_t N, int64_t nnz, int32_t precision);
 
 /* Element geometry, pair classification (Section 2.1: pairs are told apart
  * by shared vertex indices of the conforming mesh) and the far-field tile
- * lists.  Fills d_mesh_ws and
+ * lists.  For BC_MIXED it also measures the mean relative error of the FP32
+ * hardware inverse square root (a fixed computation on fixed inputs), which
+ * the FP32 far field divides out of every entry.  Fills d_mesh_ws and
  * writes the pattern sizes to *h_info.  SYNCHRONOUS (waits for `stream`),
  * because the caller needs nnz to size the pattern buffer.  d_verts, d_tris
  * must stay unchanged until bc_assemble and bc_zz_indicators have run. */

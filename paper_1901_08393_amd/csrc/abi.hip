@@ -185,6 +185,10 @@ int32_t bc_prepare(const double *d_verts, int64_t M, const int32_t *d_tris, int6
   if (st != BC_OK) return st;
   st = launch_pattern(d_verts, d_tris, N, opts->near_factor, d_mesh_ws, nullptr, 0, opts->precision, false, s);
   if (st != BC_OK) return st;
+  if (opts->precision == BC_MIXED) {
+    st = launch_rsq_bias(d_mesh_ws, N, s);
+    if (st != BC_OK) return st;
+  }
   int64_t info[8] = {0};
   if (hipMemcpyAsync(info, static_cast<char *>(d_mesh_ws) + L.info, sizeof(info), hipMemcpyDeviceToHost, s) !=
       hipSuccess)

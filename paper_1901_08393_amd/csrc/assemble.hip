@@ -21,7 +21,6 @@
 //   both (i, j) and (j, i) of the pattern.
 // k_pad: zeros in the padding columns N..ld-1.
 #include <algorithm>
-#include <mutex>
 #include <type_traits>
 
 #include "bc_internal.h"
@@ -131,47 +130,42 @@ __global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, 
 // [1, 4) (the error depends only on the mantissa and the exponent's parity,
 // as scaling x by 4 scales rsq(x) by exactly 1/2): 2^16 inputs
 // x_k = 2^(2 (k + 1/2) / 2^16), errors y sqrt(x) - 1 formed in FP64, summed
-// in a fixed order by one workgroup.  Written once per device.
-__device__ double g_rsq_bias;
+// in a fixed order by one workgroup.  Written by bc_prepare (mixed precision)
+// into the caller's mesh workspace, where the FP32 far-field kernels read it.
 constexpr int kRsqSamples = 1 << 16;
+constexpr int kRsqWG = 1024;
 
-__global__ __launch_bounds__(kWG) void k_rsq_bias() {
-  __shared__ double part[kWG];
+__global__ __launch_bounds__(kRsqWG) void k_rsq_bias(double *__restrict__ out) {
+  __shared__ double part[kRsqWG];
   double s = 0.0;
-  for (int k = threadIdx.x; k < kRsqSamples; k += kWG) {
+  for (int k = threadIdx.x; k < kRsqSamples; k += kRsqWG) {
     const float x = (float)exp2(2.0 * (k + 0.5) / kRsqSamples);
     const double y = (double)__builtin_amdgcn_rsqf(x);
     s += y * sqrt((double)x) - 1.0;
   }
   part[threadIdx.x] = s;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int q = 0; q < kWG; ++q) t += part[q];
-    g_rsq_bias = t / kRsqSamples;
+  // fixed-order tree over the 1024 partial sums
+  for (int h = kRsqWG / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) *out = part[0] / kRsqSamples;
 }
 
-// Runs k_rsq_bias once per device, on the first FP32 assembly, and waits for
-// it so that assemblies on any stream see the value.
-static int rsq_bias_ready(hipStream_t s) {
-  static std::mutex mu;
-  static bool done[64] = {};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return BC_EDEVICE;
-  std::lock_guard<std::mutex> lock(mu);
-  if (done[dev]) return BC_OK;
-  hipLaunchKernelGGL(k_rsq_bias, dim3(1), dim3(kWG), 0, s);
-  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return BC_EDEVICE;
-  done[dev] = true;
-  return BC_OK;
+int launch_rsq_bias(void *mesh_ws, int64_t N, hipStream_t s) {
+  MeshLayout L(N);
+  hipLaunchKernelGGL(k_rsq_bias, dim3(1), dim3(kRsqWG), 0, s,
+                     reinterpret_cast<double *>(static_cast<char *>(mesh_ws) + L.rsqb));
+  return hipGetLastError() == hipSuccess ? BC_OK : BC_EDEVICE;
 }
 
 template <int Q>
 __device__ __forceinline__ void far32_tile(int I, int J, const float4 *__restrict__ qpA,
                                            const float *__restrict__ qpS, const double4 *__restrict__ cen4,
                                            const double *__restrict__ area, const double *__restrict__ bbox,
-                                           double scale, int N, int64_t ld, float *__restrict__ V) {
+                                           const double *__restrict__ rsqb, double scale, int N, int64_t ld,
+                                           float *__restrict__ V) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int j = J * 64 + lane;
@@ -188,7 +182,7 @@ __device__ __forceinline__ void far32_tile(int I, int J, const float4 *__restric
   }
   const bool sep = far_separated(bbox, I, J);
   const double4 cj = cen4[jj];
-  const double aj = 4.0 * area[jj] * (scale / (1.0 + g_rsq_bias));
+  const double aj = 4.0 * area[jj] * (scale / (1.0 + *rsqb));
   const int i0 = I * 64 + w * 16;
   auto row = [&](auto SEP, int i) {
     const double4 ci = cen4[i];
@@ -241,12 +235,12 @@ template <int Q, bool LIST>
 __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, const float *__restrict__ qpS,
                                                const double4 *__restrict__ cen4, const double *__restrict__ area,
                                                const double *__restrict__ bbox, const int32_t *__restrict__ cnt,
-                                               const int32_t *__restrict__ list, double scale, int N, int64_t ld,
-                                               float *__restrict__ V) {
+                                               const int32_t *__restrict__ list, const double *__restrict__ rsqb,
+                                               double scale, int N, int64_t ld, float *__restrict__ V) {
   int I, J;
   if (!LIST) {
     tile_of(blockIdx.x, I, J);
-    far32_tile<Q>(I, J, qpA, qpS, cen4, area, bbox, scale, N, ld, V);
+    far32_tile<Q>(I, J, qpA, qpS, cen4, area, bbox, rsqb, scale, N, ld, V);
     return;
   }
   const int nt = (int)far_tiles(N), n = min(*cnt, nt);
@@ -254,7 +248,7 @@ __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, c
     const int t = list[q];
     if (t < 0 || t >= nt) continue;  // lists from another mesh: nothing out of range
     tile_of(t, I, J);
-    far32_tile<Q>(I, J, qpA, qpS, cen4, area, bbox, scale, N, ld, V);
+    far32_tile<Q>(I, J, qpA, qpS, cen4, area, bbox, rsqb, scale, N, ld, V);
   }
 }
 
@@ -284,7 +278,8 @@ template <int QP>
 __device__ __forceinline__ void far32m_tile(int I, int J, const double4 *__restrict__ qpA,
                                             const float *__restrict__ qpB, const FarWeights &fw,
                                             const double *__restrict__ area, const double *__restrict__ bbox,
-                                            double scale, int N, int64_t ld, float *__restrict__ V) {
+                                            const double *__restrict__ rsqb, double scale, int N, int64_t ld,
+                                            float *__restrict__ V) {
   static_assert(QP == 16 || QP == kQLow, "far rule of 16 or kQLow points");
   const int lane = (int)__lane_id();
   const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
@@ -322,7 +317,7 @@ __device__ __forceinline__ void far32m_tile(int I, int J, const double4 *__restr
   }
   const int j = j0 + (lane & 15), ib = i0 + 4 * k;
   if (j >= N) return;
-  const double aj = 4.0 * area[j] * (scale / (1.0 + g_rsq_bias));
+  const double aj = 4.0 * area[j] * (scale / (1.0 + *rsqb));
   float v[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) v[r] = ib + r < N ? (float)((double)S[r] * (area[ib + r] * aj)) : 0.f;
@@ -344,15 +339,15 @@ template <int QP>
 __global__ __launch_bounds__(1024) void k_far32m(const double4 *__restrict__ qpA, const float *__restrict__ qpB,
                                                  FarWeights fw, const double *__restrict__ area,
                                                  const double *__restrict__ bbox, const int32_t *__restrict__ cnt,
-                                                 const int32_t *__restrict__ list, double scale, int N, int64_t ld,
-                                                 float *__restrict__ V) {
+                                                 const int32_t *__restrict__ list, const double *__restrict__ rsqb,
+                                                 double scale, int N, int64_t ld, float *__restrict__ V) {
   const int nt = (int)far_tiles(N), n = min(*cnt, nt);
   for (int q = blockIdx.x; q < n; q += gridDim.x) {
     const int t = list[q];
     if (t < 0 || t >= nt) continue;  // lists from another mesh: nothing out of range
     int I, J;
     tile_of(t, I, J);
-    far32m_tile<QP>(I, J, qpA, qpB, fw, area, bbox, scale, N, ld, V);
+    far32m_tile<QP>(I, J, qpA, qpB, fw, area, bbox, rsqb, scale, N, ld, V);
   }
 }
 
@@ -574,19 +569,20 @@ static void far_launch(bool mixed, bool low_order, const MeshView &m, int N, int
     for (int a = 0; a < kQLow; ++a) wL.w[a] = (float)rw[a];
     const int gv = std::min(nt, 4 * cus), gm = std::min(nt, 2 * cus);
     hipLaunchKernelGGL((k_far32<Q, true>), dim3(gv), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox, cnt,
-                       list, scale, N, ld, static_cast<float *>(V));
+                       list, m.rsq_bias, scale, N, ld, static_cast<float *>(V));
     hipLaunchKernelGGL(k_far32m<16>, dim3(gm), dim3(1024), 0, s, m.qpA64, m.qpB16, w16, m.area, m.bbox, cnt + 1,
-                       list + (size_t)nt, scale, N, ld, static_cast<float *>(V));
+                       list + (size_t)nt, m.rsq_bias, scale, N, ld, static_cast<float *>(V));
     if (low_order)
       hipLaunchKernelGGL(k_far32m<kQLow>, dim3(gm), dim3(1024), 0, s, m.qpLA64, m.qpBL, wL, m.area, m.bbox,
-                         cnt + 2, list + 2 * (size_t)nt, far32_scale_w(rw, kQLow), N, ld,
+                         cnt + 2, list + 2 * (size_t)nt, m.rsq_bias, far32_scale_w(rw, kQLow), N, ld,
                          static_cast<float *>(V));
     else
       hipLaunchKernelGGL(k_far32m<16>, dim3(gm), dim3(1024), 0, s, m.qpA64, m.qpB16, w16, m.area, m.bbox, cnt + 2,
-                         list + 2 * (size_t)nt, scale, N, ld, static_cast<float *>(V));
+                         list + 2 * (size_t)nt, m.rsq_bias, scale, N, ld, static_cast<float *>(V));
   } else {
     hipLaunchKernelGGL((k_far32<Q, false>), dim3(tiles), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox,
-                       (const int32_t *)nullptr, (const int32_t *)nullptr, scale, N, ld, static_cast<float *>(V));
+                       (const int32_t *)nullptr, (const int32_t *)nullptr, m.rsq_bias, scale, N, ld,
+                       static_cast<float *>(V));
   }
 }
 
@@ -623,10 +619,6 @@ int launch_assemble(const void *mesh_ws, const int32_t *tris, const double *vert
   const int tiles = (int)(T * (T + 1) / 2);
   const double scale = far32_scale(o.far_order);
   const bool low = mixed && o.far_low == 1;
-  if (mixed) {
-    const int st = rsq_bias_ready(s);
-    if (st != BC_OK) return st;
-  }
   switch (o.far_order) {
     case 1: far_launch<1>(mixed, low, m, (int)N, ld, V, tiles, scale, s); break;
     case 2: far_launch<4>(mixed, low, m, (int)N, ld, V, tiles, scale, s); break;

@@ -33,7 +33,7 @@ __host__ __device__ inline int64_t far_tiles(int64_t N) {
 
 struct MeshLayout {
   size_t tri4, cen4, area, qpA64, qpS64, qpA32, qpS32, qpLA64, qpLS64, qpB16, qpBL, rowcnt, rowptr, kindcnt, info,
-      blockbox, tiles, total;
+      rsqb, blockbox, tiles, total;
   explicit MeshLayout(int64_t N) {
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
@@ -56,6 +56,10 @@ struct MeshLayout {
     rowptr = take(sizeof(int32_t) * (N + 1));
     kindcnt = take(sizeof(int32_t) * 4 * N);
     info = take(sizeof(int64_t) * 8);
+    // mean relative error of the FP32 hardware inverse square root, measured
+    // by bc_prepare in mixed precision and divided out of every FP32 far
+    // entry (one double)
+    rsqb = take(sizeof(double));
     blockbox = take(sizeof(double) * 8 * ((N + 63) / 64));  // per 64 elements: min xyz, max xyz, max diam^2
     // far-field tile lists: kTileClasses counts (padded to 16), one list of
     // tile indices per class, and the per-chunk counts of the list builder
@@ -82,6 +86,7 @@ struct MeshView {
   const float *qpBL;
   const int32_t *tile_cnt;   // kTileClasses counts
   const int32_t *tile_list;  // [kTileClasses][far_tiles(N)]
+  const double *rsq_bias;    // see MeshLayout::rsqb
 };
 
 inline MeshView mesh_view(const void *ws, int64_t N) {
@@ -103,6 +108,7 @@ inline MeshView mesh_view(const void *ws, int64_t N) {
   v.qpBL = reinterpret_cast<const float *>(b + L.qpBL);
   v.tile_cnt = reinterpret_cast<const int32_t *>(b + L.tiles);
   v.tile_list = v.tile_cnt + 16;
+  v.rsq_bias = reinterpret_cast<const double *>(b + L.rsqb);
   return v;
 }
 
@@ -395,6 +401,9 @@ __device__ __forceinline__ T wave_sum_full(T v) {
 namespace bc {
 int launch_geometry(const double *verts, int64_t M, const int32_t *tris, int64_t N,
                     int far_order, void *mesh_ws, hipStream_t s);
+// the mean error of the FP32 hardware inverse square root into the mesh
+// workspace (MeshLayout::rsqb)
+int launch_rsq_bias(void *mesh_ws, int64_t N, hipStream_t s);
 int launch_pattern(const double *verts, const int32_t *tris, int64_t N, double near_factor, const void *mesh_ws,
                    void *pattern, int64_t nnz, int32_t precision, bool emit, hipStream_t s);
 int launch_assemble(const void *mesh_ws, const int32_t *tris, const double *verts, int64_t N,
