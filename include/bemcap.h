@@ -250,6 +250,22 @@ int32_t bc_solve(const void *d_V, int64_t N, int32_t precision,
                  double *d_sigma, const bc_solve_opts *opts, void *d_ws,
                  size_t ws_bytes, bc_result *d_result, bc_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): bc_solve
+ * with the solver workspace in a 96 MiB device array inside the library
+ * instead of a caller buffer, enough for any N up to 32000 in either
+ * precision; larger systems return BC_ENOMEM (use bc_solve).  Same kernels,
+ * arithmetic and results as bc_solve.  Allocates nothing: each GPU holds its
+ * own copy of the array until the process ends, and the first call on a
+ * device looks up that copy's address.  Every call on one GPU shares the
+ * array, so calls that overlap on one GPU (other streams, other threads)
+ * race; the caller serialises them.  ASYNC. */
+int32_t bc_solve_static(const void *d_V, int64_t N, int32_t precision,
+                        const void *d_pattern, int64_t nnz,
+                        const double *d_area, double *d_sigma,
+                        const bc_solve_opts *opts, bc_result *d_result,
+                        bc_stream stream);
+
 /* One system of a batched solve (all pointers device pointers). */
 typedef struct bc_system {
   const void *V;        /* N x ld matrix of `precision` */

@@ -88,6 +88,7 @@ SIGNATURES = {
     "bc_solve_workspace_bytes": (SZ, [I64, I32]),
     "bc_solve_workgroups": (I32, [I64]),
     "bc_solve": (I32, [P, I64, I32, P, I64, P, P, C.POINTER(bc_solve_opts), P, SZ, P, P]),
+    "bc_solve_static": (I32, [P, I64, I32, P, I64, P, P, C.POINTER(bc_solve_opts), P, P]),
     "bc_batch_scratch_bytes": (SZ, [I32]),
     "bc_solve_batched": (I32, [I32, C.POINTER(bc_system), C.POINTER(bc_solve_opts), I32, P, SZ, P]),
     "bc_solve_capacity": (I32, [I32]),

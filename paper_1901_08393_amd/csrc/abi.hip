@@ -291,9 +291,14 @@ static int fill_desc(const bc_system &s, int wg_begin, SysDesc &d) {
   return BC_OK;
 }
 
-int32_t bc_solve(const void *d_V, int64_t N, int32_t precision, const void *d_pattern, int64_t nnz,
-                 const double *d_area, double *d_sigma, const bc_solve_opts *opts, void *d_ws, size_t ws_bytes,
-                 bc_result *d_result, bc_stream stream) {
+}  // extern "C"
+
+namespace bc {
+// bc_solve on a given workspace (also the body of the entry point whose
+// workspace is the library's own device array).
+int solve_one(const void *d_V, int64_t N, int32_t precision, const void *d_pattern, int64_t nnz, const double *d_area,
+              double *d_sigma, const bc_solve_opts *opts, void *d_ws, size_t ws_bytes, bc_result *d_result,
+              hipStream_t s) {
   if (!solve_opts_ok(opts)) return BC_EINVAL;
   if (precision != BC_FP64 && precision != BC_MIXED) return BC_EINVAL;
   if (!n_ok(N) || !d_ws) return BC_EINVAL;
@@ -306,11 +311,20 @@ int32_t bc_solve(const void *d_V, int64_t N, int32_t precision, const void *d_pa
   int st = fill_desc(sys, 0, d);
   if (st != BC_OK) return st;
   if (d.wg_count > solve_capacity(precision)) return BC_EDEVICE;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   SysDesc *dd = reinterpret_cast<SysDesc *>(static_cast<char *>(d_ws) + ((desc_off + 63) & ~size_t(63)));
   st = launch_set_desc(&d, 1, dd, s);
   if (st != BC_OK) return st;
   return launch_solve(precision, dd, 1, d.wg_count, params_of(opts, 0, 1), s);
+}
+}  // namespace bc
+
+extern "C" {
+
+int32_t bc_solve(const void *d_V, int64_t N, int32_t precision, const void *d_pattern, int64_t nnz,
+                 const double *d_area, double *d_sigma, const bc_solve_opts *opts, void *d_ws, size_t ws_bytes,
+                 bc_result *d_result, bc_stream stream) {
+  return solve_one(d_V, N, precision, d_pattern, nnz, d_area, d_sigma, opts, d_ws, ws_bytes, d_result,
+                   static_cast<hipStream_t>(stream));
 }
 
 int32_t bc_solve_batched(int32_t n_sys, const bc_system *h_sys, const bc_solve_opts *opts, int32_t iter_budget,

@@ -429,6 +429,10 @@ int run_dual_solve(const void *Vb, int32_t precision, const void *pattern, int64
 int launch_dual_zz(const void *ws, const int32_t *tris, int64_t N, int64_t M, int32_t restart, const double *x,
                    int h_mode, double *eta2, hipStream_t s);
 int solve_workgroups(int64_t N);
+// bc_solve on the workspace d_ws (ws_bytes long)
+int solve_one(const void *d_V, int64_t N, int32_t precision, const void *d_pattern, int64_t nnz, const double *d_area,
+              double *d_sigma, const bc_solve_opts *opts, void *d_ws, size_t ws_bytes, bc_result *d_result,
+              hipStream_t s);
 int launch_set_desc(const SysDesc *h, int n, SysDesc *d, hipStream_t s);
 void gauss_legendre01(int n, double *x, double *w);
 void radon7(double *s, double *t, double *w);
