@@ -24,7 +24,10 @@ path computes:
   and Doerfler marking (eq. "doerfler");
 * the dual-mesh system of the paper's Algorithm 1 (``dual``): barycentric
   V, the projections P and Q_m, the hypersingular matrix, the mass matrix,
-  the direct dual solve, its capacity and ZZ indicators (Section 2.6).
+  the direct dual solve, its capacity and ZZ indicators (Section 2.6);
+* the weighted-residual estimator of the primal solution (``residual``;
+  Appendix A, eq. "residual:indicator") with the residual evaluated in the
+  discontinuous piecewise linears.
 
 Parity pins are in tests/test_oracle_*.py.  Functions without an independent
 pin say "parity unpinned" in their docstring.
@@ -51,3 +54,4 @@ from .capacity import (  # noqa: F401
     mesh_check,
 )
 from . import dual  # noqa: F401
+from . import residual  # noqa: F401
