@@ -325,6 +325,38 @@ int32_t bc_zz_indicators(const int32_t *d_tris, int64_t N,
                          double *d_eta2, bc_stream stream);
 
 /* ------------------------------------------------------------------------ */
+/* Weighted-residual error estimator                                        */
+/* ------------------------------------------------------------------------ */
+
+/* Device scratch of bc_residual_indicators: per element 3 partial moments
+ * per column chunk (the chunk count depends on N only) and 3 moments per
+ * pattern entry.  0 for N < 1 or nnz < N. */
+size_t bc_residual_workspace_bytes(int64_t N, int64_t nnz);
+
+/* mu(T)^2 = diam(T) ||grad_G (1 - V Phi)||^2_{L2(T)} (Appendix A, eq.
+ * "residual:indicator") for the P0 density Phi = d_sigma, with the
+ * residual evaluated in the discontinuous piecewise linears (as the paper's
+ * remark on the estimator's cost describes): on each element the L2
+ * projection of 1 - V Phi onto the linear functions, whose surface gradient
+ * is constant.  It needs the first moments m_k(T) = <V Phi, lambda_k>_T
+ * (lambda_k the barycentric coordinate of the k-th input vertex of T),
+ * computed in FP64 without storing a matrix: the collapsed Gauss rule of
+ * opts->far_order on both triangles for pairs sharing no vertex, the
+ * singular rules of opts->ss_order for touching pairs; O(N^2) point pairs
+ * like the assembly (all ordered pairs).  Then
+ * mu(T)^2 = 36 diam(T) |sum_k m_k (P_{k+2} - P_{k+1})|^2 / |T|^3.
+ * d_mesh_ws, d_pattern, nnz and opts as given to bc_prepare / bc_assemble
+ * (either precision: near entries of a mixed pattern take the regular rule
+ * here).  d_mu2: N FP64; d_moments: NULL or N x 3 FP64 (m_k per element).
+ * Fixed summation order.  ASYNC. */
+int32_t bc_residual_indicators(const double *d_verts, const int32_t *d_tris,
+                               int64_t N, const bc_assembly_opts *opts,
+                               const void *d_mesh_ws, const void *d_pattern,
+                               int64_t nnz, const double *d_sigma,
+                               double *d_mu2, double *d_moments, void *d_ws,
+                               size_t ws_bytes, bc_stream stream);
+
+/* ------------------------------------------------------------------------ */
 /* Standalone product with a stored matrix                                  */
 /* ------------------------------------------------------------------------ */
 

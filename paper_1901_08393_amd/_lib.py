@@ -94,6 +94,8 @@ SIGNATURES = {
     "bc_solve_capacity": (I32, [I32]),
     "bc_capacity": (I32, [P, P, I64, P, P]),
     "bc_zz_indicators": (I32, [P, I64, P, P, I64, P, I32, P, P]),
+    "bc_residual_workspace_bytes": (SZ, [I64, I64]),
+    "bc_residual_indicators": (I32, [P, P, I64, C.POINTER(bc_assembly_opts), P, P, I64, P, P, P, P, SZ, P]),
     "bc_matvec_workspace_bytes": (SZ, [I64, I32, I32]),
     "bc_matvec": (I32, [P, I64, I32, I32, P, P, P, SZ, P]),
     "bc_dual_workspace_bytes": (SZ, [I64, I64, I32]),

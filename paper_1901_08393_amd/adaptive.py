@@ -5,7 +5,10 @@ dual mesh as the algorithm states it (adaptive_dual).
 (i)   solve: dense assembly and persistent Krylov solve on the GPU, warm
       started from the previous mesh's solution (the P0 spaces of NVB meshes
       are nested, so every son inherits its parent's value);
-(ii)  estimate: ZZ-type indicators eta(T)^2 on the GPU (eq. "zz:T");
+(ii)  estimate: ZZ-type indicators eta(T)^2 on the GPU (eq. "zz:T"), or
+      on the primal path the weighted-residual indicators mu(T)^2 of
+      Appendix A (eq. "residual:indicator"), which drive the standard
+      adaptive algorithm stated there;
 (iii) mark: Doerfler marking (eq. "doerfler") on the host;
 (iv)  refine: newest-vertex bisection of the marked elements with closure.
 
@@ -65,13 +68,18 @@ class Step:
 def adaptive_capacity(verts, tris, steps: int = 5, theta: float = 0.5, precision: str = "fp64",
                       h_mode: int = 0, warm_start: bool = True, keep: bool = False, refine: str = "bisec1",
                       max_elements: Optional[int] = None, far_order: int = 4, ss_order: int = 4,
-                      **solve_opts) -> List[Step]:
+                      estimator: str = "zz", **solve_opts) -> List[Step]:
     """Run `steps` refinements (steps + 1 solves), or stop before the first
     mesh with more than `max_elements` triangles.  `tris` must be in NVB form
     (reference edge first); use synth.init_reference_edges on a new mesh.
     refine "bisec1" bisects every marked element once and closes the mesh
     (the coarsest conforming refinement of step (iv)); "bisec3" splits
-    marked elements into four."""
+    marked elements into four.  estimator "zz" marks by the ZZ-type
+    indicators (h_mode as in bc_zz_indicators); "residual" by the
+    weighted-residual indicators mu(T)^2 (Appendix A's algorithm; always
+    with diam(T)), reported in the eta2 fields."""
+    if estimator not in ("zz", "residual"):
+        raise ValueError("estimator: 'zz' or 'residual'")
     verts = np.asarray(verts, dtype=np.float64)
     tris = np.asarray(tris, dtype=np.int32)
     x0 = None
@@ -85,7 +93,7 @@ def adaptive_capacity(verts, tris, steps: int = 5, theta: float = 0.5, precision
         ev[1].record()
         res = prob.solve(x0=x0 if warm_start else None, sync=False, **solve_opts)
         ev[2].record()
-        eta2_d = prob.zz(h_mode=h_mode)
+        eta2_d = prob.zz(h_mode=h_mode) if estimator == "zz" else prob.residual()
         ev[3].record()
         res = prob.result()
         if not res.ok:

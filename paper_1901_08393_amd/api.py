@@ -217,6 +217,23 @@ class CapacityProblem:
                                                          _ptr(eta2), _stream(stream)))
         return eta2
 
+    # ------------------------------------------------- residual estimator
+    def residual(self, sigma: Optional[torch.Tensor] = None, moments: bool = False, stream=None):
+        """Weighted-residual indicators mu(T)^2 (Appendix A, eq.
+        "residual:indicator"; bc_residual_indicators) of the density sigma
+        (default: the last solution), in FP64.  With moments=True also
+        returns the first moments <V sigma, lambda_k>_T (N x 3)."""
+        sigma = self.sigma if sigma is None else sigma
+        L = lib()
+        nb = L.bc_residual_workspace_bytes(self.N, self.nnz)
+        ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        mu2 = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        mom = torch.empty((self.N, 3), dtype=torch.float64, device=self.device) if moments else None
+        check("bc_residual_indicators", L.bc_residual_indicators(
+            _ptr(self.d_verts), _ptr(self.d_tris), self.N, C.byref(self.opts), _ptr(self.mesh_ws),
+            _ptr(self.pattern), self.nnz, _ptr(sigma), _ptr(mu2), _ptr(mom), _ptr(ws), nb, _stream(stream)))
+        return (mu2, mom) if moments else mu2
+
     def release_matrix(self):
         self.V = None
         self.solve_ws = None

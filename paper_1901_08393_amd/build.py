@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbemcap.so")
-SOURCES = ["abi.hip", "geometry.hip", "assemble.hip", "solve.hip", "zz.hip", "dual.hip", "solve_static.hip"]
+SOURCES = ["abi.hip", "geometry.hip", "assemble.hip", "solve.hip", "zz.hip", "dual.hip", "residual.hip", "solve_static.hip"]
 ARCH = os.environ.get("BEMCAP_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

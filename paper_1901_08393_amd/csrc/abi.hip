@@ -353,6 +353,21 @@ int32_t bc_capacity(const double *d_sigma, const double *d_area, int64_t N, doub
   return launch_capacity(d_sigma, d_area, N, d_cap, static_cast<hipStream_t>(stream));
 }
 
+size_t bc_residual_workspace_bytes(int64_t N, int64_t nnz) {
+  if (!n_ok(N) || nnz < N) return 0;
+  return residual_workspace_bytes(N, nnz);
+}
+
+int32_t bc_residual_indicators(const double *d_verts, const int32_t *d_tris, int64_t N, const bc_assembly_opts *opts,
+                               const void *d_mesh_ws, const void *d_pattern, int64_t nnz, const double *d_sigma,
+                               double *d_mu2, double *d_moments, void *d_ws, size_t ws_bytes, bc_stream stream) {
+  if (!d_verts || !d_tris || !d_mesh_ws || !d_pattern || !d_sigma || !d_mu2 || !d_ws) return BC_EINVAL;
+  if (!n_ok(N) || nnz < N || !opts_ok(opts)) return BC_EINVAL;
+  if (ws_bytes < residual_workspace_bytes(N, nnz)) return BC_ENOMEM;
+  return launch_residual(d_verts, N, *opts, d_mesh_ws, d_pattern, nnz, d_sigma, d_mu2, d_moments, d_ws,
+                         static_cast<hipStream_t>(stream));
+}
+
 int32_t bc_zz_indicators(const int32_t *d_tris, int64_t N, const void *d_mesh_ws, const void *d_pattern, int64_t nnz,
                          const double *d_sigma, int32_t h_mode, double *d_eta2, bc_stream stream) {
   if (!d_tris || !d_mesh_ws || !d_pattern || !d_sigma || !d_eta2 || !n_ok(N) || nnz < N) return BC_EINVAL;

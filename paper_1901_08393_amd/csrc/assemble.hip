@@ -352,57 +352,6 @@ __global__ __launch_bounds__(1024) void k_far32m(const double4 *__restrict__ qpA
 }
 
 // ------------------------------------------------------- touching and near
-struct SSRule {
-  int n;
-  int pad;
-  double x[kSSMax], w[kSSMax];
-};
-
-// Region maps of the singular rules on K = {0 <= x2 <= x1 <= 1}; (xi, e1,
-// e2, e3) in [0,1]^4.  Returns the Jacobian and writes the two reference
-// points.  kind: 3 coincident (6 regions), 2 edge (4), 1 vertex (2).
-__device__ __forceinline__ double ss_map(int kind, int reg, double xi, double e1, double e2, double e3, double &x1,
-                                         double &x2, double &y1, double &y2) {
-  double a1, a2, b1, b2, J;
-  if (kind == kCoincident) {
-    J = xi * xi * xi * e1 * e1 * e2;
-    int r = reg >> 1;
-    if (r == 0) {
-      a1 = xi; a2 = xi * (1.0 - e1 + e1 * e2);
-      b1 = xi * (1.0 - e1 * e2 * e3); b2 = xi * (1.0 - e1);
-    } else if (r == 1) {
-      a1 = xi; a2 = xi * e1 * (1.0 - e2 + e2 * e3);
-      b1 = xi * (1.0 - e1 * e2); b2 = xi * e1 * (1.0 - e2);
-    } else {
-      a1 = xi * (1.0 - e1 * e2 * e3); a2 = xi * e1 * (1.0 - e2 * e3);
-      b1 = xi; b2 = xi * e1 * (1.0 - e2);
-    }
-  } else if (kind == kEdge) {
-    if ((reg & 1) == 0) {   // {p >= w + r}
-      J = xi * xi * xi * e1 * e1 * e2;
-      a1 = xi; a2 = xi * e1;
-      b1 = xi * (1.0 - e1 * e2 * e3); b2 = xi * e1 * e2 * (1.0 - e3);
-    } else {                // {p <= w + r}
-      J = xi * xi * xi * e1 * e1;
-      a1 = xi; a2 = xi * e1 * e3;
-      b1 = xi * (1.0 - e1 * e2); b2 = xi * e1 * (1.0 - e2);
-    }
-  } else {
-    J = xi * xi * xi * e2;
-    a1 = xi; a2 = xi * e1;
-    b1 = xi * e2; b2 = xi * e2 * e3;
-  }
-  // odd regions are the mirror images (the two triangles swap roles)
-  if (kind == kEdge) {
-    // edge regions are ordered A, B, mirror A, mirror B
-    if (reg >= 2) { double t1 = a1, t2 = a2; a1 = b1; a2 = b2; b1 = t1; b2 = t2; }
-  } else if (reg & 1) {
-    double t1 = a1, t2 = a2; a1 = b1; a2 = b2; b1 = t1; b2 = t2;
-  }
-  x1 = a1; x2 = a2; y1 = b1; y2 = b2;
-  return J;
-}
-
 // NSS > 0: the singular rules' order as a compile-time constant (4, 8), so
 // that the point index splits into Gauss indices by shifts, not divisions.
 template <bool MIXED, int NSS>
@@ -428,32 +377,8 @@ __device__ __forceinline__ void sparse_entry(int64_t e, const double *__restrict
     }
     scale = kInv4Pi;
   } else {
-    const int4 ti = tri4[i], tj = tri4[j];
-    int A, B, C, D0, D1, D2;
-    if (kind == kCoincident) {
-      A = ti.x; B = ti.y; C = ti.z; D0 = ti.x; D1 = ti.y; D2 = ti.z;
-    } else if (kind == kEdge) {
-      // shared edge {A, B}, A the lower index; C, D the other vertices
-      const int tv[3] = {ti.x, ti.y, ti.z}, sv[3] = {tj.x, tj.y, tj.z};
-      int sh[2], ns = 0, c = -1, d = -1;
-      for (int a = 0; a < 3; ++a) {
-        bool in = tv[a] == sv[0] || tv[a] == sv[1] || tv[a] == sv[2];
-        if (in) sh[ns++ & 1] = tv[a]; else c = tv[a];
-        bool jn = sv[a] == tv[0] || sv[a] == tv[1] || sv[a] == tv[2];
-        if (!jn) d = sv[a];
-      }
-      A = min(sh[0], sh[1]); B = max(sh[0], sh[1]); C = c;
-      D0 = A; D1 = B; D2 = d;
-    } else {
-      // shared vertex A; the others in each element's cyclic order after A
-      const int tv[3] = {ti.x, ti.y, ti.z}, sv[3] = {tj.x, tj.y, tj.z};
-      int ki = 0, kj = 0;
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b)
-          if (tv[a] == sv[b]) { ki = a; kj = b; }
-      A = tv[ki]; B = tv[(ki + 1) % 3]; C = tv[(ki + 2) % 3];
-      D0 = A; D1 = sv[(kj + 1) % 3]; D2 = sv[(kj + 2) % 3];
-    }
+    const TouchOrder o = touch_order(kind, tri4[i], tri4[j]);
+    const int A = o.P[0], B = o.P[1], C = o.P[2], D0 = o.Q[0], D1 = o.Q[1], D2 = o.Q[2];
     const double ax = verts[3 * A], ay = verts[3 * A + 1], az = verts[3 * A + 2];
     const double bax = verts[3 * B] - ax, bay = verts[3 * B + 1] - ay, baz = verts[3 * B + 2] - az;
     const double cbx = verts[3 * C] - verts[3 * B], cby = verts[3 * C + 1] - verts[3 * B + 1],

@@ -348,6 +348,100 @@ __device__ __forceinline__ bool far_low_order(const double *bbox, int I, int J) 
   return box_dist2(bi, bj) >= kSepFarLow * kSepFarLow * fmax(bi[6], bj[6]);
 }
 
+struct SSRule {
+  int n;
+  int pad;
+  double x[kSSMax], w[kSSMax];
+};
+
+// Region maps of the singular rules on K = {0 <= x2 <= x1 <= 1}; (xi, e1,
+// e2, e3) in [0,1]^4.  Returns the Jacobian and writes the two reference
+// points.  kind: 3 coincident (6 regions), 2 edge (4), 1 vertex (2).
+__device__ __forceinline__ double ss_map(int kind, int reg, double xi, double e1, double e2, double e3, double &x1,
+                                         double &x2, double &y1, double &y2) {
+  double a1, a2, b1, b2, J;
+  if (kind == kCoincident) {
+    J = xi * xi * xi * e1 * e1 * e2;
+    int r = reg >> 1;
+    if (r == 0) {
+      a1 = xi; a2 = xi * (1.0 - e1 + e1 * e2);
+      b1 = xi * (1.0 - e1 * e2 * e3); b2 = xi * (1.0 - e1);
+    } else if (r == 1) {
+      a1 = xi; a2 = xi * e1 * (1.0 - e2 + e2 * e3);
+      b1 = xi * (1.0 - e1 * e2); b2 = xi * e1 * (1.0 - e2);
+    } else {
+      a1 = xi * (1.0 - e1 * e2 * e3); a2 = xi * e1 * (1.0 - e2 * e3);
+      b1 = xi; b2 = xi * e1 * (1.0 - e2);
+    }
+  } else if (kind == kEdge) {
+    if ((reg & 1) == 0) {   // {p >= w + r}
+      J = xi * xi * xi * e1 * e1 * e2;
+      a1 = xi; a2 = xi * e1;
+      b1 = xi * (1.0 - e1 * e2 * e3); b2 = xi * e1 * e2 * (1.0 - e3);
+    } else {                // {p <= w + r}
+      J = xi * xi * xi * e1 * e1;
+      a1 = xi; a2 = xi * e1 * e3;
+      b1 = xi * (1.0 - e1 * e2); b2 = xi * e1 * (1.0 - e2);
+    }
+  } else {
+    J = xi * xi * xi * e2;
+    a1 = xi; a2 = xi * e1;
+    b1 = xi * e2; b2 = xi * e2 * e3;
+  }
+  // odd regions are the mirror images (the two triangles swap roles)
+  if (kind == kEdge) {
+    // edge regions are ordered A, B, mirror A, mirror B
+    if (reg >= 2) { double t1 = a1, t2 = a2; a1 = b1; a2 = b2; b1 = t1; b2 = t2; }
+  } else if (reg & 1) {
+    double t1 = a1, t2 = a2; a1 = b1; a2 = b2; b1 = t1; b2 = t2;
+  }
+  x1 = a1; x2 = a2; y1 = b1; y2 = b2;
+  return J;
+}
+
+// Canonical vertex orders of a touching pair, the first element p and the
+// second q, as the singular rules use them: P = (A, B, C) on T_p and
+// Q = (D0, D1, D2) on T_q.
+//   coincident: P = Q = T_p in input order;
+//   edge:       {A, B} the shared edge, A the lower vertex index, C the free
+//               vertex of T_p; Q = (A, B, D), D the free vertex of T_q;
+//   vertex:     A the shared vertex, B and C the other vertices of T_p in its
+//               cyclic input order after A; Q = (A, D, E) likewise for T_q.
+// sp[c], sq[c]: the input slot (0..2) of P[c] in T_p and of Q[c] in T_q.
+struct TouchOrder {
+  int P[3], Q[3], sp[3], sq[3];
+};
+
+__device__ __forceinline__ TouchOrder touch_order(int kind, int4 tp, int4 tq) {
+  const int tv[3] = {tp.x, tp.y, tp.z}, sv[3] = {tq.x, tq.y, tq.z};
+  TouchOrder o;
+  if (kind == kCoincident) {
+    for (int c = 0; c < 3; ++c) { o.P[c] = tv[c]; o.Q[c] = tv[c]; }
+  } else if (kind == kEdge) {
+    int sh[2] = {0, 0}, ns = 0, c = -1, d = -1;
+    for (int a = 0; a < 3; ++a) {
+      const bool in = tv[a] == sv[0] || tv[a] == sv[1] || tv[a] == sv[2];
+      if (in) sh[ns++ & 1] = tv[a]; else c = tv[a];
+      const bool jn = sv[a] == tv[0] || sv[a] == tv[1] || sv[a] == tv[2];
+      if (!jn) d = sv[a];
+    }
+    o.P[0] = min(sh[0], sh[1]); o.P[1] = max(sh[0], sh[1]); o.P[2] = c;
+    o.Q[0] = o.P[0]; o.Q[1] = o.P[1]; o.Q[2] = d;
+  } else {
+    int ki = 0, kj = 0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        if (tv[a] == sv[b]) { ki = a; kj = b; }
+    o.P[0] = tv[ki]; o.P[1] = tv[(ki + 1) % 3]; o.P[2] = tv[(ki + 2) % 3];
+    o.Q[0] = o.P[0]; o.Q[1] = sv[(kj + 1) % 3]; o.Q[2] = sv[(kj + 2) % 3];
+  }
+  for (int c = 0; c < 3; ++c) {
+    o.sp[c] = o.P[c] == tv[0] ? 0 : (o.P[c] == tv[1] ? 1 : 2);
+    o.sq[c] = o.Q[c] == sv[0] ? 0 : (o.Q[c] == sv[1] ? 1 : 2);
+  }
+  return o;
+}
+
 // Fused multiply-add in the type of the operands (__builtin_fma alone would
 // promote float operands to double).
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -408,6 +502,11 @@ int launch_pattern(const double *verts, const int32_t *tris, int64_t N, double n
                    void *pattern, int64_t nnz, int32_t precision, bool emit, hipStream_t s);
 int launch_assemble(const void *mesh_ws, const int32_t *tris, const double *verts, int64_t N,
                     const bc_assembly_opts &o, void *pattern, int64_t nnz, void *V, hipStream_t s);
+// weighted-residual estimator: workspace bytes and the three kernels
+size_t residual_workspace_bytes(int64_t N, int64_t nnz);
+int launch_residual(const double *verts, int64_t N, const bc_assembly_opts &o, const void *mesh_ws,
+                    const void *pattern, int64_t nnz, const double *sigma, double *mu2, double *mom, void *ws,
+                    hipStream_t s);
 int launch_zz(const int32_t *tris, int64_t N, const void *mesh_ws, const void *pattern, int64_t nnz,
               const double *sigma, int h_mode, double *eta2, hipStream_t s);
 int launch_capacity(const double *sigma, const double *area, int64_t N, double *cap, hipStream_t s);
