@@ -48,6 +48,7 @@ from .operator import (  # noqa: F401
 from .capacity import (  # noqa: F401
     rhs,
     solve_direct,
+    solve_cg,
     capacity,
     zz_indicators,
     doerfler,

@@ -36,6 +36,52 @@ def solve_direct(V, b, overwrite: bool = False):
     return scipy.linalg.cho_solve(c, b)
 
 
+def solve_cg(V, b, rtol: float = 1e-14, max_iter: int = 20000, rows: int = 4096):
+    """x with ||b - V x|| <= rtol ||b|| by conjugate gradients with diagonal
+    (Jacobi) preconditioning in FP64 (V is symmetric positive definite,
+    eq. "laplace_system").  For matrices of more than 2^31 entries, where the
+    dense LAPACK factorisation of this environment does not apply (its
+    32-bit indexing fails on them); the products V p are taken in blocks of
+    `rows` rows.  Returns (x, rel_residual of the true residual, iterations).
+    The capacity of x then differs from the exact solution's by at most
+    ||x|| ||r|| / |b^T x| relative, to first order (4 pi (Cap* - Cap) =
+    x*^T r for symmetric V)."""
+    N = V.shape[0]
+
+    def mv(p):
+        y = np.empty(N)
+        for r0 in range(0, N, rows):
+            y[r0:r0 + rows] = V[r0:r0 + rows] @ p
+        return y
+
+    b = np.asarray(b, dtype=np.float64)
+    dinv = 1.0 / np.diag(V).copy()
+    x = np.zeros(N)
+    r = b.copy()
+    z = dinv * r
+    p = z.copy()
+    rz = r @ z
+    bn = np.linalg.norm(b)
+    for k in range(1, max_iter + 1):
+        q = mv(p)
+        pq = p @ q
+        if not pq > 0.0:
+            raise np.linalg.LinAlgError("p^T V p <= 0: V is not positive definite")
+        alpha = rz / pq
+        x += alpha * p
+        r -= alpha * q
+        if np.linalg.norm(r) <= 0.5 * rtol * bn:
+            rt = b - mv(x)  # the true residual decides
+            if np.linalg.norm(rt) <= rtol * bn:
+                return x, float(np.linalg.norm(rt) / bn), k
+            r = rt
+        z = dinv * r
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    raise np.linalg.LinAlgError("CG did not reach the tolerance")
+
+
 def capacity(x, area):
     """Cap = (1 / 4 pi) sum_i x_i |T_i| (eq. "cap:ell"; 4 pi Cap_l = 1 . x
     in the proof of the capacity proposition), summed with math.fsum."""

@@ -5,7 +5,8 @@ with the hypersingular operator", eq. "zz:T").
 
 Plain NumPy in FP64, written from the definitions:
 
-* the barycentric refinement (from ``synth``: topology and midpoints only);
+* the barycentric refinement, built here triangle by triangle (the GPU side
+  takes it from ``synth``; tests compare the two);
 * V_bary, the P0 Galerkin matrix of the single-layer operator on the
   barycentric mesh (the same ``assemble`` as the primal path);
 * P, the 6N x M matrix that writes the dual-cell indicator chi_j^dual as the
@@ -36,11 +37,33 @@ FOUR_PI = 4.0 * math.pi
 
 def barycentric_mesh(verts, tris):
     """(bary verts, bary tris, parent, owner) of the barycentric refinement
-    (Section 2.1, Fig. "dual_element")."""
-    import synth
-
-    mesh, parent, owner = synth.barycentric(verts, tris)
-    return mesh.verts, mesh.tris, parent, owner
+    (Section 2.1, Fig. "dual_element"): each triangle (v0, v1, v2) is cut by
+    its medians into six sons, in the order (v0, m01, c), (m01, v1, c),
+    (v1, m12, c), (m12, v2, c), (v2, m20, c), (m20, v0, c) (c the centre of
+    gravity, m the edge midpoints); son 6t + s lies in the dual cell of the
+    vertex it contains (owner).  New vertices: one midpoint per edge, edges
+    numbered by increasing (min, max) vertex pair, then one centre per
+    triangle in triangle order."""
+    verts = [tuple(map(float, p)) for p in np.asarray(verts, dtype=np.float64)]
+    tris = [tuple(map(int, t)) for t in np.asarray(tris)]
+    M = len(verts)
+    edges = sorted({(min(a, b), max(a, b)) for t in tris for a, b in ((t[0], t[1]), (t[1], t[2]), (t[2], t[0]))})
+    mid = {e: M + k for k, e in enumerate(edges)}
+    bverts = list(verts)
+    for (a, b) in edges:
+        bverts.append(tuple(0.5 * (verts[a][c] + verts[b][c]) for c in range(3)))
+    sons, parent, owner = [], [], []
+    for t, (v0, v1, v2) in enumerate(tris):
+        c = M + len(edges) + t
+        bverts.append(tuple((verts[v0][k] + verts[v1][k] + verts[v2][k]) / 3.0 for k in range(3)))
+        m01, m12, m20 = mid[(min(v0, v1), max(v0, v1))], mid[(min(v1, v2), max(v1, v2))], mid[(min(v2, v0), max(v2, v0))]
+        for son, own in (((v0, m01, c), v0), ((m01, v1, c), v1), ((v1, m12, c), v1), ((m12, v2, c), v2),
+                         ((v2, m20, c), v2), ((m20, v0, c), v0)):
+            sons.append(son)
+            parent.append(t)
+            owner.append(own)
+    return (np.array(bverts, dtype=np.float64), np.array(sons, dtype=np.int32), np.array(parent, dtype=np.int32),
+            np.array(owner, dtype=np.int32))
 
 
 def prolongation(owner, M):

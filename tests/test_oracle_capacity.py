@@ -168,3 +168,21 @@ def test_mesh_check_cases():
     v[3, 1] = np.nan
     assert not oracle.mesh_check(v, m.tris)[0]
     assert not oracle.mesh_check(m.verts, m.tris[:-1])[0]  # open surface
+
+
+def test_cg_solve_matches_cholesky():
+    """The oracle's CG solve (for matrices of more than 2^31 entries) reaches
+    the Cholesky solution: capacities within 1e-14, the solution within
+    1e-12 of its largest entry, and the reported bound on the capacity's
+    error holds."""
+    for m in (synth.cube(8), synth.voxel_union(3, 0.4, 21), synth.icosphere(3, 1.0)):
+        V = oracle.assemble(m.verts, m.tris)
+        b = oracle.rhs(m.verts, m.tris)
+        x1 = oracle.solve_direct(V, b)
+        x2, rr, its = oracle.solve_cg(V, b, rows=100)
+        assert rr <= 1e-14 and its > 1
+        c1, c2 = oracle.capacity(x1, b), oracle.capacity(x2, b)
+        assert abs(c1 - c2) <= 1e-14 * c1
+        assert np.max(np.abs(x1 - x2)) <= 1e-12 * np.max(np.abs(x1))
+        r = b - V @ x2
+        assert abs(c1 - c2) / c1 <= 2 * np.linalg.norm(x2) * np.linalg.norm(r) / abs(b @ x2) + 1e-16

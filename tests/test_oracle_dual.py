@@ -61,6 +61,23 @@ def test_barycentric_refinement():
         assert all(owner[k] in m.tris[parent[k]] for k in range(bt.shape[0]))
 
 
+def test_barycentric_generator_matches_oracle():
+    """The GPU side takes the barycentric mesh from synth.barycentric
+    (vectorised); the oracle builds it triangle by triangle from the
+    definition.  Vertices, sons, parents and owners agree bitwise, and each
+    son has its parent's orientation (the same normal direction)."""
+    for m in (synth.cube12(), synth.fichera48(), synth.voxel_union(3, 0.4, 21), synth.convex_hull(17, 5)):
+        bv, bt, parent, owner = dual.barycentric_mesh(m.verts, m.tris)
+        sm, spar, sown = synth.barycentric(m.verts, m.tris)
+        assert np.array_equal(bv, sm.verts) and np.array_equal(bt, sm.tris)
+        assert np.array_equal(parent, spar) and np.array_equal(owner, sown)
+        P = bv[bt]
+        n_son = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
+        Q = np.asarray(m.verts)[np.asarray(m.tris)][parent]
+        n_par = np.cross(Q[:, 1] - Q[:, 0], Q[:, 2] - Q[:, 0])
+        assert np.all(np.einsum("ij,ij->i", n_son, n_par) > 0)
+
+
 def test_dual_cells_tile_the_surface():
     m = synth.voxel_union(2, 0.4, 7)
     f = dual.dual_load(m.verts, m.tris)
