@@ -125,6 +125,21 @@ def cpu_baseline(mesh, seconds_target: float = 15.0):
     oracle.solve_direct(S, np.ones(n_chol))
     t_chol = (time.perf_counter() - t0) * (N / n_chol) ** 3
     total = t_assemble + t_chol
+    cpu_model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+
+        blas = [{"api": d.get("internal_api"), "threads": d.get("num_threads")} for d in threadpool_info()
+                if d.get("user_api") == "blas"]
+    except Exception:
+        blas = []
     return {
         "value": 1.0 / total,
         "unit": "solves/s",
@@ -136,6 +151,9 @@ def cpu_baseline(mesh, seconds_target: float = 15.0):
                    f"{t_chol:.0f} s"),
         "est_assemble_s": t_assemble,
         "est_cholesky_s": t_chol,
+        "cpu_model": cpu_model,
+        "host_cpus": os.cpu_count(),
+        "blas": blas,
     }
 
 
@@ -174,16 +192,15 @@ def half_matrix_bytes(N: int, elem: int) -> int:
     return total * elem
 
 
-def far_point_pairs(verts, tris, low: bool) -> float:
-    """Point pairs the far-field kernels evaluate for one assembly: 256 per
-    unique pair, and 49 (Radon's 7-point rule on both triangles) in tiles of
-    64-element blocks whose vertex boxes are at least 8 largest element
-    diameters apart when that rule is on (mixed precision,
-    bc_assembly_opts.far_low)."""
+def far_pair_classes(verts, tris, low: bool) -> dict:
+    """Unique element pairs i <= j of the far-field kernels by tile class,
+    from the 64-element blocks' vertex boxes (as bc_prepare classifies the
+    tiles): "vector" (diagonal tiles and tiles closer than 4 largest element
+    diameters: k_far32 on the vector ALU, 16 x 16 points), "mfma16" (at
+    least 4 diameters apart: k_far32m, -r^2 on the matrix cores, 16 x 16
+    points) and "mfma7" (at least 8 diameters apart with Radon's 7-point
+    rule on, far_low: 7 x 7 points)."""
     N = len(tris)
-    total = N * (N + 1) / 2 * POINT_PAIRS_PER_PAIR
-    if not low:
-        return total
     P = np.asarray(verts)[np.asarray(tris)]  # N x 3 corners x 3 coordinates
     d2 = np.max(np.sum((P[:, [1, 2, 0]] - P) ** 2, axis=2), axis=1)
     nb = (N + 63) // 64
@@ -192,10 +209,26 @@ def far_point_pairs(verts, tris, low: bool) -> float:
     bd2 = np.array([d2[64 * b: 64 * b + 64].max() for b in range(nb)])
     cnt = np.array([min(64, N - 64 * b) for b in range(nb)], dtype=np.float64)
     gap = np.maximum(0.0, np.maximum(lo[:, None, :] - hi[None, :, :], lo[None, :, :] - hi[:, None, :]))
-    far = (np.sum(gap ** 2, axis=2) >= 64.0 * np.maximum(bd2[:, None], bd2[None, :]))
-    far &= np.triu(np.ones((nb, nb), dtype=bool), 1)
-    low_pairs = float((cnt[:, None] * cnt[None, :])[far].sum())
-    return total - low_pairs * (POINT_PAIRS_PER_PAIR - 49)
+    g2 = np.sum(gap ** 2, axis=2)
+    dm = np.maximum(bd2[:, None], bd2[None, :])
+    upper = np.triu(np.ones((nb, nb), dtype=bool), 1)
+    pairs = cnt[:, None] * cnt[None, :]
+    sep = (g2 >= 16.0 * dm) & upper
+    dist = (g2 >= 64.0 * dm) & upper if low else np.zeros_like(sep)
+    total = N * (N + 1) / 2
+    m7 = float(pairs[dist].sum())
+    m16 = float(pairs[sep & ~dist].sum())
+    return {"vector": total - m7 - m16, "mfma16": m16, "mfma7": m7}
+
+
+def far_point_pairs(verts, tris, low: bool) -> float:
+    """Point pairs the far-field kernels evaluate for one assembly: 256 per
+    unique pair, and 49 (Radon's 7-point rule on both triangles) in tiles of
+    64-element blocks whose vertex boxes are at least 8 largest element
+    diameters apart when that rule is on (mixed precision,
+    bc_assembly_opts.far_low)."""
+    c = far_pair_classes(verts, tris, low)
+    return (c["vector"] + c["mfma16"]) * POINT_PAIRS_PER_PAIR + c["mfma7"] * 49
 
 
 def pct(xs, q):
@@ -206,47 +239,72 @@ def _build_request_mesh(req):
     return req.build_mesh()
 
 
-def serve_mode(a):
-    """Serving workload: 512 seeded requests (voxel unions, convex hulls,
-    boxes; N log-uniform in [500, 30000]).  Saturated run (all at t = 0) for
-    the closed-loop rate, then Poisson arrivals at 0.8 x that rate, for the
-    mixed and the FP64 GPU forms."""
+def serving_leg(n_requests: int, precisions=("mixed", "fp64"), cap_rtol: float = 1e-8, policy: str = "rr",
+                pipeline: int = 2, loads=(0.8, 0.5), log_fn=None) -> dict:
+    """The serving workload on `n_requests` seeded requests (seed 5: voxel
+    unions, convex hulls, boxes; N log-uniform in [500, 30000]): a saturated
+    run (all requests at t = 0) for the closed-loop rate, then Poisson
+    arrivals at `loads` x that rate (0.8 first), per precision; latency from
+    arrival (mesh built) to Cap on the host, with its split into queueing,
+    set-up and assembly, waiting and solving."""
     import concurrent.futures as cf
     import multiprocessing as mp
 
     import synth
 
-    reqs = synth.request_stream(a.requests, seed=5, rate=float("inf"))
+    reqs = synth.request_stream(n_requests, seed=5, rate=float("inf"))
     t0 = time.perf_counter()
     with cf.ProcessPoolExecutor(min(os.cpu_count() or 1, 16), mp_context=mp.get_context("fork")) as ex:
         meshes = list(ex.map(_build_request_mesh, reqs, chunksize=4))
-    log(f"built {len(meshes)} request meshes in {time.perf_counter() - t0:.1f} s "
-        f"(N {min(m.N for m in meshes)}..{max(m.N for m in meshes)})")
+    if log_fn:
+        log_fn(f"built {len(meshes)} request meshes in {time.perf_counter() - t0:.1f} s "
+               f"(N {min(m.N for m in meshes)}..{max(m.N for m in meshes)})")
     import torch
 
     from paper_1901_08393_amd.serve import CapacityServer, summarize
 
-    torch.cuda.set_device(0)
-    out = {"mode": "serve", "requests": len(reqs), "seed": 5}
+    out = {"requests": len(reqs), "seed": 5, "policy": policy, "chunks_in_flight": pipeline,
+           "N_range": [min(m.N for m in meshes), max(m.N for m in meshes)]}
     caps = {}
-    for prec in ("mixed", "fp64"):
+    for prec in precisions:
         # the mixed form at the capacity tolerance; the FP64 form at its tight default, the reference
-        srv = CapacityServer(prec, solve_opts={"cap_rtol": a.cap_rtol} if prec == "mixed" else None)
+        srv = CapacityServer(prec, solve_opts={"cap_rtol": cap_rtol} if prec == "mixed" else None, policy=policy,
+                             pipeline=pipeline)
         srv.run(reqs[:8], meshes[:8], realtime=False)  # warm-up
         recs = srv.run(reqs, meshes, realtime=False)
         sat = summarize(recs)
-        rate = 0.8 * sat["solves_per_s"]
-        preqs = synth.request_stream(a.requests, seed=5, rate=rate)
-        precs = srv.run(preqs, meshes, realtime=True)
-        poi = summarize(precs)
-        caps[prec] = np.array([r.cap for r in precs])
-        out[prec] = {"saturated": sat, "poisson": dict(poi, rate=rate)}
-        log(f"{prec}: saturated {sat['solves_per_s']:.1f} solves/s; poisson p50 {poi['p50_ms']:.1f} ms "
-            f"p99 {poi['p99_ms']:.1f} ms")
+        out[prec] = {"saturated": sat}
+        for load in loads:
+            rate = load * sat["solves_per_s"]
+            preqs = synth.request_stream(n_requests, seed=5, rate=rate)
+            precs = srv.run(preqs, meshes, realtime=True)
+            poi = summarize(precs)
+            key = "poisson" if load == loads[0] else f"poisson_load{load:g}"
+            out[prec][key] = dict(poi, rate=rate, load=load)
+            if load == loads[0]:
+                caps[prec] = np.array([r.cap for r in precs])
+            if log_fn:
+                log_fn(f"{prec}: saturated {sat['solves_per_s']:.1f} solves/s; poisson at {load:g} x: p50 "
+                       f"{poi['p50_ms']:.1f} ms p99 {poi['p99_ms']:.1f} ms")
         del srv
         torch.cuda.empty_cache()
-    rel = np.abs(caps["mixed"] - caps["fp64"]) / caps["fp64"]
-    out["cap_rel_err_mixed_vs_fp64"] = {"max": float(rel.max()), "median": float(np.median(rel))}
+    if "mixed" in caps and "fp64" in caps:
+        rel = np.abs(caps["mixed"] - caps["fp64"]) / caps["fp64"]
+        out["cap_rel_err_mixed_vs_fp64"] = {"max": float(rel.max()), "median": float(np.median(rel))}
+    return out
+
+
+def serve_mode(a):
+    """Serving workload: 512 seeded requests (voxel unions, convex hulls,
+    boxes; N log-uniform in [500, 30000]).  Saturated run (all at t = 0) for
+    the closed-loop rate, then Poisson arrivals at 0.8 x that rate, for the
+    mixed and the FP64 GPU forms."""
+    import torch
+
+    torch.cuda.set_device(0)
+    out = {"mode": "serve"}
+    out.update(serving_leg(a.requests, cap_rtol=a.cap_rtol, policy=a.serve_policy, pipeline=a.serve_pipeline,
+                           log_fn=log))
     print(json.dumps(out))
 
 
@@ -490,6 +548,96 @@ def mixed60k_mode(a):
                       "matrix_gb_fp32": p32.matrix_bytes() / 1e9}))
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden", "full_size.json")
+
+
+def golden(name: str):
+    """The FP64 oracle's stored result for a full-size workload (written by
+    tests/golden/make_full_size.py from the oracle alone), or None."""
+    try:
+        return json.load(open(GOLDEN)).get(name)
+    except Exception:
+        return None
+
+
+def mesh_sha(verts, tris) -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(verts, dtype=np.float64).tobytes())
+    h.update(np.ascontiguousarray(tris, dtype=np.int32).tobytes())
+    return h.hexdigest()[:16]
+
+
+def voxel_60k_mesh():
+    """Config 4's mesh: the voxel union of 26 unit voxels (seed 4), NVB
+    refined uniformly and then by bisection of its largest elements until
+    N >= 60000 (the recipe of the stored oracle result)."""
+    import synth
+
+    m = synth.voxel_union(4, 0.4, 4)
+    t0 = synth.init_reference_edges(m.verts, m.tris)
+    return synth.refine_to_size(m.verts, t0, 60000)
+
+
+def timed(torch, fn, reps: int = 1):
+    """(result of the last call, mean ms per call) with events on the current stream."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        r = fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return r, e0.elapsed_time(e1) / reps
+
+
+def mixed_60k_leg(torch) -> dict:
+    """Config 4 at N = 60000: the FP64 form (28.8 GB matrix, residual 1e-12)
+    and the mixed form (14.4 GB) solved to the capacity tolerances 1e-6,
+    1e-8 and 1e-10, each capacity against the stored FP64 oracle result;
+    times of assembly and solve; the standalone product on the FP32
+    matrix."""
+    from paper_1901_08393_amd import api
+
+    v, t = voxel_60k_mesh()
+    g = golden("voxel_60k")
+    out = {"workload": "voxel union (seed 4) refined to N = 60000 (config 4)", "N": int(len(t))}
+    ref = g["cap"] if g is not None and g.get("mesh_sha") == mesh_sha(v, t) else None
+    out["oracle_cap"] = ref
+    p = api.CapacityProblem(v, t, "fp64")
+    p.allocate()
+    _, asm64 = timed(torch, p.assemble)
+    r64, sol64 = timed(torch, lambda: p.solve())
+    out["fp64"] = {"assemble_ms": round(asm64, 2), "solve_ms": round(sol64, 2), "iters": r64.iters, "cap": r64.cap,
+                   "matrix_gb": round(p.matrix_bytes() / 1e9, 2),
+                   "cap_rel_err_vs_oracle": abs(r64.cap - ref) / ref if ref else None}
+    p.release_matrix()
+    del p
+    torch.cuda.empty_cache()
+    q = api.CapacityProblem(v, t, "mixed")
+    q.allocate()
+    _, asm32 = timed(torch, q.assemble)
+    rows = []
+    for tol in (1e-6, 1e-8, 1e-10):
+        r, ms = timed(torch, lambda: q.solve(rtol=0.0, cap_rtol=tol))
+        rows.append({"cap_rtol": tol, "solve_ms": round(ms, 2), "iters": r.iters, "outer": r.outer, "cap": r.cap,
+                     "cap_bound": r.cap_bound,
+                     "cap_rel_err_vs_oracle": abs(r.cap - ref) / ref if ref else None,
+                     "cap_rel_err_vs_fp64_gpu": abs(r.cap - r64.cap) / r64.cap})
+    xv = torch.randn(q.N, dtype=torch.float32, device="cuda")
+    api.matvec(q, xv)
+    _, mv_ms = timed(torch, lambda: api.matvec(q, xv), reps=10)
+    mv_gbs = half_matrix_bytes(q.N, 4) / (mv_ms * 1e-3) / 1e9
+    out["mixed"] = {"assemble_ms": round(asm32, 2), "matrix_gb": round(q.matrix_bytes() / 1e9, 2), "solves": rows,
+                    "matvec_standalone": {"ms": round(mv_ms, 3), "gbs": round(mv_gbs, 1),
+                                          "frac_of_hbm_peak": round(mv_gbs / HBM_PEAK_GBS, 4)}}
+    q.release_matrix()
+    del q, xv
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -503,8 +651,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-dual", action="store_true", help="skip the Algorithm 1 (dual mode) summary")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=128, help="requests of the serving leg")
+    ap.add_argument("--no-60k", action="store_true", help="skip the N = 60000 leg (config 4)")
     ap.add_argument("--serve", action="store_true", help="serving workload instead of the sphere")
     ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--serve-policy", default="rr", choices=["rr", "srpt"],
+                    help="serving: round robin (rr) or the least remaining work first (srpt)")
+    ap.add_argument("--serve-pipeline", type=int, default=2, help="serving: solver chunks kept in flight")
     ap.add_argument("--adaptive", action="store_true", help="adaptive voxel-union workload (FP64 path)")
     ap.add_argument("--adaptive-mixed", action="store_true", help="run the adaptive workload in mixed precision")
     ap.add_argument("--mixed60k", action="store_true", help="mixed vs FP64 at N >= 60000")
@@ -601,6 +755,24 @@ def main():
     if a.precision == "mixed":
         roof_asm["peak_unpacked"] = FP32_UNPACKED_PEAK
         roof_asm["frac_unpacked"] = round(asm_tflops / FP32_UNPACKED_PEAK, 4)
+        # on separated tiles the 8 flops of -r^2 (3 differences, 5 for the
+        # square) are one matrix-core product per point pair
+        # (v_mfma_f32_16x16x4f32: 16 x 16 x 4 x 2 flops for 256 point pairs);
+        # the inverse square root and the weighted sums stay on the vector ALU
+        cls = far_pair_classes(mesh.verts, mesh.tris, bool(prob.opts.far_low))
+        pp_vec = cls["vector"] * POINT_PAIRS_PER_PAIR
+        pp_mm = cls["mfma16"] * POINT_PAIRS_PER_PAIR + cls["mfma7"] * 49
+        vec_flops = pp_vec * FLOPS_PER_POINT_PAIR + pp_mm * 3
+        mm_flops = pp_mm * 8
+        sec = mean("assemble_ms") * 1e-3
+        roof_asm["split"] = {
+            "pairs_by_tile_class": {k: int(v) for k, v in cls.items()},
+            "vector_tflops": round(vec_flops / sec / 1e12, 2),
+            "vector_frac_of_157.3": round(vec_flops / sec / 1e12 / FP32_VECTOR_PEAK, 4),
+            "matrix_core_tflops": round(mm_flops / sec / 1e12, 2),
+            "matrix_core_frac_of_157.3": round(mm_flops / sec / 1e12 / FP32_VECTOR_PEAK, 4),
+            "note": "flops by the 11-per-point-pair convention; on matrix-core tiles 8 of them are MFMA flops",
+        }
     dominant = roof_solve if mean("solve_ms") >= mean("assemble_ms") else roof_asm
     other = roof_asm if dominant is roof_solve else roof_solve
 
@@ -620,8 +792,10 @@ def main():
         "config": {"workload": f"sphere r={radius:.6f} (seed 2) as icosphere L{a.level}, N={N}, "
                                f"{a.precision} precision, Cap to rel {a.cap_rtol:g}",
                    "N": N, "precision": a.precision, "far_order": 4, "ss_order": 4, "cap_rtol": a.cap_rtol},
-        "latency_ms": {"p50": round(pct([r["step_ms"] for r in recs], 50), 3),
-                       "p99": round(pct([r["step_ms"] for r in recs], 99), 3)},
+        "step_latency_ms": {"p50": round(pct([r["step_ms"] for r in recs], 50), 3),
+                            "p99": round(pct([r["step_ms"] for r in recs], 99), 3),
+                            "note": "over the timed back-to-back steps on one mesh; the latency distribution "
+                                    "under load is in serving"},
         "phases_ms": {k: round(mean(k), 4) for k in ("prepare_ms", "assemble_ms", "solve_ms", "zz_ms")},
         "assembly_gpairs_per_s": round(asm_gpairs, 3),
         "matvec_gbs": round(solve_gbs, 1),
@@ -674,6 +848,47 @@ def main():
     if not a.no_dual:
         log("Algorithm 1 (dual mode) on the unit cube of Table 1 ...")
         out["algorithm1_dual"] = dual_summary()
+
+    # the headline capacity against the FP64 oracle's (stored result, same mesh)
+    g = golden("sphere_L5")
+    if g is not None and g.get("mesh_sha") == mesh_sha(mesh.verts, mesh.tris):
+        out["oracle_cap"] = g["cap"]
+        out["cap_rel_err_vs_oracle"] = abs(res.cap - g["cap"]) / g["cap"]
+        out["cap_target_met_vs_oracle"] = bool(out["cap_rel_err_vs_oracle"] <= (1e-8 if a.precision == "mixed"
+                                                                              else 1e-12))
+
+    if a.precision == "mixed":
+        # the 4 x 4 rule everywhere (no Radon rule on distant tiles), same mesh
+        p44 = api.CapacityProblem(mesh.verts, mesh.tris, "mixed", far_low=False)
+        p44.allocate()
+        p44.assemble()
+        _, ms44 = timed(torch, p44.assemble, reps=3)
+        r44 = p44.solve(cap_rtol=a.cap_rtol)
+        out["assembly_4x4_everywhere"] = {
+            "assemble_ms": round(ms44, 3), "gpairs_per_s": round(pairs / (ms44 * 1e-3) / 1e9, 3),
+            "tflops": round(pairs * POINT_PAIRS_PER_PAIR * FLOPS_PER_POINT_PAIR / (ms44 * 1e-3) / 1e12, 2),
+            "cap": r44.cap, "cap_rel_err_vs_radon_rule_run": abs(r44.cap - res.cap) / res.cap}
+        del p44
+        torch.cuda.empty_cache()
+
+    # the weighted-residual estimator of Appendix A on the headline solution (FP64)
+    prob.residual()
+    mu2, ms_mu = timed(torch, prob.residual, reps=3)
+    pp_mu = float(N) * N * POINT_PAIRS_PER_PAIR
+    out["residual_estimator"] = {
+        "kernel": "bc_residual_indicators (k_res_far + k_res_touch + k_res_finish), FP64",
+        "ms": round(ms_mu, 3), "mu2_sum": float(mu2.sum().item()),
+        "point_pairs": pp_mu, "tflops_11_flop_convention": round(pp_mu * FLOPS_PER_POINT_PAIR / (ms_mu * 1e-3) / 1e12, 2),
+        "frac_of_fp64_peak": round(pp_mu * FLOPS_PER_POINT_PAIR / (ms_mu * 1e-3) / 1e12 / FP64_VECTOR_PEAK, 4)}
+
+    if not a.no_serve:
+        log(f"serving leg ({a.serve_requests} requests) ...")
+        out["serving"] = serving_leg(a.serve_requests, cap_rtol=a.cap_rtol, policy=a.serve_policy,
+                                     pipeline=a.serve_pipeline, log_fn=log)
+
+    if not a.no_60k:
+        log("config 4: N = 60000, FP64 and mixed against the oracle ...")
+        out["mixed_60k"] = mixed_60k_leg(torch)
 
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample) ...")

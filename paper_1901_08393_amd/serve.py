@@ -7,17 +7,22 @@ resident in HBM and works on many of them at once:
 * admission: FIFO, while the sum of the admitted requests' footprints
   (N x ld matrix plus geometry, pattern and solver workspaces) stays within
   the memory budget (free HBM, at most 288 GB); a request that can never fit
-  is rejected;
-* assembly: geometry, classification and the dense matrix of each admitted
-  request are built on an assembly stream, overlapping the solves;
+  is rejected.  Several requests are admitted per loop pass (up to
+  `admit_ms` of host time);
+* set-up and assembly: geometry and classification (bc_prepare, which waits
+  for its own stream) on a set-up stream, then the dense matrix on an
+  assembly stream, overlapping the solves;
 * solving: assembled systems join the next cooperative solver launch on the
   solve stream.  A launch ("chunk") packs systems up to the number of
-  co-resident workgroups; each system gets a bound on its matrix products
-  sized so that a chunk streams about `chunk_ms` of HBM traffic.  Between
-  chunks finished systems retire (their memory is released and their Cap is
-  reported), unfinished ones resume bitwise where they stopped, and newly
-  assembled ones start.  A system's arithmetic depends only on its own N, so
-  every result is the same alone and in the mix.
+  co-resident workgroups, in the order of the scheduling policy (round
+  robin by default, or the least remaining work first); each system gets a bound on its matrix
+  products sized so that a chunk streams about `chunk_ms` of HBM traffic.
+  Two chunks are kept in flight, so that the GPU does not wait for the host
+  between them.  As chunks complete, finished systems retire (their memory
+  is released and their Cap is reported), unfinished ones resume bitwise
+  where they stopped, and newly assembled ones start.  A system's arithmetic
+  depends only on its own N, so every result is the same alone and in the
+  mix.
 
 Latency of a request = from its arrival (mesh already built) to its Cap
 being available on the host.
@@ -62,17 +67,33 @@ class Record:
 
 
 class _Live:
-    __slots__ = ("rec", "prob", "event", "foot", "started", "G")
+    __slots__ = ("rec", "prob", "event", "foot", "started", "G", "finished", "products")
 
     def __init__(self, rec, prob, event, foot, G):
         self.rec, self.prob, self.event, self.foot, self.G = rec, prob, event, foot, G
         self.started = False
+        self.finished = False
+        self.products = 0  # matrix products granted so far (budgets of launched chunks)
 
 
 class CapacityServer:
+    """policy: order in which ready systems are packed into a chunk.
+    "rr" serves them round robin (a system that took part in a chunk goes to
+    the back); "srpt" takes the least remaining work first, estimated as
+    N ld (expected products - products granted so far).  pipeline: chunks
+    kept in flight on the solve stream (2: the next chunk is queued while
+    the current one runs, so the host's retire-and-launch turnaround does not
+    leave the GPU idle; a system that finished in the running chunk is a
+    no-op in the queued one).  admit_ms: host time one loop pass may spend
+    admitting requests (each admission runs bc_prepare, which waits for its
+    own stream)."""
+
     def __init__(self, precision: str = "mixed", budget_bytes: Optional[float] = None, chunk_ms: float = 2.0,
                  stream_gbs: float = 5000.0, device: str = "cuda", solve_opts: Optional[dict] = None,
-                 keep_sigma: bool = False):
+                 keep_sigma: bool = False, policy: str = "rr", pipeline: int = 2, admit_ms: float = 1.0,
+                 expected_products: int = 60):
+        if policy not in ("rr", "srpt"):
+            raise ValueError("policy: 'rr' or 'srpt'")
         self.precision = precision
         self.prec = 0 if precision == "fp64" else 1
         self.device = torch.device(device)
@@ -84,10 +105,20 @@ class CapacityServer:
             raise RuntimeError("bc_solve_capacity: no co-resident solver workgroups")
         self.chunk_ms = chunk_ms
         self.stream_gbs = stream_gbs
+        self.prep_stream = torch.cuda.Stream(self.device)
         self.asm_stream = torch.cuda.Stream(self.device)
         self.solve_stream = torch.cuda.Stream(self.device)
         self.solve_opts = solve_opts or {}
         self.keep_sigma = keep_sigma
+        self.policy = policy
+        self.pipeline = max(1, int(pipeline))
+        self.admit_ms = admit_ms
+        self.expected_products = expected_products
+        # pinned host slots for the results of the chunks in flight (one
+        # system per workgroup at most)
+        rs = ctypes_sizeof_result()
+        self._pinned = [torch.empty((self.capacity_wg, rs), dtype=torch.uint8, pin_memory=True)
+                        for _ in range(self.pipeline)]
 
     # ------------------------------------------------------------- sizes
     def footprint(self, N: int) -> int:
@@ -100,19 +131,41 @@ class CapacityServer:
         per = elem * N * lib().bc_matrix_ld(N)
         return max(2, int(self.chunk_ms * 1e-3 * self.stream_gbs * 1e9 / per))
 
+    def _remaining(self, lv: "_Live") -> float:
+        return float(lv.rec.N) * float(lv.rec.N) * max(1, self.expected_products - lv.products)
+
+    def _admit(self, rec: "Record", mesh, foot: int, G: int, t0: float) -> "_Live":
+        rec.admitted = time.perf_counter() - t0
+        # bc_prepare waits for its stream: its own stream, so that it does not
+        # wait for queued assemblies; the assembly follows on the assembly
+        # stream (prepare has completed when the constructor returns)
+        with torch.cuda.stream(self.prep_stream):
+            prob = CapacityProblem(mesh.verts, mesh.tris, self.precision, device=str(self.device),
+                                   stream=self.prep_stream)
+        for tns in (prob.d_verts, prob.d_tris, prob.mesh_ws, prob.pattern, prob.area, prob.sigma, prob.result_buf):
+            tns.record_stream(self.asm_stream)
+        with torch.cuda.stream(self.asm_stream):
+            prob.assemble(stream=self.asm_stream)
+            prob._ensure_solve_ws()
+            ev = torch.cuda.Event()
+            ev.record(self.asm_stream)
+        return _Live(rec, prob, ev, foot, G)
+
     # --------------------------------------------------------------- run
     def run(self, requests, meshes, realtime: bool = True) -> List[Record]:
         """Serve `requests` (objects with rid, arrival, kind) whose meshes
         are meshes[k] (objects with verts, tris).  realtime=False treats
         every request as arrived at t = 0."""
         L = lib()
+        rsize = ctypes_sizeof_result()
         order = sorted(range(len(requests)), key=lambda k: (requests[k].arrival if realtime else 0.0, k))
         recs = [Record(requests[k].rid, int(meshes[k].tris.shape[0]), requests[k].kind,
                        requests[k].arrival if realtime else 0.0) for k in range(len(requests))]
         waiting = collections.deque()
         assembling: List[_Live] = []
         ready: List[_Live] = []  # assembled or running, in service order
-        inflight = None
+        inflight = collections.deque()  # (batch, event, scratch, slot)
+        slot_free = list(range(self.pipeline))
         used = 0
         nxt = 0
         n_done = 0
@@ -123,8 +176,9 @@ class CapacityServer:
                 waiting.append(order[nxt])
                 nxt += 1
             progressed = False
-            # admission (one per pass keeps the loop responsive)
-            if waiting:
+            # admission: FIFO, as long as memory allows and this pass's time lasts
+            ta = time.perf_counter()
+            while waiting and (time.perf_counter() - ta) * 1e3 < self.admit_ms:
                 k = waiting[0]
                 foot = self.footprint(recs[k].N)
                 G = int(L.bc_solve_workgroups(recs[k].N))
@@ -137,16 +191,10 @@ class CapacityServer:
                 elif used + foot <= self.budget:
                     waiting.popleft()
                     used += foot
-                    recs[k].admitted = time.perf_counter() - t0
-                    with torch.cuda.stream(self.asm_stream):
-                        prob = CapacityProblem(meshes[k].verts, meshes[k].tris, self.precision,
-                                               device=str(self.device), stream=self.asm_stream)
-                        prob.assemble(stream=self.asm_stream)
-                        prob._ensure_solve_ws()
-                        ev = torch.cuda.Event()
-                        ev.record(self.asm_stream)
-                    assembling.append(_Live(recs[k], prob, ev, foot, G))
+                    assembling.append(self._admit(recs[k], meshes[k], foot, G, t0))
                     progressed = True
+                else:
+                    break
             # assembly completion
             still = []
             for lv in assembling:
@@ -160,16 +208,18 @@ class CapacityServer:
                 else:
                     still.append(lv)
             assembling = still
-            # retire a finished chunk
-            if inflight is not None and inflight[1].query():
-                batch, _ev, _keep = inflight
-                with torch.cuda.stream(self.solve_stream):
-                    res = torch.stack([lv.prob.result_buf for lv in batch]).cpu().numpy()
+            # retire finished chunks, oldest first
+            while inflight and inflight[0][1].query():
+                batch, _ev, _keep, slot = inflight.popleft()
+                res = self._pinned[slot][: len(batch)].numpy()
                 tnow = time.perf_counter() - t0
                 for lv, row in zip(batch, res):
+                    if lv.finished:
+                        continue  # finished in an earlier chunk (a no-op in this one)
                     r = _lib.bc_result.from_buffer_copy(row.tobytes())
                     lv.rec.chunks += 1
                     if r.status != _lib.BC_RUNNING:
+                        lv.finished = True
                         lv.rec.done = tnow
                         lv.rec.cap, lv.rec.iters, lv.rec.outer = r.cap, r.iters, r.outer
                         lv.rec.status, lv.rec.rel_residual = r.status, r.rel_residual
@@ -179,51 +229,75 @@ class CapacityServer:
                         ready.remove(lv)
                         used -= lv.foot
                         n_done += 1
-                    else:
-                        # served systems go to the back of the queue
-                        ready.remove(lv)
-                        ready.append(lv)
-                inflight = None
+                slot_free.append(slot)
                 progressed = True
-            # launch the next chunk
-            if inflight is None and ready:
+            # launch chunks until `pipeline` are in flight
+            while len(inflight) < self.pipeline and ready and slot_free:
+                cand = ready if self.policy == "rr" else sorted(ready, key=self._remaining)
                 batch, wg = [], 0
-                for lv in ready:
+                for lv in cand:
                     if wg + lv.G <= self.capacity_wg:
                         batch.append(lv)
                         wg += lv.G
                 start = [0 if lv.started else 1 for lv in batch]
                 budgets = [self.product_budget(lv.rec.N) for lv in batch]
                 tnow = time.perf_counter() - t0
-                for lv in batch:
+                for lv, bdg in zip(batch, budgets):
+                    lv.products += bdg
                     if not lv.started:
                         lv.started = True
                         lv.rec.started = tnow
+                slot = slot_free.pop()
                 with torch.cuda.stream(self.solve_stream):
                     keep = solve_batched([lv.prob for lv in batch], self.precision, start=start, budgets=budgets,
                                          stream=self.solve_stream, **self.solve_opts)
+                    host = self._pinned[slot]
+                    for q, lv in enumerate(batch):
+                        host[q].copy_(lv.prob.result_buf, non_blocking=True)
                     ev = torch.cuda.Event()
                     ev.record(self.solve_stream)
-                inflight = (batch, ev, keep)
+                inflight.append((batch, ev, keep, slot))
                 progressed = True
+                if self.policy == "rr":
+                    for lv in batch:  # the queued chunk's systems yield to the others for the next one
+                        ready.remove(lv)
+                        ready.append(lv)
             if not progressed:
-                if nxt < len(order) and not waiting and not assembling and not ready and inflight is None:
+                if nxt < len(order) and not waiting and not assembling and not ready and not inflight:
                     wait = recs[order[nxt]].arrival - (time.perf_counter() - t0)
                     if wait > 0:
                         time.sleep(min(wait, 0.01))
                 else:
                     time.sleep(5e-5)
         torch.cuda.synchronize(self.device)
+        assert rsize == self._pinned[0].shape[1]
         return recs
 
 
+def ctypes_sizeof_result() -> int:
+    import ctypes
+
+    return ctypes.sizeof(_lib.bc_result)
+
+
 def summarize(recs: List[Record]) -> dict:
+    """Rate, latency percentiles, and the latency split into queueing
+    (arrival to admission), set-up and assembly (admission to assembled),
+    waiting for the first chunk and solving (first chunk to Cap on the
+    host), each as p50 / p99 over the requests; and the latency p99 of the
+    smallest and the largest half of the requests by N."""
     import numpy as np
 
     ok = [r for r in recs if r.status == _lib.BC_OK]
     lat = np.array([r.latency for r in ok]) * 1e3
     span = max(r.done for r in recs) - min(r.arrival for r in recs)
-    return {
+
+    def pp(x):
+        x = np.asarray(x) * 1e3
+        return {"p50": round(float(np.percentile(x, 50)), 3), "p99": round(float(np.percentile(x, 99)), 3)} \
+            if len(x) else {}
+
+    out = {
         "requests": len(recs),
         "ok": len(ok),
         "rejected": sum(1 for r in recs if r.status == _lib.BC_ENOMEM),
@@ -234,3 +308,18 @@ def summarize(recs: List[Record]) -> dict:
         "makespan_s": span,
         "mean_iters": float(np.mean([r.iters for r in ok])) if ok else float("nan"),
     }
+    if ok:
+        out["breakdown_ms"] = {
+            "queue": pp([r.admitted - r.arrival for r in ok]),
+            "setup_assembly": pp([r.assembled - r.admitted for r in ok]),
+            "wait_first_chunk": pp([r.started - r.assembled for r in ok]),
+            "solve": pp([r.done - r.started for r in ok]),
+        }
+        Ns = np.array([r.N for r in ok])
+        med = np.median(Ns)
+        small = lat[Ns <= med]
+        large = lat[Ns > med]
+        out["p99_ms_by_size"] = {"N<=median": float(np.percentile(small, 99)) if len(small) else None,
+                                 "N>median": float(np.percentile(large, 99)) if len(large) else None,
+                                 "median_N": float(med)}
+    return out

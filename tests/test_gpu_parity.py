@@ -233,6 +233,66 @@ def test_far_low_order_rule(api):
     assert 1.0 < cap_ref < 2.0
 
 
+def _block_classes(verts, tris):
+    """Tile class of every element pair from the 64-element blocks' vertex
+    boxes, as bc_prepare classifies the far-field tiles: 2 where the boxes
+    are at least 8 largest element diameters apart (Radon's rule), 1 at
+    least 4 apart, else 0; and the box distance in diameters per pair."""
+    P = np.asarray(verts)[np.asarray(tris)]
+    N = len(tris)
+    d2 = np.max(np.sum((P[:, [1, 2, 0]] - P) ** 2, axis=2), axis=1)
+    nb = (N + 63) // 64
+    lo = np.array([P[64 * b: 64 * b + 64].reshape(-1, 3).min(0) for b in range(nb)])
+    hi = np.array([P[64 * b: 64 * b + 64].reshape(-1, 3).max(0) for b in range(nb)])
+    bd2 = np.array([d2[64 * b: 64 * b + 64].max() for b in range(nb)])
+    gap = np.maximum(0.0, np.maximum(lo[:, None, :] - hi[None, :, :], lo[None, :, :] - hi[:, None, :]))
+    g2 = np.sum(gap ** 2, axis=2)
+    dm = np.maximum(bd2[:, None], bd2[None, :])
+    cls = np.where(g2 >= 64.0 * dm, 2, np.where(g2 >= 16.0 * dm, 1, 0))
+    np.fill_diagonal(cls, 0)
+    blk = np.arange(N) // 64
+    return cls[np.ix_(blk, blk)], np.sqrt(g2 / dm)[np.ix_(blk, blk)]
+
+
+def test_far_low_order_rule_at_threshold(api):
+    """The same two spheres 4.7 radii apart: the closest block pairs across
+    the gap are between 8 and 8.5 largest element diameters apart, at the
+    distant class's threshold, where Radon's rule has its largest error.
+    Entries of distant tiles against the oracle's 7-point and 4 x 4 entries,
+    the other cross entries against its 4 x 4 entries: FP32 rounding (4e-6
+    each) and no bias (mean 2e-9); the capacity within 1e-8 of the oracle's
+    4 x 4 capacity."""
+    _flush("far low-order rule at 8 diameters (two spheres 4.7 apart)")
+    verts, tris = _two_spheres(4.7)
+    N = tris.shape[0]
+    half = N // 2
+    cls, dist = _block_classes(verts, tris)
+    cross = np.s_[:half, half:]
+    c_cross, d_cross = cls[cross], dist[cross]
+    assert (c_cross == 2).any()
+    near_far = d_cross[c_cross == 2].min()
+    assert 8.0 <= near_far <= 8.5, near_far
+    ref4 = oracle.assemble(verts, tris, 4, 4)
+    p = api.CapacityProblem(verts, tris, "mixed")
+    V32 = p.assemble()
+    torch.cuda.synchronize()
+    V32 = V32.cpu().numpy()[:, :N].astype(np.float64)
+    ref7 = _radon_cross(verts, tris, half)
+    got = V32[cross]
+    far = c_cross == 2
+    r7 = (got[far] - ref7[far]) / ref7[far]
+    r4 = (got - ref4[cross]) / ref4[cross]
+    _flush(f"  distant tiles ({far.sum()} entries, nearest at {near_far:.2f} diameters): vs Radon 7 max "
+           f"{np.abs(r7).max():.2e} mean {r7.mean():.2e}; all cross entries vs 4x4 max {np.abs(r4).max():.2e} "
+           f"mean {r4.mean():.2e}; distant vs 4x4 mean {r4[far].mean():.2e}")
+    for r in (r7, r4, r4[far]):
+        assert np.abs(r).max() <= 4e-6 and abs(r.mean()) <= 2e-9
+    b = oracle.rhs(verts, tris)
+    cap_ref = oracle.capacity(oracle.solve_direct(ref4, b), b)
+    r = p.solve()
+    assert r.ok and abs(r.cap - cap_ref) / cap_ref <= 1e-8, (r.cap, cap_ref)
+
+
 # ----------------------------------------------------------------- solves
 
 def _oracle_cap(name):
@@ -312,6 +372,13 @@ def test_capacity_tolerance_stop(api, name):
     rm = pm.solve(cap_rtol=1e-8)
     assert rm.ok and rm.cap_bound <= 1e-8 and rm.iters <= rm_tight.iters, (rm, rm_tight)
     assert abs(rm.cap - cap_ref) / cap_ref <= 1e-8
+    # mixed precision where the first inner solve's own capacity stop applies
+    # (0.3 cap_rtol above the inner tolerance): the FP32 CG with the bound
+    # estimated from its recurrence stops it, one FP64 residual confirms
+    re = pm.solve(rtol=0.0, inner_rtol=1e-7, cap_rtol=1e-6)
+    assert re.ok and re.outer == 2 and 0.0 < re.cap_bound <= 1e-6, re
+    assert re.iters < rm_tight.iters
+    assert abs(re.cap - cap_ref) / cap_ref <= re.cap_bound + 1e-8, (re, cap_ref)
 
 
 def test_capacity_reduction(api):
