@@ -213,8 +213,10 @@ def far_pair_classes(verts, tris, low: bool) -> dict:
     dm = np.maximum(bd2[:, None], bd2[None, :])
     upper = np.triu(np.ones((nb, nb), dtype=bool), 1)
     pairs = cnt[:, None] * cnt[None, :]
-    sep = (g2 >= 16.0 * dm) & upper
-    dist = (g2 >= 64.0 * dm) & upper if low else np.zeros_like(sep)
+    half_diag2 = np.sum((0.5 * (hi - lo)) ** 2, axis=1)
+    compact = half_diag2[None, :] <= 2.5 ** 2 * g2  # the column block against the gap
+    sep = (g2 >= 16.0 * dm) & upper & compact
+    dist = (g2 >= 64.0 * dm) & sep if low else np.zeros_like(sep)
     total = N * (N + 1) / 2
     m7 = float(pairs[dist].sum())
     m16 = float(pairs[sep & ~dist].sum())

@@ -127,6 +127,22 @@ typedef struct bc_assembly_opts {
                          |c_i - c_j|^2 < near_factor^2 max(diam_i, diam_j)^2
                          are computed in FP64 and corrected exactly; 0 = none.
                          Must be 0 for BC_FP64. */
+  /* Orders of the singular rules chosen per touching pair (0 = off; all
+   * zero gives ss_order everywhere).  ss_order is then the coincident
+   * pairs' order. */
+  int32_t ss_order_edge;   /* edge-adjacent pairs; 0: ss_order; 0..8 */
+  int32_t ss_order_vertex; /* vertex-adjacent pairs; 0: ss_order; 0..8 */
+  int32_t ss_order_sliver; /* > 0: at least this order for every touching
+                              pair with an element whose diam^2 exceeds
+                              sliver_ratio |T|.  The rules lose accuracy on
+                              thin elements: the coincident integral of a
+                              triangle with angles (10, 85, 85) degrees
+                              (diam^2/|T| = 11.5) is off by 2.4e-3 at order
+                              4 and 2.7e-5 at order 8; with angles
+                              (10, 10, 160) (22.7) by 8.7e-2 and 1.6e-2.
+                              0..8 */
+  int32_t reserved;        /* must be 0 */
+  double sliver_ratio;     /* > 0 when ss_order_sliver > 0 */
 } bc_assembly_opts;
 
 /* Sparse pattern produced by bc_prepare: every ordered pair (i, j) that

@@ -44,6 +44,7 @@ from .operator import (  # noqa: F401
     entry,
     assemble,
     assemble_rows,
+    SSOrders,
 )
 from .capacity import (  # noqa: F401
     rhs,

@@ -35,7 +35,7 @@ from concurrent.futures import ProcessPoolExecutor
 
 import numpy as np
 
-from .operator import classify_pairs, element_geometry, quad_points
+from .operator import SSOrders, _pair_order, classify_pairs, element_geometry, quad_points
 from .quadrature import ss_rule, triangle_rule
 
 FOUR_PI = 4.0 * math.pi
@@ -105,9 +105,10 @@ def touching_moments(verts, tris, p, q, kind, Tp, Tq, ss_order: int = 4):
     return mp, mq
 
 
-def p1_moments(verts, tris, sigma, far_order: int = 4, ss_order: int = 4, workers: int | None = None):
+def p1_moments(verts, tris, sigma, far_order: int = 4, ss_order=4, workers: int | None = None):
     """m (N, 3): m[i, k] = <V Phi, lambda_k>_{T_i} for the P0 density Phi =
-    sigma (see the module docstring)."""
+    sigma (see the module docstring); ss_order an int or SSOrders, as for
+    the matrix."""
     verts = np.asarray(verts, dtype=np.float64)
     tris = np.asarray(tris)
     sigma = np.asarray(sigma, dtype=np.float64)
@@ -126,8 +127,10 @@ def p1_moments(verts, tris, sigma, far_order: int = 4, ss_order: int = 4, worker
     else:
         for i, R in _regular_rows((verts, tris, blocks[0], far_order)):
             m[i] = R @ sigma
+    orders = SSOrders.of(ss_order)
+    geo = element_geometry(verts, tris)
     for (p, q, kind, Tp, Tq) in classify_pairs(tris):
-        mp_, mq_ = touching_moments(verts, tris, p, q, kind, Tp, Tq, ss_order)
+        mp_, mq_ = touching_moments(verts, tris, p, q, kind, Tp, Tq, _pair_order(orders, geo, kind, p, q))
         m[p] += sigma[q] * mp_
         if q != p:
             m[q] += sigma[p] * mq_
@@ -154,7 +157,7 @@ def residual_from_moments(verts, tris, m):
     return out
 
 
-def residual_indicators(verts, tris, sigma, far_order: int = 4, ss_order: int = 4, workers: int | None = None):
+def residual_indicators(verts, tris, sigma, far_order: int = 4, ss_order=4, workers: int | None = None):
     """mu_l(T)^2 for every element (eq. "residual:indicator") of the P0
     density sigma; returns (mu2 (N,), m (N, 3))."""
     m = p1_moments(verts, tris, sigma, far_order, ss_order, workers)

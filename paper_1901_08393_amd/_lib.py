@@ -30,7 +30,9 @@ BC_F32_F64 = 2
 
 class bc_assembly_opts(C.Structure):
     _fields_ = [("far_order", C.c_int32), ("ss_order", C.c_int32), ("precision", C.c_int32),
-                ("far_low", C.c_int32), ("near_factor", C.c_double)]
+                ("far_low", C.c_int32), ("near_factor", C.c_double), ("ss_order_edge", C.c_int32),
+                ("ss_order_vertex", C.c_int32), ("ss_order_sliver", C.c_int32), ("reserved", C.c_int32),
+                ("sliver_ratio", C.c_double)]
 
 
 class bc_pattern_info(C.Structure):

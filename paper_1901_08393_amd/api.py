@@ -80,7 +80,14 @@ class CapacityProblem:
 
     def __init__(self, verts, tris, precision: str = "fp64", far_order: int = 4, ss_order: int = 4,
                  near_factor: Optional[float] = None, device: str = "cuda", validate: bool = True, stream=None,
-                 far_low: Optional[bool] = None):
+                 far_low: Optional[bool] = None, ss_order_edge: int = 0, ss_order_vertex: int = 0,
+                 ss_order_sliver: int = 0, sliver_ratio: float = 0.0):
+        """ss_order: points per coordinate of the singular rules (coincident
+        pairs, and every touching pair unless the next three say otherwise);
+        ss_order_edge / ss_order_vertex: the orders of edge- and
+        vertex-adjacent pairs (0: ss_order); ss_order_sliver with
+        sliver_ratio: at least that order for touching pairs with an element
+        whose diam^2 exceeds sliver_ratio |T| (0: off)."""
         if precision not in PRECISION:
             raise ValueError(f"precision must be one of {list(PRECISION)}")
         L = lib()
@@ -100,7 +107,9 @@ class CapacityProblem:
             near_factor = 1.5 if precision == "mixed" else 0.0
         if far_low is None:  # Radon's 7-point rule for distant blocks: mixed precision with the 4 x 4 far rule
             far_low = precision == "mixed" and far_order == 4
-        self.opts = _lib.bc_assembly_opts(far_order, ss_order, self.prec, int(bool(far_low)), float(near_factor))
+        self.opts = _lib.bc_assembly_opts(far_order, ss_order, self.prec, int(bool(far_low)), float(near_factor),
+                                          int(ss_order_edge), int(ss_order_vertex), int(ss_order_sliver), 0,
+                                          float(sliver_ratio))
         self.d_verts = torch.from_numpy(verts).to(self.device)
         self.d_tris = torch.from_numpy(tris).to(self.device)
         nb = L.bc_mesh_workspace_bytes(self.N)

@@ -72,10 +72,26 @@ void gauss_legendre01(int n, double *x, double *w) {
   }
 }
 
+SSTable ss_table(const bc_assembly_opts &o) {
+  SSTable t{};
+  for (int n = 1; n <= kSSMax; ++n) gauss_legendre01(n, t.x[n], t.w[n]);
+  t.base = o.ss_order;
+  t.edge = o.ss_order_edge;
+  t.vertex = o.ss_order_vertex;
+  t.sliver = o.ss_order_sliver;
+  t.sliver_ratio = o.sliver_ratio;
+  return t;
+}
+
 static bool opts_ok(const bc_assembly_opts *o) {
   if (!o) return false;
   if (o->far_order < 1 || o->far_order > 4) return false;
   if (o->ss_order < 1 || o->ss_order > kSSMax) return false;
+  for (int32_t n : {o->ss_order_edge, o->ss_order_vertex, o->ss_order_sliver})
+    if (n < 0 || n > kSSMax) return false;
+  if (o->reserved != 0) return false;
+  if (!(o->sliver_ratio >= 0.0) || !std::isfinite(o->sliver_ratio)) return false;
+  if (o->ss_order_sliver > 0 && !(o->sliver_ratio > 0.0)) return false;
   if (o->precision != BC_FP64 && o->precision != BC_MIXED) return false;
   if (o->far_low != 0 && o->far_low != 1) return false;
   if (o->far_low == 1 && o->precision != BC_MIXED) return false;

@@ -352,15 +352,16 @@ __global__ __launch_bounds__(1024) void k_far32m(const double4 *__restrict__ qpA
 }
 
 // ------------------------------------------------------- touching and near
-// NSS > 0: the singular rules' order as a compile-time constant (4, 8), so
-// that the point index splits into Gauss indices by shifts, not divisions.
-template <bool MIXED, int NSS>
+// One pattern entry (i, j), j >= i: touching pairs with the singular rule of
+// the pair's order (ss_order_of), near pairs with the regular rule, FP64.
+template <bool MIXED>
 __device__ __forceinline__ void sparse_entry(int64_t e, const double *__restrict__ verts,
-                                             const int4 *__restrict__ tri4, const double *__restrict__ area,
-                                             const double4 *__restrict__ qpA, int Q, const SSRule &ss,
-                                             const int32_t *__restrict__ prowptr, const int32_t *__restrict__ pcol,
-                                             const int32_t *__restrict__ prow, const int32_t *__restrict__ pkind,
-                                             double *__restrict__ pcorr, int64_t ld, void *__restrict__ Vout) {
+                                             const int4 *__restrict__ tri4, const double4 *__restrict__ cen4,
+                                             const double *__restrict__ area, const double4 *__restrict__ qpA, int Q,
+                                             const SSTable &ss, const int32_t *__restrict__ prowptr,
+                                             const int32_t *__restrict__ pcol, const int32_t *__restrict__ prow,
+                                             const int32_t *__restrict__ pkind, double *__restrict__ pcorr,
+                                             int64_t ld, void *__restrict__ Vout) {
   const int lane = threadIdx.x & 63;
   const int i = prow[e], j = pcol[e];
   if (j < i) return;
@@ -387,24 +388,15 @@ __device__ __forceinline__ void sparse_entry(int64_t e, const double *__restrict
     const double e1x = verts[3 * D1] - dx0, e1y = verts[3 * D1 + 1] - dy0, e1z = verts[3 * D1 + 2] - dz0;
     const double e2x = verts[3 * D2] - verts[3 * D1], e2y = verts[3 * D2 + 1] - verts[3 * D1 + 1],
                  e2z = verts[3 * D2 + 2] - verts[3 * D1 + 2];
-    const int n = NSS > 0 ? NSS : ss.n, n2 = n * n, n4 = n2 * n2;
-    const int nreg = kind == kCoincident ? 6 : (kind == kEdge ? 4 : 2);
-    for (int p = lane; p < nreg * n4; p += 64) {
-      const int reg = p / n4;
-      int q = p - reg * n4;
-      const int i3 = q % n; q /= n;
-      const int i2 = q % n; q /= n;
-      const int i1 = q % n; q /= n;
-      const int i0 = q;
-      double x1, x2, y1, y2;
-      const double Jac = ss_map(kind, reg, ss.x[i0], ss.x[i1], ss.x[i2], ss.x[i3], x1, x2, y1, y2);
-      const double wgt = ss.w[i0] * ss.w[i1] * ss.w[i2] * ss.w[i3] * Jac;
+    const double ai = area[i], aj = area[j];
+    const int n = ss_order_of(ss, kind, cen4[i].w, ai, cen4[j].w, aj);
+    ss_points_n(kind, ss, n, lane, [&](double x1, double x2, double y1, double y2, double wgt) {
       const double px = ax + x1 * bax + x2 * cbx, py = ay + x1 * bay + x2 * cby, pz = az + x1 * baz + x2 * cbz;
       const double qx = dx0 + y1 * e1x + y2 * e2x, qy = dy0 + y1 * e1y + y2 * e2y, qz = dz0 + y1 * e1z + y2 * e2z;
       const double rx = px - qx, ry = py - qy, rz = pz - qz;
       acc += wgt * rsqrt64(rx * rx + ry * ry + rz * rz);
-    }
-    scale = (2.0 * area[i]) * (2.0 * area[j]) * kInv4Pi;
+    });
+    scale = (2.0 * ai) * (2.0 * aj) * kInv4Pi;
   }
   const double v = wave_sum(acc) * scale;
   if (lane != 0) return;
@@ -434,15 +426,17 @@ __device__ __forceinline__ void sparse_entry(int64_t e, const double *__restrict
 // One wavefront per pattern entry.  (Fewer wavefronts taking the entries
 // grid-stride were slower: an entry's chain of dependent loads is then
 // waited for one entry after another.)
-template <bool MIXED, int NSS>
+template <bool MIXED>
 __global__ __launch_bounds__(kWG) void k_sparse(const double *__restrict__ verts, const int4 *__restrict__ tri4,
-                                                const double *__restrict__ area, const double4 *__restrict__ qpA,
-                                                int Q, SSRule ss, const int32_t *__restrict__ prowptr,
-                                                const int32_t *__restrict__ pcol, const int32_t *__restrict__ prow,
-                                                const int32_t *__restrict__ pkind, double *__restrict__ pcorr,
-                                                int64_t nnz, int64_t ld, void *__restrict__ Vout) {
+                                                const double4 *__restrict__ cen4, const double *__restrict__ area,
+                                                const double4 *__restrict__ qpA, int Q, SSTable ss,
+                                                const int32_t *__restrict__ prowptr, const int32_t *__restrict__ pcol,
+                                                const int32_t *__restrict__ prow, const int32_t *__restrict__ pkind,
+                                                double *__restrict__ pcorr, int64_t nnz, int64_t ld,
+                                                void *__restrict__ Vout) {
   const int64_t e = (int64_t)blockIdx.x * (kWG / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (e < nnz) sparse_entry<MIXED, NSS>(e, verts, tri4, area, qpA, Q, ss, prowptr, pcol, prow, pkind, pcorr, ld, Vout);
+  if (e < nnz)
+    sparse_entry<MIXED>(e, verts, tri4, cen4, area, qpA, Q, ss, prowptr, pcol, prow, pkind, pcorr, ld, Vout);
 }
 
 template <typename T>
@@ -553,9 +547,7 @@ int launch_assemble(const void *mesh_ws, const int32_t *tris, const double *vert
   }
   if (hipGetLastError() != hipSuccess) return BC_EDEVICE;
   if (nnz > 0) {
-    SSRule ss{};
-    ss.n = o.ss_order;
-    gauss_legendre01(o.ss_order, ss.x, ss.w);
+    const SSTable ss = ss_table(o);
     PatternLayout P(N, nnz, o.precision);
     char *pb = static_cast<char *>(pattern);
     const int32_t *prowptr = reinterpret_cast<const int32_t *>(pb + P.rowptr);
@@ -565,10 +557,8 @@ int launch_assemble(const void *mesh_ws, const int32_t *tris, const double *vert
     double *pcorr = mixed ? reinterpret_cast<double *>(pb + P.corr) : nullptr;
     const int grid = (int)((nnz + 3) / 4);
     const int Q = o.far_order * o.far_order;
-    auto kern = mixed ? (ss.n == 4 ? k_sparse<true, 4> : ss.n == 8 ? k_sparse<true, 8> : k_sparse<true, 0>)
-                      : (ss.n == 4 ? k_sparse<false, 4> : ss.n == 8 ? k_sparse<false, 8> : k_sparse<false, 0>);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWG), 0, s, verts, m.tri4, m.area, m.qpA64, Q, ss, prowptr, pcol, prow,
-                       pkind, pcorr, nnz, ld, V);
+    hipLaunchKernelGGL(mixed ? k_sparse<true> : k_sparse<false>, dim3(grid), dim3(kWG), 0, s, verts, m.tri4, m.cen4,
+                       m.area, m.qpA64, Q, ss, prowptr, pcol, prow, pkind, pcorr, nnz, ld, V);
     if (hipGetLastError() != hipSuccess) return BC_EDEVICE;
   }
   if (ld > N) {

@@ -348,11 +348,28 @@ __device__ __forceinline__ bool far_low_order(const double *bbox, int I, int J) 
   return box_dist2(bi, bj) >= kSepFarLow * kSepFarLow * fmax(bi[6], bj[6]);
 }
 
-struct SSRule {
-  int n;
-  int pad;
-  double x[kSSMax], w[kSSMax];
+// Gauss rules of the singular quadrature for every order a launch may use
+// (row n: the n-point rule on [0, 1]) and how a touching pair picks its
+// order: `base` for coincident pairs, `edge` / `vertex` for edge- and
+// vertex-adjacent pairs (0: base), raised to `sliver` when an element of
+// the pair has diam^2 > sliver_ratio |T| (sliver 0: off).
+struct SSTable {
+  double x[kSSMax + 1][kSSMax], w[kSSMax + 1][kSSMax];
+  int32_t base, edge, vertex, sliver;
+  double sliver_ratio;
 };
+
+// filled from the assembly options on the host (abi.hip)
+SSTable ss_table(const bc_assembly_opts &o);
+
+__device__ __forceinline__ int ss_order_of(const SSTable &t, int kind, double d2i, double ai, double d2j,
+                                           double aj) {
+  int n = t.base;
+  if (kind == kEdge && t.edge > 0) n = t.edge;
+  else if (kind == kVertex && t.vertex > 0) n = t.vertex;
+  if (t.sliver > 0 && (d2i > t.sliver_ratio * ai || d2j > t.sliver_ratio * aj)) n = max(n, t.sliver);
+  return n;
+}
 
 // Region maps of the singular rules on K = {0 <= x2 <= x1 <= 1}; (xi, e1,
 // e2, e3) in [0,1]^4.  Returns the Jacobian and writes the two reference
@@ -399,6 +416,37 @@ __device__ __forceinline__ double ss_map(int kind, int reg, double xi, double e1
   return J;
 }
 
+// The points of the singular rule of order n for a pair of class `kind`,
+// shared out over the 64 lanes of a wavefront: f(x1, x2, y1, y2, w) per
+// point, with the reference points of both triangles and the weight (the
+// Jacobian included).  NSS > 0 makes the order a compile-time constant, so
+// that the point index splits into Gauss indices by shifts.
+template <int NSS, typename F>
+__device__ __forceinline__ void ss_points(int kind, const double *sx, const double *sw, int nrt, int lane, F &&f) {
+  const int n = NSS > 0 ? NSS : nrt, n2 = n * n, n4 = n2 * n2;
+  const int nreg = kind == kCoincident ? 6 : (kind == kEdge ? 4 : 2);
+  for (int p = lane; p < nreg * n4; p += 64) {
+    const int reg = p / n4;
+    int q = p - reg * n4;
+    const int i3 = q % n; q /= n;
+    const int i2 = q % n; q /= n;
+    const int i1 = q % n; q /= n;
+    const int i0 = q;
+    double x1, x2, y1, y2;
+    const double Jac = ss_map(kind, reg, sx[i0], sx[i1], sx[i2], sx[i3], x1, x2, y1, y2);
+    f(x1, x2, y1, y2, sw[i0] * sw[i1] * sw[i2] * sw[i3] * Jac);
+  }
+}
+
+// ss_points for the pair's order n (uniform in the wavefront): orders 4
+// and 8 compiled as constants, the others at run time.
+template <typename F>
+__device__ __forceinline__ void ss_points_n(int kind, const SSTable &t, int n, int lane, F &&f) {
+  if (n == 4) ss_points<4>(kind, t.x[4], t.w[4], 4, lane, f);
+  else if (n == 8) ss_points<8>(kind, t.x[8], t.w[8], 8, lane, f);
+  else ss_points<0>(kind, t.x[n], t.w[n], n, lane, f);
+}
+
 // Canonical vertex orders of a touching pair, the first element p and the
 // second q, as the singular rules use them: P = (A, B, C) on T_p and
 // Q = (D0, D1, D2) on T_q.
@@ -440,6 +488,25 @@ __device__ __forceinline__ TouchOrder touch_order(int kind, int4 tp, int4 tq) {
     o.sq[c] = o.Q[c] == sv[0] ? 0 : (o.Q[c] == sv[1] ? 1 : 2);
   }
   return o;
+}
+
+// The matrix-core far field expands -r^2 = 2 e.y - |e|^2 - |y|^2 about the
+// centre of the column block's box, so its FP32 rounding error grows like
+// (|e|^2 + |y|^2) / r^2.  A tile takes that kernel only if the column block
+// is compact against the gap: the half-diagonal of its box at most
+// kCompact times the box distance.  Blocks of spatially scattered elements
+// (a caller's element order) fail the test and keep the vector-ALU kernel,
+// which expands about each column element's own centroid.
+constexpr double kCompact = 2.5;
+
+__device__ __forceinline__ bool far_compact(const double *bbox, int I, int J) {
+  const double *bj = bbox + 8 * J;
+  double h2 = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const double d = 0.5 * (bj[3 + c] - bj[c]);
+    h2 += d * d;
+  }
+  return h2 <= kCompact * kCompact * box_dist2(bbox + 8 * I, bj);
 }
 
 // Fused multiply-add in the type of the operands (__builtin_fma alone would

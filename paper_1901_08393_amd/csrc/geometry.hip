@@ -182,7 +182,7 @@ static_assert(kTileChunk == 4096, "MeshLayout sizes the per-chunk counts for chu
 __device__ __forceinline__ int tile_class(const double *bbox, int t) {
   int I, J;
   tile_of(t, I, J);
-  return (I == J || !far_separated(bbox, I, J)) ? 0 : (far_low_order(bbox, I, J) ? 2 : 1);
+  return (I == J || !far_separated(bbox, I, J) || !far_compact(bbox, I, J)) ? 0 : (far_low_order(bbox, I, J) ? 2 : 1);
 }
 
 __global__ __launch_bounds__(kWG) void k_tile_count(const double *__restrict__ bbox, int ntiles,

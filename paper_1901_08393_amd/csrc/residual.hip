@@ -130,17 +130,16 @@ __global__ __launch_bounds__(kWG) void k_res_far(const double4 *__restrict__ qpA
 }
 
 // tv[e][k] = moment k on T_i of the pattern entry e = (i, j) with the
-// singular rule of its class, scale (1/4pi)(2|T_p|)(2|T_q|) included; 0 for
+// singular rule of the pair's order, scale (1/4pi)(2|T_p|)(2|T_q|) included; 0 for
 // near entries (k_res_far covers them).  The rule runs on the canonical pair
 // (p, q) = (min(i, j), max(i, j)); the linear weight is taken at the points
 // of T_i: lambda = (1 - x1, x1 - x2, x2) on the canonical vertices of T_p,
 // or (1 - y1, y1 - y2, y2) on those of T_q.
-template <int NSS>
 __global__ __launch_bounds__(kWG) void k_res_touch(const double *__restrict__ verts, const int4 *__restrict__ tri4,
-                                                   const double *__restrict__ area, SSRule ss,
-                                                   const int32_t *__restrict__ prow, const int32_t *__restrict__ pcol,
-                                                   const int32_t *__restrict__ pkind, int64_t nnz,
-                                                   double *__restrict__ tv) {
+                                                   const double4 *__restrict__ cen4, const double *__restrict__ area,
+                                                   SSTable ss, const int32_t *__restrict__ prow,
+                                                   const int32_t *__restrict__ pcol, const int32_t *__restrict__ pkind,
+                                                   int64_t nnz, double *__restrict__ tv) {
   const int64_t e = (int64_t)blockIdx.x * (kWG / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (e >= nnz) return;
   const int lane = threadIdx.x & 63;
@@ -162,18 +161,10 @@ __global__ __launch_bounds__(kWG) void k_res_touch(const double *__restrict__ ve
     const double e1x = verts[3 * D1] - dx0, e1y = verts[3 * D1 + 1] - dy0, e1z = verts[3 * D1 + 2] - dz0;
     const double e2x = verts[3 * D2] - verts[3 * D1], e2y = verts[3 * D2 + 1] - verts[3 * D1 + 1],
                  e2z = verts[3 * D2 + 2] - verts[3 * D1 + 2];
-    const int n = NSS, n2 = n * n, n4 = n2 * n2;
-    const int nreg = kind == kCoincident ? 6 : (kind == kEdge ? 4 : 2);
-    for (int pt = lane; pt < nreg * n4; pt += 64) {
-      const int reg = pt / n4;
-      int r = pt - reg * n4;
-      const int i3 = r % n; r /= n;
-      const int i2 = r % n; r /= n;
-      const int i1 = r % n; r /= n;
-      const int i0 = r;
-      double x1, x2, y1, y2;
-      const double Jac = ss_map(kind, reg, ss.x[i0], ss.x[i1], ss.x[i2], ss.x[i3], x1, x2, y1, y2);
-      const double wgt = ss.w[i0] * ss.w[i1] * ss.w[i2] * ss.w[i3] * Jac;
+    const double ap = area[p], aq = area[q];
+    // the order of the canonical pair, as for its matrix entry
+    const int n = ss_order_of(ss, kind, cen4[p].w, ap, cen4[q].w, aq);
+    ss_points_n(kind, ss, n, lane, [&](double x1, double x2, double y1, double y2, double wgt) {
       const double px = ax + x1 * bax + x2 * cbx, py = ay + x1 * bay + x2 * cby, pz = az + x1 * baz + x2 * cbz;
       const double qx = dx0 + y1 * e1x + y2 * e2x, qy = dy0 + y1 * e1y + y2 * e2y, qz = dz0 + y1 * e1z + y2 * e2z;
       const double rx = px - qx, ry = py - qy, rz = pz - qz;
@@ -182,8 +173,8 @@ __global__ __launch_bounds__(kWG) void k_res_touch(const double *__restrict__ ve
       mc0 = __builtin_fma(1.0 - u1, f, mc0);
       mc1 = __builtin_fma(u1 - u2, f, mc1);
       mc2 = __builtin_fma(u2, f, mc2);
-    }
-    scale = (2.0 * area[p]) * (2.0 * area[q]) * kInv4Pi;
+    });
+    scale = (2.0 * ap) * (2.0 * aq) * kInv4Pi;
   }
   mc0 = wave_sum(mc0) * scale;
   mc1 = wave_sum(mc1) * scale;
@@ -278,21 +269,10 @@ int launch_residual(const double *verts, int64_t N, const bc_assembly_opts &o, c
   const int32_t *pcol = reinterpret_cast<const int32_t *>(pb + P.col);
   const int32_t *prow = reinterpret_cast<const int32_t *>(pb + P.row);
   const int32_t *pkind = reinterpret_cast<const int32_t *>(pb + P.kind);
-  SSRule ss{};
-  ss.n = o.ss_order;
-  gauss_legendre01(o.ss_order, ss.x, ss.w);
+  const SSTable ss = ss_table(o);
   const unsigned grid = (unsigned)((nnz + 3) / 4);
-  switch (o.ss_order) {
-#define BC_RES_TOUCH(K)                                                                                          \
-  case K:                                                                                                        \
-    hipLaunchKernelGGL(k_res_touch<K>, dim3(grid), dim3(kWG), 0, s, verts, m.tri4, m.area, ss, prow, pcol, pkind, \
-                       nnz, tv);                                                                                 \
-    break;
-    BC_RES_TOUCH(1) BC_RES_TOUCH(2) BC_RES_TOUCH(3) BC_RES_TOUCH(4) BC_RES_TOUCH(5) BC_RES_TOUCH(6)
-    BC_RES_TOUCH(7) BC_RES_TOUCH(8)
-#undef BC_RES_TOUCH
-    default: return BC_EINVAL;
-  }
+  hipLaunchKernelGGL(k_res_touch, dim3(grid), dim3(kWG), 0, s, verts, m.tri4, m.cen4, m.area, ss, prow, pcol, pkind,
+                     nnz, tv);
   if (hipGetLastError() != hipSuccess) return BC_EDEVICE;
   hipLaunchKernelGGL(k_res_finish, dim3((unsigned)((N + kWG - 1) / kWG)), dim3(kWG), 0, s, verts, m.tri4, m.cen4,
                      m.area, sigma, (const double *)part, C, prowptr, pcol, (const double *)tv, (int)N, mu2, mom);

@@ -237,7 +237,8 @@ def _block_classes(verts, tris):
     """Tile class of every element pair from the 64-element blocks' vertex
     boxes, as bc_prepare classifies the far-field tiles: 2 where the boxes
     are at least 8 largest element diameters apart (Radon's rule), 1 at
-    least 4 apart, else 0; and the box distance in diameters per pair."""
+    least 4 apart, else 0 (also where the column block's half-diagonal
+    exceeds 2.5 times the gap); and the box distance in diameters."""
     P = np.asarray(verts)[np.asarray(tris)]
     N = len(tris)
     d2 = np.max(np.sum((P[:, [1, 2, 0]] - P) ** 2, axis=2), axis=1)
@@ -248,7 +249,8 @@ def _block_classes(verts, tris):
     gap = np.maximum(0.0, np.maximum(lo[:, None, :] - hi[None, :, :], lo[None, :, :] - hi[:, None, :]))
     g2 = np.sum(gap ** 2, axis=2)
     dm = np.maximum(bd2[:, None], bd2[None, :])
-    cls = np.where(g2 >= 64.0 * dm, 2, np.where(g2 >= 16.0 * dm, 1, 0))
+    compact = (np.sum((0.5 * (hi - lo)) ** 2, axis=1)[None, :] <= 2.5 ** 2 * g2) | (g2 == 0)
+    cls = np.where(~compact, 0, np.where(g2 >= 64.0 * dm, 2, np.where(g2 >= 16.0 * dm, 1, 0)))
     np.fill_diagonal(cls, 0)
     blk = np.arange(N) // 64
     return cls[np.ix_(blk, blk)], np.sqrt(g2 / dm)[np.ix_(blk, blk)]
@@ -291,6 +293,105 @@ def test_far_low_order_rule_at_threshold(api):
     cap_ref = oracle.capacity(oracle.solve_direct(ref4, b), b)
     r = p.solve()
     assert r.ok and abs(r.cap - cap_ref) / cap_ref <= 1e-8, (r.cap, cap_ref)
+
+
+def _straddling_spheres():
+    """Three level-2 unit spheres on the x axis at 0, 6.5 and 200, the first
+    one's elements in order, the other two's interleaved: every block of
+    the last ten spans the second and the third sphere (half-diagonal about
+    97 against a gap of 4.5 to the first sphere's blocks).  Expanded about
+    such a block's box centre in FP32, the entries of the first two
+    spheres' pairs would carry errors up to 2.7e-5 with a mean of 4e-7 (a
+    CPU emulation of the FP32 products and sums)."""
+    m = synth.icosphere(2, 1.0)
+    n, nv = m.N, m.verts.shape[0]
+    verts = np.vstack([m.verts, m.verts + [6.5, 0.0, 0.0], m.verts + [200.0, 0.0, 0.0]])
+    tb, tc = m.tris + nv, m.tris + 2 * nv
+    inter = np.empty((2 * n, 3), dtype=np.int64)
+    inter[0::2], inter[1::2] = tb, tc
+    return verts, np.vstack([m.tris, inter]).astype(np.int32)
+
+
+def test_mixed_scattered_blocks(api):
+    """A caller's element order that makes 64-element blocks span far-apart
+    parts: such tiles keep the vector-ALU far field (no expansion about the
+    block's centre); FP32 entries within 4e-6 of the oracle's, no bias, and
+    the mixed capacity within 1e-8 of the oracle's."""
+    _flush("mixed precision, blocks of scattered elements")
+    verts, tris = _straddling_spheres()
+    N = tris.shape[0]
+    cls, dist = _block_classes(verts, tris)
+    n1 = N // 3
+    # the first sphere's blocks against the straddling ones: far apart, yet not compact
+    assert dist[:n1, n1:].min() >= 8.0 and (cls[:n1, n1:] == 0).all()
+    ref = oracle.assemble(verts, tris, 4, 4)
+    p = api.CapacityProblem(verts, tris, "mixed")
+    V32 = p.assemble()
+    torch.cuda.synchronize()
+    V32 = V32.cpu().numpy()[:, :N].astype(np.float64)
+    mask = ~np.eye(N, dtype=bool)
+    rel = (V32 - ref)[mask] / ref[mask]
+    touch = np.zeros((N, N), dtype=bool)
+    for (i, j, *_r) in oracle.classify_pairs(tris):
+        touch[i, j] = touch[j, i] = True
+    far = ~touch & mask
+    rf = (V32[far] - ref[far]) / ref[far]
+    _flush(f"  far entries: max {np.abs(rf).max():.2e} mean {rf.mean():.2e}")
+    assert np.abs(rf).max() <= 4e-6 and abs(rf.mean()) <= 2e-9
+    assert np.isfinite(rel).all()
+    b = oracle.rhs(verts, tris)
+    cap_ref = oracle.capacity(oracle.solve_direct(ref, b), b)
+    r = p.solve()
+    assert r.ok and abs(r.cap - cap_ref) / cap_ref <= 1e-8, (r.cap, cap_ref)
+
+
+@pytest.mark.parametrize("case", ["per_class", "sliver_hull"])
+def test_singular_orders_per_pair(api, case):
+    """Singular rules of different orders per touching pair (bc_assembly_opts
+    ss_order_edge / ss_order_vertex, and ss_order_sliver for pairs with a
+    thin element), FP64: entries and capacity within 1e-12 of the oracle
+    with the same per-pair orders.  The sliver case is a convex hull with
+    facets down to 2.5 degrees (diam^2/|T| up to 67), refined once; raising
+    the order on its thin elements moves the capacity towards the one with
+    order-10 rules everywhere."""
+    _flush(f"singular orders per pair: {case}")
+    if case == "per_class":
+        m = synth.cube(8)
+        verts, tris = m.verts, m.tris
+        kw = dict(ss_order=8, ss_order_edge=6, ss_order_vertex=4)
+        orders = oracle.SSOrders(8, 6, 4)
+    else:
+        h = synth.convex_hull(14, 0, min_angle=0.0)
+        verts, tris, _ = synth.refine_uniform(h.verts, synth.init_reference_edges(h.verts, h.tris), 1)
+        kw = dict(ss_order=4, ss_order_sliver=8, sliver_ratio=12.0)
+        orders = oracle.SSOrders(4, sliver=8, sliver_ratio=12.0)
+        g = oracle.element_geometry(verts, tris)
+        assert (g["diam2"] > 12.0 * g["area"]).any() and (g["diam2"] <= 12.0 * g["area"]).any()
+    N = len(tris)
+    ref = oracle.assemble(verts, tris, 4, orders)
+    p = api.CapacityProblem(verts, tris, "fp64", **kw)
+    Vg = p.assemble().cpu().numpy()[:, :N]
+    rel = np.abs(Vg - ref) / np.abs(ref)
+    assert rel.max() <= 1e-12, rel.max()
+    b = oracle.rhs(verts, tris)
+    cap_ref = oracle.capacity(oracle.solve_direct(ref, b), b)
+    r = p.solve()
+    assert r.ok and abs(r.cap - cap_ref) <= 1e-12 * cap_ref, (r.cap, cap_ref)
+    if case == "sliver_hull":
+        V4 = oracle.assemble(verts, tris, 4, 4)
+        V10 = oracle.assemble(verts, tris, 4, 10)
+        c4 = oracle.capacity(oracle.solve_direct(V4, b), b)
+        c10 = oracle.capacity(oracle.solve_direct(V10, b), b)
+        _flush(f"  vs order 10 everywhere: order 4 {abs(c4 / c10 - 1):.1e}, per pair {abs(r.cap / c10 - 1):.1e}")
+        assert abs(r.cap / c10 - 1) < abs(c4 / c10 - 1)
+    # the residual estimator takes the same per-pair orders for its moments
+    from oracle import residual as R
+
+    x = oracle.solve_direct(ref, b)
+    _, mom_ref = R.residual_indicators(verts, tris, x, 4, orders)
+    mag = R.p1_moments(verts, tris, np.abs(x), 4, orders)
+    _, mom = p.residual(torch.from_numpy(x).to("cuda"), moments=True)
+    assert np.max(np.abs(mom.cpu().numpy() - mom_ref) / mag) <= 1e-13
 
 
 # ----------------------------------------------------------------- solves
