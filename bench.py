@@ -428,7 +428,8 @@ def adaptive_cube_mode(a):
     t0 = synth.init_reference_edges(m.verts, m.tris)
     w0 = time.perf_counter()
     steps = adaptive_capacity(m.verts, t0, steps=1000, theta=0.5, precision=a.precision, h_mode=1,
-                              max_elements=a.target_n, ss_order=a.ss_order)
+                              max_elements=a.target_n, ss_order=a.ss_order, ss_order_edge=a.ss_order_edge,
+                              ss_order_vertex=a.ss_order_vertex, estimator=a.estimator)
     wall = time.perf_counter() - w0
     rows = []
     for s in steps:
@@ -438,9 +439,53 @@ def adaptive_cube_mode(a):
                          solve_ms=round(s.t_solve_ms, 2), host_ms=round(s.t_refine_ms, 1)))
         log(f"l={s.level} N={s.N} cap={s.cap:.12f} err={err:.3e} eta2={s.eta2:.3e} its={s.iters} "
             f"asm {s.t_assemble_ms:.1f} ms solve {s.t_solve_ms:.1f} ms")
-    print(json.dumps({"mode": "adaptive_cube", "precision": a.precision, "ss_order": a.ss_order, "steps": rows,
+    print(json.dumps({"mode": "adaptive_cube", "precision": a.precision, "estimator": a.estimator,
+                      "ss_orders": [a.ss_order, a.ss_order_edge or a.ss_order, a.ss_order_vertex or a.ss_order],
+                      "steps": rows,
                       "wall_s": round(wall, 2),
                       "monotone": all(steps[k].cap < steps[k + 1].cap for k in range(len(steps) - 1))}))
+
+
+def orders_study_mode(a):
+    """Singular-rule orders per pair class on adapted unit-cube meshes (the
+    primal loop of --adaptive-cube, order 4, stopped at about 2000 and 20000
+    triangles): the capacity with per-class orders (coincident, edge,
+    vertex) against the one with order-8 rules everywhere (order 10 is
+    beyond the library's table; order 8 is within 2e-9 of it on such meshes,
+    see DESIGN), with the time of the touching-pair kernel's assembly."""
+    import torch
+
+    import synth
+    from paper_1901_08393_amd import api
+    from paper_1901_08393_amd.adaptive import adaptive_capacity
+
+    torch.cuda.set_device(0)
+    m = synth.cube12()
+    t0 = synth.init_reference_edges(m.verts, m.tris)
+    out = {"mode": "orders_study", "workload": "unit cube adapted by the primal loop (theta 0.5, |T|^(1/2))",
+           "meshes": []}
+    for target in (2000, 20000):
+        steps = adaptive_capacity(m.verts, t0, steps=1000, theta=0.5, precision="fp64", h_mode=1,
+                                  max_elements=target, keep=True)
+        v, t = steps[-1].verts, steps[-1].tris
+        rows = []
+        ref = None
+        for c, e, vx in ((8, 8, 8), (4, 4, 4), (6, 6, 6), (8, 6, 4), (8, 8, 4), (8, 4, 4), (6, 4, 4), (8, 6, 6)):
+            p = api.CapacityProblem(v, t, "fp64", ss_order=c, ss_order_edge=e, ss_order_vertex=vx)
+            p.allocate()
+            p.assemble()
+            _, ms = timed(torch, p.assemble, reps=3)
+            r = p.solve()
+            if ref is None:
+                ref = r.cap
+            rows.append({"orders": [c, e, vx], "cap": r.cap, "rel_to_order8": (r.cap - ref) / ref,
+                         "assemble_ms": round(ms, 3)})
+            log(f"N={len(t)} orders {c},{e},{vx}: cap {r.cap:.12f} rel {(r.cap - ref) / ref:+.2e} asm {ms:.2f} ms")
+            del p
+            torch.cuda.empty_cache()
+        out["meshes"].append({"N": int(len(t)), "rows": rows,
+                              "err_vs_reference_capacity": abs(CUBE_CAPACITY - ref)})
+    print(json.dumps(out))
 
 
 def dual_summary(max_n: int = 12000) -> dict:
@@ -674,9 +719,15 @@ def main():
     ap.add_argument("--inexact-lambda", type=float, default=0.0,
                     help="dual mode: stop GMRES when the energy of its update is below lambda x the estimator")
     ap.add_argument("--ss-order", type=int, default=4, help="--adaptive-cube: Gauss points per coordinate of the "
-                    "singular rules")
+                    "singular rules (coincident pairs, and all when the next two are 0)")
+    ap.add_argument("--ss-order-edge", type=int, default=0, help="--adaptive-cube: edge-adjacent pairs' order")
+    ap.add_argument("--ss-order-vertex", type=int, default=0, help="--adaptive-cube: vertex-adjacent pairs' order")
+    ap.add_argument("--estimator", default="zz", choices=["zz", "residual"],
+                    help="--adaptive-cube: ZZ indicators or the weighted-residual estimator of Appendix A")
     ap.add_argument("--adaptive-cube", action="store_true",
                     help="the unit-cube experiment on the primal path, up to --target-n triangles")
+    ap.add_argument("--orders-study", action="store_true",
+                    help="singular-rule orders per pair class on adapted unit-cube meshes")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy first (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -695,6 +746,8 @@ def main():
         return adaptive_cube_mode(a)
     if a.dual_theta:
         return dual_theta_mode(a)
+    if a.orders_study:
+        return orders_study_mode(a)
 
     import torch
 

@@ -68,7 +68,8 @@ class Step:
 def adaptive_capacity(verts, tris, steps: int = 5, theta: float = 0.5, precision: str = "fp64",
                       h_mode: int = 0, warm_start: bool = True, keep: bool = False, refine: str = "bisec1",
                       max_elements: Optional[int] = None, far_order: int = 4, ss_order: int = 4,
-                      estimator: str = "zz", **solve_opts) -> List[Step]:
+                      estimator: str = "zz", ss_order_edge: int = 0, ss_order_vertex: int = 0,
+                      **solve_opts) -> List[Step]:
     """Run `steps` refinements (steps + 1 solves), or stop before the first
     mesh with more than `max_elements` triangles.  `tris` must be in NVB form
     (reference edge first); use synth.init_reference_edges on a new mesh.
@@ -77,7 +78,9 @@ def adaptive_capacity(verts, tris, steps: int = 5, theta: float = 0.5, precision
     marked elements into four.  estimator "zz" marks by the ZZ-type
     indicators (h_mode as in bc_zz_indicators); "residual" by the
     weighted-residual indicators mu(T)^2 (Appendix A's algorithm; always
-    with diam(T)), reported in the eta2 fields."""
+    with diam(T)), reported in the eta2 fields.  ss_order_edge /
+    ss_order_vertex: singular-rule orders of edge- and vertex-adjacent pairs
+    (0: ss_order)."""
     if estimator not in ("zz", "residual"):
         raise ValueError("estimator: 'zz' or 'residual'")
     verts = np.asarray(verts, dtype=np.float64)
@@ -86,7 +89,8 @@ def adaptive_capacity(verts, tris, steps: int = 5, theta: float = 0.5, precision
     out: List[Step] = []
     for level in range(steps + 1):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        prob = CapacityProblem(verts, tris, precision, far_order, ss_order)
+        prob = CapacityProblem(verts, tris, precision, far_order, ss_order, ss_order_edge=ss_order_edge,
+                               ss_order_vertex=ss_order_vertex)
         prob.allocate()  # allocation (tens of GB at large N) is not assembly time
         ev[0].record()
         prob.assemble()
