@@ -107,7 +107,8 @@ def near_pairs(verts, tris, near_factor: float):
     |c_i - c_j|^2 < near_factor^2 * max(diam_i^2, diam_j^2), with
     |d|^2 = (dx dx + dy dy) + dz dz.  Returned sorted by (i, j), both
     orders included.  (Mixed-precision bookkeeping, no arithmetic of the
-    method; parity unpinned beyond its definition.)"""
+    method.)  Pinned by hand-built pairs at known distances and by a k-d
+    tree search over the same definition."""
     g = element_geometry(verts, tris)
     c, d2 = g["centroid"], g["diam2"]
     tris = np.asarray(tris)

@@ -131,6 +131,47 @@ def test_assemble_parallel_equals_serial():
     assert np.array_equal(a, b)
 
 
+def test_near_pairs_hand_built():
+    """Two unit right triangles in the plane z = 0 and a third one far away:
+    the first two share no vertex, their centroids are a known distance
+    apart, and they are near exactly when that distance is below
+    near_factor times the common diameter sqrt(2)."""
+    for gap, factor, expect in ((0.5, 1.5, True), (0.5, 0.9, False), (3.0, 1.5, False), (0.6, 1.2, True),
+                                (2.0, 1.2, False)):
+        verts = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0],
+                          [1 + gap, 0, 0], [2 + gap, 0, 0], [1 + gap, 1, 0],
+                          [50, 0, 0], [51, 0, 0], [50, 1, 0]], dtype=np.float64)
+        tris = np.array([[0, 1, 2], [3, 4, 5], [6, 7, 8]])
+        # both centroids at height 1/3; x = 1/3 and 1 + gap + 1/3
+        dist = 1.0 + gap
+        assert (dist < factor * math.sqrt(2.0)) == expect
+        got = set(oracle.near_pairs(verts, tris, factor))
+        assert got == ({(0, 1), (1, 0)} if expect else set())
+
+
+def test_near_pairs_spatial_search():
+    """The pair list against a k-d tree search (scipy), a different
+    enumeration of the same definition, on meshes with graded elements."""
+    from scipy.spatial import cKDTree
+
+    for m in (synth.icosphere(2), synth.voxel_union(3, 0.4, 21)):
+        v, t = m.verts, m.tris
+        if m.name.startswith("voxel"):
+            v, t, _ = synth.refine_nvb(v, synth.init_reference_edges(v, t), [0, 5, 9], "bisec3")
+        g = oracle.element_geometry(v, t)
+        c, d2 = g["centroid"], g["diam2"]
+        tree = cKDTree(c)
+        cand = tree.query_pairs(1.5 * np.sqrt(d2.max()) * (1 + 1e-9))
+        shared = lambda i, j: bool(set(t[i].tolist()) & set(t[j].tolist()))  # noqa: E731
+        ref = set()
+        for i, j in cand:
+            dd = c[i] - c[j]
+            # on squares, as defined: lattice meshes have pairs exactly at the threshold
+            if (dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2] < 2.25 * max(d2[i], d2[j]) and not shared(i, j):
+                ref |= {(i, j), (j, i)}
+        assert set(oracle.near_pairs(v, t, 1.5)) == ref and len(ref) > 0
+
+
 def test_near_pairs_definition():
     m = synth.icosphere(2)
     g = oracle.element_geometry(m.verts, m.tris)
