@@ -112,17 +112,18 @@ typedef struct bc_assembly_opts {
                          rules (coincident 6, edge 4, vertex 2 subdomains);
                          1..8, default 4 */
   int32_t precision;  /* bc_precision */
-  int32_t far_low;    /* BC_MIXED with far_order 4: 1 integrates pairs of
-                         64-element blocks whose bounding boxes are at least
-                         8 largest element diameters apart with Radon's
-                         7-point rule of degree 5 on each triangle (49
-                         instead of 256 point pairs).  There its relative
-                         error is at most 6e-10, below the FP32 rounding of
-                         the stored entry (6e-8).  0: one far
-                         rule everywhere.  Ignored for far_order < 4; must
-                         be 0 for BC_FP64.  The tile lists it uses are built
-                         by bc_prepare, so bc_prepare must have run on the
-                         mesh workspace before bc_assemble. */
+  int32_t far_low;    /* far_order 4: 1 integrates pairs of 64-element
+                         blocks whose bounding boxes are far apart with
+                         Radon's 7-point rule of degree 5 on each triangle
+                         (49 instead of 256 point pairs): BC_MIXED from 8
+                         largest element diameters, where its relative error
+                         is at most 6e-10, below the FP32 rounding of the
+                         stored entry (6e-8); BC_FP64 from 32 diameters,
+                         where it is at most 1.4e-13.  0: one far rule
+                         everywhere.  Ignored for far_order < 4.  The tile
+                         lists it uses are built by bc_prepare, so
+                         bc_prepare must have run on the mesh workspace (with
+                         the same options) before bc_assemble. */
   double near_factor; /* BC_MIXED: pairs sharing no vertex with
                          |c_i - c_j|^2 < near_factor^2 max(diam_i, diam_j)^2
                          are computed in FP64 and corrected exactly; 0 = none.

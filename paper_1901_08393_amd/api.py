@@ -105,8 +105,8 @@ class CapacityProblem:
         self.device = torch.device(device)
         if near_factor is None:
             near_factor = 1.5 if precision == "mixed" else 0.0
-        if far_low is None:  # Radon's 7-point rule for distant blocks: mixed precision with the 4 x 4 far rule
-            far_low = precision == "mixed" and far_order == 4
+        if far_low is None:  # Radon's 7-point rule on distant blocks (8 diameters mixed, 32 FP64), 4 x 4 far rule
+            far_low = far_order == 4
         self.opts = _lib.bc_assembly_opts(far_order, ss_order, self.prec, int(bool(far_low)), float(near_factor),
                                           int(ss_order_edge), int(ss_order_vertex), int(ss_order_sliver), 0,
                                           float(sliver_ratio))

@@ -94,7 +94,6 @@ static bool opts_ok(const bc_assembly_opts *o) {
   if (o->ss_order_sliver > 0 && !(o->sliver_ratio > 0.0)) return false;
   if (o->precision != BC_FP64 && o->precision != BC_MIXED) return false;
   if (o->far_low != 0 && o->far_low != 1) return false;
-  if (o->far_low == 1 && o->precision != BC_MIXED) return false;
   if (!(o->near_factor >= 0.0) || !std::isfinite(o->near_factor)) return false;
   if (o->precision == BC_FP64 && o->near_factor != 0.0) return false;
   return true;

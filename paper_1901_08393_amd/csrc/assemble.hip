@@ -45,12 +45,13 @@ __device__ __forceinline__ double rsqrt64_far(double x) {
   return __builtin_fma(0.5 * y, e, y);
 }
 
-template <int Q>
-__global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, const double *__restrict__ qpS,
-                                               const double4 *__restrict__ cen4, const double *__restrict__ bbox,
-                                               int N, int64_t ld, double *__restrict__ V) {
-  int I, J;
-  tile_of(blockIdx.x, I, J);
+// One 64 x 64 tile (I, J), I <= J, with the Q-point rule whose points sit
+// STRIDE apart per element in the row table qpA ([N][STRIDE]) and in the
+// column table qpS ([(b*4+c)][N]).
+template <int Q, int STRIDE>
+__device__ __forceinline__ void far64_tile(int I, int J, const double4 *__restrict__ qpA,
+                                           const double *__restrict__ qpS, const double4 *__restrict__ cen4,
+                                           const double *__restrict__ bbox, int N, int64_t ld, double *__restrict__ V) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int j = J * 64 + lane;
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, 
   }
   const int i0 = I * 64 + w * 16;
   auto row = [&](auto SEP, int i) {
-    const double4 *xa = qpA + (size_t)i * kQMax;
+    const double4 *xa = qpA + (size_t)i * STRIDE;
     double acc = 0.0;
 #pragma unroll 2
     for (int a = 0; a < Q; ++a) {
@@ -104,6 +105,28 @@ __global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, 
     const int i = i0 + k;
     if (i >= N) break;
     if (sep) row(std::true_type{}, i); else row(std::false_type{}, i);
+  }
+}
+
+// One workgroup per tile of the upper block triangle, or (LIST) the tiles of
+// one list from bc_prepare, visited grid-stride.
+template <int Q, int STRIDE, bool LIST>
+__global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, const double *__restrict__ qpS,
+                                               const double4 *__restrict__ cen4, const double *__restrict__ bbox,
+                                               const int32_t *__restrict__ cnt, const int32_t *__restrict__ list,
+                                               int N, int64_t ld, double *__restrict__ V) {
+  int I, J;
+  if (!LIST) {
+    tile_of(blockIdx.x, I, J);
+    far64_tile<Q, STRIDE>(I, J, qpA, qpS, cen4, bbox, N, ld, V);
+    return;
+  }
+  const int nt = (int)far_tiles(N), n = min(*cnt, nt);
+  for (int q = blockIdx.x; q < n; q += gridDim.x) {
+    const int t = list[q];
+    if (t < 0 || t >= nt) continue;  // lists from another mesh: nothing out of range
+    tile_of(t, I, J);
+    far64_tile<Q, STRIDE>(I, J, qpA, qpS, cen4, bbox, N, ld, V);
   }
 }
 
@@ -466,9 +489,19 @@ static int device_cus() {
 template <int Q>
 static void far_launch(bool mixed, bool low_order, const MeshView &m, int N, int64_t ld, void *V, int tiles,
                        double scale, hipStream_t s) {
-  if (!mixed) {
-    hipLaunchKernelGGL(k_far64<Q>, dim3(tiles), dim3(kWG), 0, s, m.qpA64, m.qpS64, m.cen4, m.bbox, N, ld,
-                       static_cast<double *>(V));
+  if (!mixed && !(low_order && Q == 16)) {
+    hipLaunchKernelGGL((k_far64<Q, kQMax, false>), dim3(tiles), dim3(kWG), 0, s, m.qpA64, m.qpS64, m.cen4, m.bbox,
+                       (const int32_t *)nullptr, (const int32_t *)nullptr, N, ld, static_cast<double *>(V));
+  } else if (!mixed) {
+    // FP64 with Radon's rule on the tiles at least kSepFarLow64 diameters
+    // apart (class 2 of bc_prepare's lists); the 4 x 4 rule on the others
+    const int nt = (int)far_tiles(N);
+    const int g = std::min(nt, 4 * device_cus());
+    for (int c = 0; c < 2; ++c)
+      hipLaunchKernelGGL((k_far64<16, kQMax, true>), dim3(g), dim3(kWG), 0, s, m.qpA64, m.qpS64, m.cen4, m.bbox,
+                         m.tile_cnt + c, m.tile_list + (size_t)c * nt, N, ld, static_cast<double *>(V));
+    hipLaunchKernelGGL((k_far64<kQLow, kQLow, true>), dim3(g), dim3(kWG), 0, s, m.qpLA64, m.qpLS64, m.cen4, m.bbox,
+                       m.tile_cnt + 2, m.tile_list + 2 * (size_t)nt, N, ld, static_cast<double *>(V));
   } else if (Q == 16) {
     // Each tile class on its own kernel, over the tile lists of bc_prepare:
     // near and diagonal tiles on the vector ALU, separated ones on the
@@ -537,7 +570,7 @@ int launch_assemble(const void *mesh_ws, const int32_t *tris, const double *vert
   const int64_t T = (N + 63) / 64;
   const int tiles = (int)(T * (T + 1) / 2);
   const double scale = far32_scale(o.far_order);
-  const bool low = mixed && o.far_low == 1;
+  const bool low = o.far_low == 1;
   switch (o.far_order) {
     case 1: far_launch<1>(mixed, low, m, (int)N, ld, V, tiles, scale, s); break;
     case 2: far_launch<4>(mixed, low, m, (int)N, ld, V, tiles, scale, s); break;

@@ -179,19 +179,23 @@ constexpr int kTilesPerThread = 16;
 constexpr int kTileChunk = kWG * kTilesPerThread;
 static_assert(kTileChunk == 4096, "MeshLayout sizes the per-chunk counts for chunks of 4096 tiles");
 
-__device__ __forceinline__ int tile_class(const double *bbox, int t) {
+// Far-field tile classes: 0 near or diagonal (or a column block that is not
+// compact against the gap), 1 separated, 2 distant (Radon's rule: from
+// kSepFarLow diameters in mixed precision, kSepFarLow64 in FP64).
+__device__ __forceinline__ int tile_class(const double *bbox, int t, double sep_low) {
   int I, J;
   tile_of(t, I, J);
-  return (I == J || !far_separated(bbox, I, J) || !far_compact(bbox, I, J)) ? 0 : (far_low_order(bbox, I, J) ? 2 : 1);
+  return (I == J || !far_separated(bbox, I, J) || !far_compact(bbox, I, J)) ? 0
+                                                                            : (far_low_order(bbox, I, J, sep_low) ? 2 : 1);
 }
 
-__global__ __launch_bounds__(kWG) void k_tile_count(const double *__restrict__ bbox, int ntiles,
+__global__ __launch_bounds__(kWG) void k_tile_count(const double *__restrict__ bbox, int ntiles, double sep_low,
                                                     int32_t *__restrict__ chunk_cnt) {
   __shared__ int part[kTileClasses][kWG];
   int c3[kTileClasses] = {0, 0, 0};
   const int t0 = blockIdx.x * kTileChunk + (int)threadIdx.x * kTilesPerThread;
   for (int k = 0; k < kTilesPerThread; ++k)
-    if (t0 + k < ntiles) ++c3[tile_class(bbox, t0 + k)];
+    if (t0 + k < ntiles) ++c3[tile_class(bbox, t0 + k, sep_low)];
   for (int c = 0; c < kTileClasses; ++c) part[c][threadIdx.x] = c3[c];
   __syncthreads();
   for (int h = kWG / 2; h > 0; h >>= 1) {
@@ -202,7 +206,7 @@ __global__ __launch_bounds__(kWG) void k_tile_count(const double *__restrict__ b
   if (threadIdx.x < kTileClasses) chunk_cnt[blockIdx.x * kTileClasses + threadIdx.x] = part[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(kWG) void k_tile_emit(const double *__restrict__ bbox, int ntiles,
+__global__ __launch_bounds__(kWG) void k_tile_emit(const double *__restrict__ bbox, int ntiles, double sep_low,
                                                    const int32_t *__restrict__ chunk_cnt, int32_t *__restrict__ tile_cnt,
                                                    int32_t *__restrict__ tile_list) {
   __shared__ int pre[kTileClasses][kWG];
@@ -217,7 +221,7 @@ __global__ __launch_bounds__(kWG) void k_tile_emit(const double *__restrict__ bb
   int c3[kTileClasses] = {0, 0, 0};
   const int t0 = blockIdx.x * kTileChunk + tid * kTilesPerThread;
   for (int k = 0; k < kTilesPerThread; ++k) {
-    cls[k] = t0 + k < ntiles ? tile_class(bbox, t0 + k) : -1;
+    cls[k] = t0 + k < ntiles ? tile_class(bbox, t0 + k, sep_low) : -1;
     if (cls[k] >= 0) ++c3[cls[k]];
   }
   for (int c = 0; c < kTileClasses; ++c) pre[c][tid] = c3[c];
@@ -451,9 +455,10 @@ int launch_pattern(const double *verts, const int32_t *tris, int64_t N, double n
     hipLaunchKernelGGL(k_colpoints, dim3((unsigned)((N + kWG - 1) / kWG)), dim3(kWG), 0, s,
                        reinterpret_cast<const double *>(base + L.qpS64), reinterpret_cast<const double *>(base + L.qpLS64),
                        bbox, (int)N, reinterpret_cast<float *>(base + L.qpB16), reinterpret_cast<float *>(base + L.qpBL));
-    hipLaunchKernelGGL(k_tile_count, dim3(nchunk), dim3(kWG), 0, s, bbox, (int)ntiles, chunk_cnt);
-    hipLaunchKernelGGL(k_tile_emit, dim3(nchunk), dim3(kWG), 0, s, bbox, (int)ntiles, (const int32_t *)chunk_cnt,
-                       tile_cnt, tile_list);
+    const double sep_low = precision == BC_FP64 ? kSepFarLow64 : kSepFarLow;
+    hipLaunchKernelGGL(k_tile_count, dim3(nchunk), dim3(kWG), 0, s, bbox, (int)ntiles, sep_low, chunk_cnt);
+    hipLaunchKernelGGL(k_tile_emit, dim3(nchunk), dim3(kWG), 0, s, bbox, (int)ntiles, sep_low,
+                       (const int32_t *)chunk_cnt, tile_cnt, tile_list);
     if (hipGetLastError() != hipSuccess) return BC_EDEVICE;
     hipLaunchKernelGGL(k_pattern<false>, dim3(grid), dim3(kWG), 0, s, tri4, cen4, bbox, (int)N, nf2, rowcnt, kindcnt,
                        (const int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr);

@@ -111,8 +111,8 @@ def test_argument_errors_without_device(L):
     bad = _lib.bc_assembly_opts(9, 4, 0, 0, 0.0)
     assert L.bc_prepare(C.c_void_p(16), 8, C.c_void_p(16), 12, C.byref(bad), C.c_void_p(16), 1 << 30,
                         C.byref(info), null) == -1
-    for bad in (_lib.bc_assembly_opts(4, 4, 0, 1, 0.0), _lib.bc_assembly_opts(4, 4, 1, 2, 1.5)):
-        # the 7-point rule for distant blocks is a mixed-precision option (0 or 1)
+    for bad in (_lib.bc_assembly_opts(4, 4, 0, 2, 0.0), _lib.bc_assembly_opts(4, 4, 1, 2, 1.5)):
+        # the 7-point rule for distant blocks is an option (0 or 1)
         assert L.bc_prepare(C.c_void_p(16), 8, C.c_void_p(16), 12, C.byref(bad), C.c_void_p(16), 1 << 30,
                             C.byref(info), null) == -1
     # per-pair singular orders: orders within 0..8, a ratio with the sliver order, reserved 0

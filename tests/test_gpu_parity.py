@@ -233,6 +233,37 @@ def test_far_low_order_rule(api):
     assert 1.0 < cap_ref < 2.0
 
 
+def test_far_low_order_rule_fp64(api):
+    """FP64 with Radon's rule on tiles at least 32 element diameters apart
+    (two level-2 spheres 13 radii apart: box gap 11 = 34 diameters): those
+    entries within 2e-13 of the oracle's 4 x 4 entries and within 1e-14 of
+    its 7-point entries, the others within 1e-12; the capacity within 1e-12
+    of the oracle's 4 x 4 capacity."""
+    _flush("far low-order rule in FP64 (two spheres 13 apart)")
+    verts, tris = _two_spheres(13.0)
+    N = tris.shape[0]
+    half = N // 2
+    ref4 = oracle.assemble(verts, tris, 4, 4)
+    p = api.CapacityProblem(verts, tris, "fp64")
+    assert p.opts.far_low == 1
+    V = p.assemble().cpu().numpy()[:, :N]
+    cross = np.s_[:half, half:]
+    r4 = np.abs(V[cross] - ref4[cross]) / ref4[cross]
+    ref7 = _radon_cross(verts, tris, half)
+    r7 = np.abs(V[cross] - ref7) / ref7
+    _flush(f"  cross entries: vs 4x4 {r4.max():.1e}, vs Radon 7 {r7.max():.1e}")
+    assert r4.max() <= 2e-13 and r7.max() <= 1e-14
+    within = np.ones((N, N), dtype=bool)
+    within[cross] = False
+    within[half:, :half] = False
+    assert np.max(np.abs(V - ref4)[within] / np.abs(ref4[within])) <= 1e-12
+    assert not np.array_equal(V[cross], ref4[cross])  # the rule did change there
+    b = oracle.rhs(verts, tris)
+    cap_ref = oracle.capacity(oracle.solve_direct(ref4, b), b)
+    r = p.solve()
+    assert r.ok and abs(r.cap - cap_ref) <= 1e-12 * cap_ref, (r.cap, cap_ref)
+
+
 def _block_classes(verts, tris):
     """Tile class of every element pair from the 64-element blocks' vertex
     boxes, as bc_prepare classifies the far-field tiles: 2 where the boxes

@@ -253,6 +253,36 @@ def test_radon7_far_pair_accuracy():
     assert worst <= 1e-9, worst
 
 
+def test_radon7_accuracy_by_distance():
+    """The distance thresholds of Radon's rule: at 32 diameters (the FP64
+    far field's) its relative error against a 12 x 12 collapsed Gauss
+    reference is below 2e-13 on random pairs, and it falls like d^-6
+    (16 -> 32 diameters: a factor of at least 30)."""
+    rng = np.random.default_rng(5)
+    s7, t7, w7 = oracle.radon7()
+    s12, t12, w12 = oracle.triangle_rule(12)
+
+    def pair(Ta, Tb, s, t, w):
+        Xa = Ta[0] + s[:, None] * (Ta[1] - Ta[0]) + t[:, None] * (Ta[2] - Ta[0])
+        Xb = Tb[0] + s[:, None] * (Tb[1] - Tb[0]) + t[:, None] * (Tb[2] - Tb[0])
+        r = np.linalg.norm(Xa[:, None, :] - Xb[None, :, :], axis=2)
+        return np.sum(w[:, None] * w[None, :] / r)
+
+    worst = {}
+    for D in (16.0, 32.0):
+        wmax = 0.0
+        for _ in range(400):
+            Ta, Tb = rng.normal(size=(3, 3)), rng.normal(size=(3, 3))
+            d = max(np.linalg.norm(T[i] - T[k]) for T in (Ta, Tb) for i in range(3) for k in range(i))
+            Ta, Tb = Ta / d, Tb / d
+            u = rng.normal(size=3)
+            Tb = Tb - Tb.mean(0) + Ta.mean(0) + D * u / np.linalg.norm(u)
+            wmax = max(wmax, abs(pair(Ta, Tb, s7, t7, w7) / pair(Ta, Tb, s12, t12, w12) - 1))
+        worst[D] = wmax
+    assert worst[32.0] < 2e-13, worst
+    assert worst[16.0] / worst[32.0] > 30, worst
+
+
 def test_triangle_potential_far_point():
     A, B, D = P(0, 0, 0), P(1, 0, 0), P(0.5, 0, 0.7)
     x = P(0.2, 0.3, 1.5)[None]
