@@ -232,7 +232,8 @@ struct MatvecLayout {
 
 // Workspace of the dual-mesh system (bc_dual_*).
 struct DualLayout {
-  size_t area, diam, curl, f, mdiag, basis, wbas, ubas, w, t1, t2, t3, eta2, ones, bvec, yvec, dots, mv, total;
+  size_t area, diam, curl, f, mdiag, basis, wbas, ubas, w, t1, t2, t3, eta2, ones, bvec, yvec, dots, mv, gctl, H, G,
+      rot, total;
   int64_t nb;
   DualLayout(int64_t N, int64_t M, int32_t restart);
 };
@@ -588,7 +589,9 @@ int solve_capacity(int32_t precision);
 // BC_FP64 with nr = 1 or 3, BC_MIXED (FP32 matrix and vectors) with nr = 1,
 // kMatvecF32X64 (FP32 matrix, FP64 vectors and sums) with nr = 1 or 3.
 // ws: MatvecLayout(N, kind, nr).
-int launch_matvec(int32_t kind, const void *V, int64_t N, int nr, const void *x, void *y, void *ws, hipStream_t s);
+// skip (may be NULL): a device flag; the launches do nothing while it is set.
+int launch_matvec(int32_t kind, const void *V, int64_t N, int nr, const void *x, void *y, void *ws, hipStream_t s,
+                  const int32_t *skip = nullptr);
 int launch_dual_setup(const double *verts, const int32_t *tris, int64_t N, int64_t M, const int32_t *iptr,
                       const int32_t *itri, void *ws, int32_t restart, hipStream_t s);
 // V_bary: FP64 (precision BC_FP64) or FP32 plus the FP64 correction of the

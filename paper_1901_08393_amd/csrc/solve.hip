@@ -1060,8 +1060,12 @@ constexpr int32_t matvec_kind() {
   return sizeof(MT) == 8 ? BC_FP64 : (sizeof(XT) == 8 ? kMatvecF32X64 : BC_MIXED);
 }
 
+// skip (may be NULL): when *skip != 0 the launch does nothing (a product
+// queued behind a solver's stop decision on the device).
 template <typename MT, typename XT, int NR>
-__global__ __launch_bounds__(kSolveWG) void k_matvec_pad(const XT *__restrict__ x, int64_t N, char *ws) {
+__global__ __launch_bounds__(kSolveWG) void k_matvec_pad(const XT *__restrict__ x, int64_t N, char *ws,
+                                                         const int32_t *__restrict__ skip) {
+  if (skip && *skip) return;
   const MatvecLayout Lay(N, matvec_kind<MT, XT>(), NR);
   XT *xp = reinterpret_cast<XT *>(ws + Lay.xpad);
   for (int64_t i = (int64_t)blockIdx.x * kSolveWG + threadIdx.x; i < NR * Lay.ld; i += (int64_t)gridDim.x * kSolveWG) {
@@ -1083,7 +1087,8 @@ __device__ __forceinline__ HalfPlan matvec_plan(const MatvecLayout &Lay, int64_t
 // NR x 8 row sums stay in registers.
 template <typename MT, typename XT, int NR>
 __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) void k_matvec_part(
-    const MT *__restrict__ V, int64_t N, char *ws) {
+    const MT *__restrict__ V, int64_t N, char *ws, const int32_t *__restrict__ skip) {
+  if (skip && *skip) return;
   static_assert(NR == 1 || sizeof(XT) == 8, "several vectors: FP64 vectors only");
   using L = typename std::conditional<
       sizeof(MT) == sizeof(XT), typename std::conditional<NR == 1, Load16<MT, XT>, LoadD1>::type,
@@ -1100,7 +1105,9 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
 }
 
 template <typename MT, typename XT, int NR>
-__global__ __launch_bounds__(kSolveWG) void k_matvec_gather(int64_t N, const char *ws, XT *__restrict__ y) {
+__global__ __launch_bounds__(kSolveWG) void k_matvec_gather(int64_t N, const char *ws, XT *__restrict__ y,
+                                                            const int32_t *__restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double s_part[16 * 64];
   __shared__ double s_band[kMaxBand];
   const MatvecLayout Lay(N, matvec_kind<MT, XT>(), NR);
@@ -1119,21 +1126,25 @@ __global__ __launch_bounds__(kSolveWG) void k_matvec_gather(int64_t N, const cha
 }
 
 template <typename MT, typename XT, int NR>
-static void matvec_launch(const void *V, int64_t N, const void *x, void *y, char *w, hipStream_t s) {
+static void matvec_launch(const void *V, int64_t N, const void *x, void *y, char *w, const int32_t *skip,
+                          hipStream_t s) {
   const int G = solve_workgroups(N);
-  hipLaunchKernelGGL((k_matvec_pad<MT, XT, NR>), dim3(16), dim3(kSolveWG), 0, s, static_cast<const XT *>(x), N, w);
-  hipLaunchKernelGGL((k_matvec_part<MT, XT, NR>), dim3(G), dim3(kSolveWG), 0, s, static_cast<const MT *>(V), N, w);
+  hipLaunchKernelGGL((k_matvec_pad<MT, XT, NR>), dim3(16), dim3(kSolveWG), 0, s, static_cast<const XT *>(x), N, w,
+                     skip);
+  hipLaunchKernelGGL((k_matvec_part<MT, XT, NR>), dim3(G), dim3(kSolveWG), 0, s, static_cast<const MT *>(V), N, w,
+                     skip);
   hipLaunchKernelGGL((k_matvec_gather<MT, XT, NR>), dim3(G), dim3(kSolveWG), 0, s, N, (const char *)w,
-                     static_cast<XT *>(y));
+                     static_cast<XT *>(y), skip);
 }
 
-int launch_matvec(int32_t kind, const void *V, int64_t N, int nr, const void *x, void *y, void *ws, hipStream_t s) {
+int launch_matvec(int32_t kind, const void *V, int64_t N, int nr, const void *x, void *y, void *ws, hipStream_t s,
+                  const int32_t *skip) {
   char *w = static_cast<char *>(ws);
-  if (kind == BC_FP64 && nr == 1) matvec_launch<double, double, 1>(V, N, x, y, w, s);
-  else if (kind == BC_FP64 && nr == 3) matvec_launch<double, double, 3>(V, N, x, y, w, s);
-  else if (kind == BC_MIXED && nr == 1) matvec_launch<float, float, 1>(V, N, x, y, w, s);
-  else if (kind == kMatvecF32X64 && nr == 1) matvec_launch<float, double, 1>(V, N, x, y, w, s);
-  else if (kind == kMatvecF32X64 && nr == 3) matvec_launch<float, double, 3>(V, N, x, y, w, s);
+  if (kind == BC_FP64 && nr == 1) matvec_launch<double, double, 1>(V, N, x, y, w, skip, s);
+  else if (kind == BC_FP64 && nr == 3) matvec_launch<double, double, 3>(V, N, x, y, w, skip, s);
+  else if (kind == BC_MIXED && nr == 1) matvec_launch<float, float, 1>(V, N, x, y, w, skip, s);
+  else if (kind == kMatvecF32X64 && nr == 1) matvec_launch<float, double, 1>(V, N, x, y, w, skip, s);
+  else if (kind == kMatvecF32X64 && nr == 3) matvec_launch<float, double, 3>(V, N, x, y, w, skip, s);
   else return BC_EINVAL;
   return hipGetLastError() == hipSuccess ? BC_OK : BC_EDEVICE;
 }
