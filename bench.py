@@ -951,23 +951,5 @@ def main():
     print(json.dumps(out))
 
 
-def release_device():
-    """Drop the library's device buffers, wait for the device and empty
-    torch's cache before the interpreter exits, so that no device work or
-    allocation is left to the runtime's teardown (profilers intercept it)."""
-    import gc
-
-    sys.stdout.flush()
-    if "torch" in sys.modules:
-        torch = sys.modules["torch"]
-        gc.collect()
-        if torch.cuda.is_initialized():
-            torch.cuda.synchronize()
-            torch.cuda.empty_cache()
-            torch.cuda.synchronize()
-
-
 if __name__ == "__main__":
-    rc = main()
-    release_device()
-    sys.exit(rc if isinstance(rc, int) else 0)
+    main()

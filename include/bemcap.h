@@ -269,12 +269,14 @@ int32_t bc_solve(const void *d_V, int64_t N, int32_t precision,
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): bc_solve
- * with the solver workspace in a 96 MiB device array inside the library
- * instead of a caller buffer, enough for any N up to 32000 in either
- * precision; larger systems return BC_ENOMEM (use bc_solve).  Same kernels,
- * arithmetic and results as bc_solve.  Allocates nothing: each GPU holds its
- * own copy of the array until the process ends, and the first call on a
- * device looks up that copy's address.  Every call on one GPU shares the
+ * with the solver workspace in a 96 MiB device array instead of a caller
+ * buffer, enough for any N up to 32000 in either precision; larger systems
+ * return BC_ENOMEM (use bc_solve).  Same kernels, arithmetic and results as
+ * bc_solve.  Exported by the companion library libbemcap_static.so (link
+ * -lbemcap_static -lbemcap), which holds the array, so that only processes
+ * that load it pay for it.  Allocates nothing: each GPU that runs the
+ * companion library holds its own copy of the array until the process ends,
+ * and the first call on a device looks up that copy's address.  Every call on one GPU shares the
  * array, so calls that overlap on one GPU (other streams, other threads)
  * race; the caller serialises them.  ASYNC. */
 int32_t bc_solve_static(const void *d_V, int64_t N, int32_t precision,

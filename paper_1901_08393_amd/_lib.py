@@ -1,5 +1,6 @@
-"""ctypes binding of libbemcap.so: the C ABI declared in include/bemcap.h,
-function for function, with argument marshalling only.
+"""ctypes binding of libbemcap.so (and of libbemcap_static.so, which holds
+bc_solve_static): the C ABI declared in include/bemcap.h, function for
+function, with argument marshalling only.
 
 The library is built in-tree (``python -m paper_1901_08393_amd.build``).  If
 it is missing, :func:`lib` raises: there is no fallback implementation.
@@ -12,6 +13,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbemcap.so")
+STATIC_PATH = os.path.join(HERE, "libbemcap_static.so")
 
 BC_OK = 0
 BC_EINVAL = -1
@@ -90,7 +92,6 @@ SIGNATURES = {
     "bc_solve_workspace_bytes": (SZ, [I64, I32]),
     "bc_solve_workgroups": (I32, [I64]),
     "bc_solve": (I32, [P, I64, I32, P, I64, P, P, C.POINTER(bc_solve_opts), P, SZ, P, P]),
-    "bc_solve_static": (I32, [P, I64, I32, P, I64, P, P, C.POINTER(bc_solve_opts), P, P]),
     "bc_batch_scratch_bytes": (SZ, [I32]),
     "bc_solve_batched": (I32, [I32, C.POINTER(bc_system), C.POINTER(bc_solve_opts), I32, P, SZ, P]),
     "bc_solve_capacity": (I32, [I32]),
@@ -107,7 +108,13 @@ SIGNATURES = {
     "bc_dual_zz": (I32, [P, SZ, P, I64, I64, I32, P, I32, P, P]),
 }
 
+# the allocation-free solve lives in libbemcap_static.so (with its device array)
+STATIC_SIGNATURES = {
+    "bc_solve_static": (I32, [P, I64, I32, P, I64, P, P, C.POINTER(bc_solve_opts), P, P]),
+}
+
 _LIB = None
+_STATIC = None
 
 
 class BemcapError(RuntimeError):
@@ -130,6 +137,23 @@ def lib():
             f.argtypes = args
         _LIB = L
     return _LIB
+
+
+def lib_static():
+    """Load libbemcap_static.so (once, after libbemcap.so, which it links
+    against) and declare bc_solve_static."""
+    global _STATIC
+    if _STATIC is None:
+        lib()
+        if not os.path.exists(STATIC_PATH):
+            raise RuntimeError(f"{STATIC_PATH} is missing: build it with `python -m paper_1901_08393_amd.build`")
+        L = C.CDLL(STATIC_PATH)
+        for name, (res, args) in STATIC_SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _STATIC = L
+    return _STATIC
 
 
 def check(fn: str, status: int) -> int:

@@ -1,4 +1,11 @@
-"""Build libbemcap.so for gfx950 with hipcc (in-tree, no JIT cache).
+"""Build libbemcap.so, and libbemcap_static.so beside it, for gfx950 with
+hipcc (in-tree, no JIT cache).
+
+libbemcap_static.so holds only bc_solve_static and the device array that is
+its workspace; it links against libbemcap.so.  Keeping the array out of the
+main library means that a process holds its 96 MiB per GPU only when it
+loads the companion library, i.e. when it uses the allocation-free entry
+point.
 
     python -m paper_1901_08393_amd.build [--jobs N]
 """
@@ -15,7 +22,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbemcap.so")
-SOURCES = ["abi.hip", "geometry.hip", "assemble.hip", "solve.hip", "zz.hip", "dual.hip", "residual.hip", "solve_static.hip"]
+LIB_STATIC = os.path.join(HERE, "libbemcap_static.so")
+SOURCES = ["abi.hip", "geometry.hip", "assemble.hip", "solve.hip", "zz.hip", "dual.hip", "residual.hip"]
+SOURCES_STATIC = ["solve_static.hip"]
 ARCH = os.environ.get("BEMCAP_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -36,19 +45,26 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1, 16)
-    with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+def _link(objs, out: str, extra=()) -> None:
+    tmp = out + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, *extra, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+        raise RuntimeError(f"link of {os.path.basename(out)} failed:\n{r.stderr}")
+    os.replace(tmp, out)
+
+
+def build(jobs: int | None = None, verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = SOURCES + SOURCES_STATIC
+    jobs = jobs or min(len(srcs), os.cpu_count() or 1, 16)
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = dict(zip(srcs, ex.map(_compile, srcs)))
+    _link([objs[s] for s in SOURCES], LIB)
+    # the companion library finds libbemcap.so next to itself
+    _link([objs[s] for s in SOURCES_STATIC], LIB_STATIC, ["-L" + HERE, "-l:libbemcap.so", "-Wl,-rpath,$ORIGIN"])
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {LIB_STATIC}")
     return LIB
 
 

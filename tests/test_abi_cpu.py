@@ -34,9 +34,12 @@ def test_every_declared_symbol_exported(L):
 
     names = declared_functions()
     assert len(names) >= 15
+    S = _lib.lib_static()
     for n in names:
-        assert hasattr(L, n), n
-    assert set(names) == set(_lib.SIGNATURES)
+        assert hasattr(S if n in _lib.STATIC_SIGNATURES else L, n), n
+    assert set(names) == set(_lib.SIGNATURES) | set(_lib.STATIC_SIGNATURES)
+    # the main library does not carry the allocation-free entry point's array
+    assert not hasattr(L, "bc_solve_static")
 
 
 def test_version_and_status_strings(L):

@@ -1,6 +1,6 @@
-"""bc_solve_static (the solve whose workspace is the library's own device
-array, for callers that cannot allocate) against bc_solve, through the C
-ABI: two calls in a row, the second on a smaller system, each bitwise equal
+"""bc_solve_static (the solve whose workspace is a device array of
+libbemcap_static.so, for callers that cannot allocate) against bc_solve,
+through the C ABI: two calls in a row, the second on a smaller system, each bitwise equal
 to bc_solve's result (same kernels, same fixed-order reductions), in both
 precisions; and the size limit returns BC_ENOMEM."""
 
@@ -26,7 +26,7 @@ def _run(L, _lib, api, p, static):
     res = torch.zeros(C.sizeof(_lib.bc_result), dtype=torch.uint8, device="cuda")
     stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
     if static:
-        st = L.bc_solve_static(_ptr(p.V), p.N, p.prec, _ptr(p.pattern), p.nnz, _ptr(p.area), _ptr(sigma), C.byref(o),
+        st = _lib.lib_static().bc_solve_static(_ptr(p.V), p.N, p.prec, _ptr(p.pattern), p.nnz, _ptr(p.area), _ptr(sigma), C.byref(o),
                                _ptr(res), stream)
     else:
         nb = L.bc_solve_workspace_bytes(p.N, p.prec)
@@ -58,9 +58,9 @@ def test_static_solve_equals_solve(prec):
 def test_static_solve_size_limit():
     from paper_1901_08393_amd import _lib, api
 
-    L = _lib.lib()
+    S = _lib.lib_static()
     o = api.default_solve_opts("mixed")
     dummy = torch.zeros(8, dtype=torch.float64, device="cuda")
-    st = L.bc_solve_static(_ptr(dummy), 40000, _lib.BC_MIXED, _ptr(dummy), 40000, _ptr(dummy), _ptr(dummy),
+    st = S.bc_solve_static(_ptr(dummy), 40000, _lib.BC_MIXED, _ptr(dummy), 40000, _ptr(dummy), _ptr(dummy),
                            C.byref(o), _ptr(dummy), C.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert st == _lib.BC_ENOMEM
