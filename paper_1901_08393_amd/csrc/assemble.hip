@@ -30,19 +30,23 @@ namespace bc {
 // ----------------------------------------------------------------- far field
 // FP64 far field: V_ij = (1/4pi) sum_a sum_b W_a W_b / |x_a - y_b| over the
 // tensor rule's points (absolute coordinates, FP64), the inverse square root
-// refined by one Newton step (rsqrt64_far).  Tiles at least kSepFar block
+// refined by one Newton step (rsqrt64_far2).  Tiles at least kSepFar block
 // diameters apart expand -r^2 = -|x|^2 - |y|^2 + 2 x.y about the column
 // element's centroid (as in the FP32 kernel); closer tiles form differences.
-// Inverse square root for the FP64 far field: the hardware estimate and one
-// Newton step y <- y + (y/2)(1 - x y^2).  Measured over log-uniform inputs:
-// at most 37 ulp (4.2e-15 relative), mean -1.5e-16.  A far entry sums 256 such
-// terms with positive weights, so its relative error stays below 5e-15; the
-// cubic step of rsqrt64 (kept for the singular and near rules) costs two more
-// FP64 operations per point pair, about 14% of this kernel.
-__device__ __forceinline__ double rsqrt64_far(double x) {
+// Inverse square root for the FP64 far field: the hardware estimate y and one
+// Newton step, y (3 - x y^2) / 2, returned without the factor 1/2, which the
+// column weights carry: two multiplications and one FMA.  Measured over
+// log-uniform inputs against 1/sqrt(x): at most 38 ulp (4.3e-15 relative),
+// mean -1.5e-16, the same as the form y + (y/2)(1 - x y^2), which needs one
+// FMA more.  A far entry sums 256 such terms with positive weights, so its
+// relative error stays below 5e-15.  The kernel is bound by instruction
+// issue: per point pair four FP64 operations for -r^2, the estimate (3.2
+// FMA-equivalents, measured), three for the Newton step and one to accumulate.
+// (The cubic step of rsqrt64, kept for the singular and near rules, costs two
+// more FP64 operations per point pair.)
+__device__ __forceinline__ double rsqrt64_far2(double x) {
   const double y = __builtin_amdgcn_rsq(x);
-  const double e = __builtin_fma(-(x * y), y, 1.0);
-  return __builtin_fma(0.5 * y, e, y);
+  return y * __builtin_fma(-(x * y), y, 3.0);
 }
 
 // One 64 x 64 tile (I, J), I <= J, with the Q-point rule whose points sit
@@ -68,7 +72,7 @@ __device__ __forceinline__ void far64_tile(int I, int J, const double4 *__restri
     yx[b] = qpS[(size_t)(b * 4 + 0) * N + jj] - ox;
     yy[b] = qpS[(size_t)(b * 4 + 1) * N + jj] - oy;
     yz[b] = qpS[(size_t)(b * 4 + 2) * N + jj] - oz;
-    yw[b] = qpS[(size_t)(b * 4 + 3) * N + jj];
+    yw[b] = 0.5 * qpS[(size_t)(b * 4 + 3) * N + jj];  // the Newton step's 1/2
     yn[b] = -(yx[b] * yx[b] + yy[b] * yy[b] + yz[b] * yz[b]);
   }
   const int i0 = I * 64 + w * 16;
@@ -91,7 +95,7 @@ __device__ __forceinline__ void far64_tile(int I, int J, const double4 *__restri
           const double dx = ex - yx[b], dy = ey - yy[b], dz = ez - yz[b];
           c = -(dx * dx + dy * dy + dz * dz);
         }
-        s = __builtin_fma(yw[b], rsqrt64_far(-c), s);
+        s = __builtin_fma(yw[b], rsqrt64_far2(-c), s);
       }
       acc = __builtin_fma(p.w, s, acc);
     }
