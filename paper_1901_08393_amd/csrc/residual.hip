@@ -64,11 +64,11 @@ struct ResLayout {
   }
 };
 
-__device__ __forceinline__ double rsqrt64_res(double x) {
-  // hardware estimate and one Newton step, as in the FP64 far field
+__device__ __forceinline__ double rsqrt64_res2(double x) {
+  // hardware estimate and one Newton step, as in the FP64 far field: returns
+  // y (3 - x y^2), twice the refined value (the caller halves the weight)
   const double y = __builtin_amdgcn_rsq(x);
-  const double e = __builtin_fma(-(x * y), y, 1.0);
-  return __builtin_fma(0.5 * y, e, y);
+  return y * __builtin_fma(-(x * y), y, 3.0);
 }
 
 // part[c][i][k] = sum_{j in chunk c, no vertex shared with i} Phi_j
@@ -98,10 +98,11 @@ __global__ __launch_bounds__(kWG) void k_res_far(const double4 *__restrict__ qpA
 #pragma unroll 4
     for (int b = 0; b < Q; ++b) {
       const double4 y = yb[b];
+      const double hw = 0.5 * y.w;  // the Newton step's 1/2
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
         const double dx = xx[a] - y.x, dy = xy[a] - y.y, dz = xz[a] - y.z;
-        s[a] = __builtin_fma(y.w, rsqrt64_res(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx))), s[a]);
+        s[a] = __builtin_fma(hw, rsqrt64_res2(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx))), s[a]);
       }
     }
     double t0 = 0.0, t1 = 0.0, t2 = 0.0;

@@ -184,3 +184,36 @@ def test_near_pairs_definition():
             inside = d < 1.5 * max(g["diam"][i], g["diam"][j])
             expect = inside and (i, j) not in touching and i != j
             assert ((i, j) in near) == expect
+
+
+def test_per_pair_orders_select_by_class_and_shape():
+    """Singular-rule orders chosen per touching pair (oracle.SSOrders): every
+    entry of the matrix equals, bitwise, the entry of the uniform-order
+    matrix whose order that pair calls for: 6 / 5 / 3 points for pairs that
+    share 3 / 2 / 1 vertices, at least 8 where either element is thin
+    (diam^2 > 12 |T|); regular entries do not depend on the orders.  Shared
+    vertices and thinness are counted here directly from the triangles."""
+    h = synth.convex_hull(14, 0, min_angle=0.0)  # facets down to a few degrees
+    verts, tris, _ = synth.refine_uniform(h.verts, synth.init_reference_edges(h.verts, h.tris), 1)
+    verts, tris = np.asarray(verts), np.asarray(tris)
+    P = verts[tris]
+    d2 = np.max(np.sum((P[:, [1, 2, 0]] - P) ** 2, axis=2), axis=1)
+    area = 0.5 * np.linalg.norm(np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]), axis=1)
+    thin = d2 > 12.0 * area
+    assert thin.any() and (~thin).any()
+    got = oracle.assemble(verts, tris, 4, oracle.SSOrders(6, 5, 3, sliver=8, sliver_ratio=12.0))
+    uniform = {n: oracle.assemble(verts, tris, 4, n) for n in (3, 5, 6, 8)}
+    N = len(tris)
+    seen = set()
+    for i in range(N):
+        for j in range(N):
+            shared = len(set(tris[i].tolist()) & set(tris[j].tolist()))
+            if shared == 0:
+                assert got[i, j] == uniform[3][i, j] == uniform[8][i, j]
+                continue
+            n = {3: 6, 2: 5, 1: 3}[shared]
+            if thin[i] or thin[j]:
+                n = max(n, 8)
+            seen.add(n)
+            assert got[i, j] == uniform[n][i, j], (i, j, shared, n)
+    assert seen == {3, 5, 6, 8}
