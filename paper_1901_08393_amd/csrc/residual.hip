@@ -26,8 +26,8 @@
 // pattern entry, on the canonical pair (min, max) so that both orders use the
 // same points as the pair's matrix entry), and k_res_finish sums the chunks
 // and the row's pattern entries in a fixed order.  ALU-bound like the
-// assembly: N^2 Q^2 point pairs (all ordered pairs), about 14 FP64 VALU
-// slots each.
+// assembly: N^2 Q^2 point pairs (all ordered pairs), each about ten FP64
+// instructions and one inverse square root (instruction counters).
 #include "bc_internal.h"
 
 namespace bc {
