@@ -228,6 +228,14 @@ typedef struct bc_solve_opts {
                          once the same bound, estimated from its recurrence
                          residual, is below 0.3 cap_rtol.  Must be finite
                          and < 1. */
+  int32_t spin_limit; /* 0: default (2^22 polls of about 64 clocks each).
+                         > 0: bound on the polls of every cross-workgroup
+                         wait of the solver; a wait that exceeds it ends the
+                         solve with BC_ETIMEOUT (every workgroup leaves its
+                         loop, nothing hangs).  A small value forces that
+                         path, for tests of failure handling.  Must be
+                         >= 0. */
+  int32_t reserved;   /* must be 0 */
 } bc_solve_opts;
 
 /* Device-side result, written when a system finishes. */

@@ -45,7 +45,7 @@ class bc_pattern_info(C.Structure):
 class bc_solve_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("inner_rtol", C.c_double), ("max_iter", C.c_int32),
                 ("max_outer", C.c_int32), ("jacobi", C.c_int32), ("x0_given", C.c_int32),
-                ("cap_rtol", C.c_double)]
+                ("cap_rtol", C.c_double), ("spin_limit", C.c_int32), ("reserved", C.c_int32)]
 
 
 class bc_result(C.Structure):

@@ -259,7 +259,8 @@ size_t bc_batch_scratch_bytes(int32_t n_sys) { return n_sys < 1 ? 0 : align256(s
 static bool solve_opts_ok(const bc_solve_opts *o) {
   return o && o->rtol >= 0.0 && std::isfinite(o->rtol) && o->inner_rtol > 0.0 && o->inner_rtol < 1.0 &&
          o->max_iter >= 1 && o->max_outer >= 1 && (o->jacobi == 0 || o->jacobi == 1) &&
-         (o->x0_given == 0 || o->x0_given == 1) && o->cap_rtol >= 0.0 && o->cap_rtol < 1.0;
+         (o->x0_given == 0 || o->x0_given == 1) && o->cap_rtol >= 0.0 && o->cap_rtol < 1.0 && o->spin_limit >= 0 &&
+         o->reserved == 0;
 }
 
 static SolveParams params_of(const bc_solve_opts *o, int32_t budget, int n_sys) {
@@ -272,7 +273,7 @@ static SolveParams params_of(const bc_solve_opts *o, int32_t budget, int n_sys) 
   p.jacobi = o->jacobi;
   p.x0_given = o->x0_given;
   p.iter_budget = budget;
-  p.spin_limit = 1u << 22;
+  p.spin_limit = o->spin_limit > 0 ? (uint32_t)o->spin_limit : 1u << 22;
   p.n_sys = n_sys;
   return p;
 }

@@ -141,6 +141,10 @@ def test_argument_errors_without_device(L):
         so = _lib.bc_solve_opts(1e-12, 1e-11, 10, 1, 1, 0, cap_rtol)
         assert L.bc_solve(C.c_void_p(16), 12, 0, null, 0, C.c_void_p(16), C.c_void_p(16), C.byref(so),
                           C.c_void_p(16), 1 << 30, C.c_void_p(16), null) == -1
+    for spin, res in ((-1, 0), (0, 1)):  # negative spin limit, reserved field set
+        so = _lib.bc_solve_opts(1e-12, 1e-11, 10, 1, 1, 0, 0.0, spin, res)
+        assert L.bc_solve(C.c_void_p(16), 12, 0, null, 0, C.c_void_p(16), C.c_void_p(16), C.byref(so),
+                          C.c_void_p(16), 1 << 30, C.c_void_p(16), null) == -1
     assert L.bc_zz_indicators(null, 12, null, null, 12, null, 0, null, null) == -1
     assert L.bc_capacity(null, null, 5, null, null) == -1
     assert L.bc_matvec(C.c_void_p(16), 100, 0, 2, C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), 1 << 30,

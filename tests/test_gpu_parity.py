@@ -648,6 +648,27 @@ def test_no_convergence_and_breakdown_status(api):
     assert r.status == _lib.BC_EBREAKDOWN
 
 
+def test_barrier_time_out_status(api):
+    """The solver's time-out path, forced from the host: with a spin limit of
+    one poll on every cross-workgroup wait the solve ends with BC_ETIMEOUT
+    (every workgroup leaves its loop, so the call returns), and the same
+    workspace then solves normally, bitwise as before.  N = 5120 gives 64
+    workgroups, whose arrivals at a barrier are microseconds apart, far more
+    than one poll of about 64 clocks."""
+    from paper_1901_08393_amd import _lib
+
+    m = synth.icosphere(4, 0.9)
+    for prec in ("fp64", "mixed"):
+        _flush(f"time-out path, {prec}")
+        p = api.CapacityProblem(m.verts, m.tris, prec)
+        p.assemble()
+        r0 = p.solve()
+        rt = p.solve(spin_limit=1)
+        assert rt.status == _lib.BC_ETIMEOUT, rt
+        r1 = p.solve()
+        assert r0.ok and r1.ok and r1.cap == r0.cap and r1.iters == r0.iters
+
+
 def test_nested_cube_capacity_monotone(api):
     caps = []
     for n in (2, 4, 8):
