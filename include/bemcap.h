@@ -215,18 +215,29 @@ typedef struct bc_solve_opts {
   int32_t max_outer;  /* cap on FP64 residual evaluations */
   int32_t jacobi;     /* 1: diagonal (Jacobi) preconditioning */
   int32_t x0_given;   /* 1: start from the caller's sigma; 0: from zero */
-  double cap_rtol;    /* 0: off.  > 0: also stop once ||sigma|| ||r|| <=
-                         cap_rtol |b^T sigma| at an FP64 residual r = b -
-                         A sigma.  For symmetric A the capacity error of an
-                         iterate is exactly 4pi (Cap* - Cap) = sigma*^T r
-                         (the algebraic form of the identity behind
-                         Section 2.7's Proposition), so the left side bounds
-                         Cap's relative algebraic error to first order;
-                         solving to a capacity tolerance needs no tighter
-                         residual than this.  The first inner solve from a
-                         zero start, where no such target exists yet, stops
-                         once the same bound, estimated from its recurrence
-                         residual, is below 0.3 cap_rtol.  Must be finite
+  double cap_rtol;    /* 0: off.  > 0: also stop once the capacity's
+                         algebraic error is estimated below cap_rtol
+                         (relative).  The capacity is reported as
+                         (1/4pi) J(sigma), J(x) = 2 b^T x - x^T A x
+                         = b^T x + x^T r with r = b - A x the last FP64
+                         residual; for symmetric positive definite A it falls
+                         short of the exact discrete capacity by exactly
+                         (1/4pi) ||sigma* - sigma||_A^2 (the algebraic form of
+                         Section 2.7's Proposition: the capacity error is the
+                         squared energy error), so the capacity converges
+                         twice as fast as the residual.  Each inner CG run
+                         estimates that error from its steps: the sum of its
+                         last four terms alpha_j gamma_j is the drop of the
+                         squared energy error over those steps, a lower
+                         bound on the error four steps back and above the
+                         current error once that error halves over four
+                         steps (Hestenes and Stiefel); the run stops once
+                         the estimate is below 0.3 cap_rtol J; the
+                         following FP64 residual step stops the solve once
+                         it is below cap_rtol J.  Independently, the solve
+                         also stops once ||sigma|| ||r|| <= cap_rtol
+                         |b^T sigma|, a first-order bound that needs no CG
+                         run (a converged initial guess).  Must be finite
                          and < 1. */
   int32_t spin_limit; /* 0: default (2^22 polls of about 64 clocks each).
                          > 0: bound on the polls of every cross-workgroup
@@ -240,17 +251,23 @@ typedef struct bc_solve_opts {
 
 /* Device-side result, written when a system finishes. */
 typedef struct bc_result {
-  double cap;          /* (1/4pi) sum_i sigma_i |T_i|, FP64, fixed-order sum */
+  double cap;          /* (1/4pi) (b^T sigma + sigma^T r), b = |T|, r the
+                          last FP64 residual: (1/4pi) sum_i sigma_i |T_i| at
+                          the exact discrete solution, and below it by
+                          (1/4pi) ||sigma* - sigma||_A^2 otherwise (see
+                          bc_solve_opts.cap_rtol); FP64, fixed-order sums */
   double rel_residual; /* ||b - A sigma|| / ||b|| at the last FP64 residual */
   int32_t iters;       /* CG iterations (matrix products with V) */
   int32_t outer;       /* FP64 residual evaluations */
   int32_t status;      /* BC_OK, BC_ENOCONV, BC_EBREAKDOWN, BC_ETIMEOUT, or
                           BC_RUNNING while a chunked batch is unfinished */
   int32_t precision;
-  double cap_bound;    /* ||sigma|| ||b - A sigma|| / |b^T sigma| at the last
-                          FP64 residual: the first-order bound on Cap's
-                          relative error from the unsolved residual (see
-                          bc_solve_opts.cap_rtol); 0 if not finished */
+  double cap_bound;    /* estimate of Cap's relative algebraic error: with
+                          cap_rtol > 0 after a CG run, the last run's
+                          estimate of ||sigma* - sigma||_A^2 / J(sigma);
+                          otherwise ||sigma|| ||b - A sigma|| / |b^T sigma|,
+                          a first-order bound (see bc_solve_opts.cap_rtol);
+                          0 if not finished */
 } bc_result;
 
 /* Workspace of one system's solver state.  Depends on N and precision. */

@@ -321,6 +321,7 @@ int solve_one(const void *d_V, int64_t N, int32_t precision, const void *d_patte
   SolveLayout L(N, precision);
   // the descriptor lives after the control block, inside the workspace
   const size_t desc_off = sizeof(SolveCtl);
+  static_assert(((sizeof(SolveCtl) + 63) & ~size_t(63)) + sizeof(SysDesc) <= 1024, "control block of 1 KB");
   if (ws_bytes < L.total) return BC_ENOMEM;
   bc_system sys{d_V, d_pattern, d_area, d_sigma, d_ws, d_result, N, nnz, precision, 1, 0, 0};
   SysDesc d;

@@ -250,8 +250,13 @@ struct SolveCtl {
   int32_t inner;
   int32_t status;
   uint32_t epoch;
-  int32_t pad;
+  int32_t hs_n;  // terms alpha_j gamma_j of the current inner solve so far
   double bnorm, rnorm, scale, gamma, eta, alpha, beta, itol;
+  // capacity stop (cap_rtol > 0): the last four terms alpha_j gamma_j of the
+  // current inner solve, their running sum, the functional J = b^T x + x^T r
+  // at its start, the scale rnorm^2 of its terms, and the estimate of the
+  // capacity's algebraic error (J units) it ended with (< 0: none)
+  double hs[4], hs_sum, jres, est;
 };
 
 // Solver descriptor built by the host for each system of a launch.

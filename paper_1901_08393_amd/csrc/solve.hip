@@ -9,12 +9,16 @@
 //
 //   RESID  r = b - A x in FP64 (A = V, plus the FP64 sparse correction of
 //          touching/near entries in mixed precision); stop if
-//          ||r|| <= rtol ||b||, or, with a capacity tolerance, if
-//          ||x|| ||r|| <= cap_rtol |b^T x| (for symmetric A,
-//          4pi (Cap* - Cap) = x*^T r, the algebraic form of the identity
-//          in the proof of Section 2.7's Proposition); else start an
-//          inner CG on A d = r / ||r||.  The first inner CG from x = 0
-//          also stops on that bound, estimated from its own recurrence.
+//          ||r|| <= rtol ||b||, or, with a capacity tolerance, once the
+//          capacity's algebraic error is estimated below it.  The capacity
+//          is reported as (1/4pi) J(x), J(x) = 2 b^T x - x^T A x =
+//          b^T x + x^T r, which for symmetric positive definite A
+//          falls short of J(x*) = b^T x* by exactly ||x* - x||_A^2 (the
+//          algebraic form of Section 2.7's Proposition: the capacity error is
+//          the squared energy error).  The estimate of that error comes from
+//          the last inner CG (QUAD in cg_loop); ||x|| ||r|| <= cap_rtol
+//          |b^T x|, which bounds 4pi (Cap* - b^T x / 4pi) = x*^T r to first
+//          order, also stops.  Else start an inner CG on A d = r / ||r||.
 //   CG     preconditioned CG in the Chronopoulos-Gear arrangement: the two
 //          inner products of an iteration are reduced together, so an
 //          iteration costs one product with V and two cross-workgroup
@@ -589,7 +593,6 @@ struct CGCtx {
   gptr<MT> vr, vu, vp, vs, vd, idg, rp, cp;
   gptr<BarSlot> slots;
   gptr<BarRel> rel;
-  gptr<const double> b;
   HalfPlan H;
   int r0, r1, G, rank;
   uint32_t spin_limit;
@@ -597,19 +600,27 @@ struct CGCtx {
 };
 struct CGState {
   double alpha, beta, gamma, eta, itol;
-  double capt;  // capacity stop of a first inner solve (CAP): 0.3 cap_rtol / ||b||
+  // capacity stop (QUAD): the last four terms alpha_j gamma_j, the sum of
+  // all of them, their scale rnorm^2, J at the inner start, 0.3 cap_rtol, and
+  // the error estimate at exit (< 0: none yet)
+  double hs[4], hs_sum, hs_scale, jres, hs_tol, est;
+  int32_t hs_n;
   int32_t iters, inner, budget;
   uint32_t epoch;
   int32_t exit;  // 0 budget used up, 1 inner solve done, 2 breakdown, 3 aborted
 };
 
-// CAP: the first inner solve from x = 0 with a capacity tolerance, which the
-// outer residual cannot turn into a residual target (x = 0 gives no Cap).
-// Then x = ||b|| d and r = ||b|| r_inner, so the first-order bound
-// ||x|| ||r|| / |b^T x| is ||b|| ||d|| ||r_inner|| / |b^T d|, formed from
-// two more sums per iteration; the solve stops once it is below 0.3 cap_rtol
-// (the outer step checks it again with the true residual).
-template <typename MT, bool CAP>
+// QUAD: the capacity stop.  The inner problem A d = r_hat (||r_hat|| = 1)
+// starts from d = 0, and CG's step j lowers the squared energy norm of its
+// error by exactly alpha_j gamma_j (gamma_j = r_j^T M^-1 r_j), so the error
+// of the iterate four steps back is the sum of the last four terms plus the
+// current iterate's error: the sum is a lower bound on the former and above
+// the latter once the error halves over four steps (Hestenes and Stiefel;
+// the estimate stays reliable in finite precision).  Scaled by rnorm^2 it is the algebraic error of the capacity
+// functional J(x) = 2 b^T x - x^T A x at x + rnorm d, whose value is J at the
+// inner start plus rnorm^2 times the sum of all terms.  The inner solve stops
+// once the estimate is at most 0.3 cap_rtol J.
+template <typename MT, bool QUAD>
 __device__ __noinline__ void cg_loop(lptr<CGCtx<MT>> Cp, lptr<CGState> Sp, lptr<MT> lbuf, lptr<MT> lpart,
                                      lptr<MT> band, lptr<double> lred, lptr<int> lflag) {
   using VT = MT;
@@ -631,8 +642,13 @@ __device__ __noinline__ void cg_loop(lptr<CGCtx<MT>> Cp, lptr<CGState> Sp, lptr<
   double alpha = uniform_f64(Sp->alpha), beta = uniform_f64(Sp->beta), gamma = uniform_f64(Sp->gamma);
   double eta = uniform_f64(Sp->eta);
   const double itol = uniform_f64(Sp->itol);
-  const double capt = CAP ? uniform_f64(Sp->capt) : 0.0;
-  const gptr<const double> b = CAP ? uniform_ptr(Cp->b) : nullptr;
+  double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0, hs_sum = 0.0, hs_scale = 0.0, jres = 0.0, hs_tol = 0.0;
+  int hs_n = 0;
+  if (QUAD) {
+    h0 = uniform_f64(Sp->hs[0]); h1 = uniform_f64(Sp->hs[1]); h2 = uniform_f64(Sp->hs[2]); h3 = uniform_f64(Sp->hs[3]);
+    hs_sum = uniform_f64(Sp->hs_sum); hs_scale = uniform_f64(Sp->hs_scale); jres = uniform_f64(Sp->jres);
+    hs_tol = uniform_f64(Sp->hs_tol); hs_n = uniform32(Sp->hs_n);
+  }
   int iters = uniform32(Sp->iters), inner = uniform32(Sp->inner), budget = uniform32(Sp->budget);
   const int t = threadIdx.x;
   int ex = 0;
@@ -642,7 +658,7 @@ __device__ __noinline__ void cg_loop(lptr<CGCtx<MT>> Cp, lptr<CGState> Sp, lptr<
     // w = V u of the last product
     half_gather_body<VT>(H, r0, r1, rp, cp, lpart, band);
     const VT a = (VT)alpha, bt = (VT)beta;
-    double pru = 0.0, prr = 0.0, pdd = 0.0, pbd = 0.0;
+    double pru = 0.0, prr = 0.0;
     // the lane's first row, formed anew in every iteration: kept across the
     // product instead, the vectors' addresses would be spilled
     int i0 = r0 + t;
@@ -654,10 +670,6 @@ __device__ __noinline__ void cg_loop(lptr<CGCtx<MT>> Cp, lptr<CGState> Sp, lptr<
       vs[i] = si;
       const VT di = vd[i] + a * pi;
       vd[i] = di;
-      if (CAP) {
-        pdd += (double)di * (double)di;
-        pbd += b[i] * (double)di;
-      }
       const VT ri = vr[i] - a * si;
       vr[i] = ri;
       const VT ui = idg[i] * ri;
@@ -666,15 +678,7 @@ __device__ __noinline__ void cg_loop(lptr<CGCtx<MT>> Cp, lptr<CGState> Sp, lptr<
       prr += (double)ri * (double)ri;
     }
     double gnew, rr;
-    bool cap_met = false;
-    if (CAP) {
-      const double v[4] = {pru, prr, pdd, pbd};
-      double tot[4];
-      if (!sys_sync_body<4>(bar, v, tot, lred, lflag)) { ex = 3; break; }
-      gnew = tot[0];
-      rr = tot[1];
-      cap_met = sqrt(rr * tot[2]) <= capt * fabs(tot[3]);
-    } else {
+    {
       const double v[2] = {pru, prr};
       double tot[2];
       if (!sys_sync_body<2>(bar, v, tot, lred, lflag)) { ex = 3; break; }
@@ -682,6 +686,15 @@ __device__ __noinline__ void cg_loop(lptr<CGCtx<MT>> Cp, lptr<CGState> Sp, lptr<
       rr = tot[1];
     }
     inner += 1;
+    bool cap_met = false;
+    if (QUAD) {
+      // the step just taken (with alpha, gamma) lowered the error by alpha gamma
+      const double term = alpha * gamma;
+      h0 = h1; h1 = h2; h2 = h3; h3 = term;
+      hs_n += 1;
+      hs_sum += term;
+      if (hs_n >= 4) cap_met = hs_scale * (((h0 + h1) + h2) + h3) <= hs_tol * (jres + hs_scale * hs_sum);
+    }
     if (!(sqrt(rr) > itol) || cap_met || iters >= max_iter) { ex = 1; break; }
     double pwu = 0.0;
     half_product<MT, VT, VT, true, true>(V, vu, H, rp, cp, lbuf, pwu);
@@ -703,6 +716,11 @@ __device__ __noinline__ void cg_loop(lptr<CGCtx<MT>> Cp, lptr<CGState> Sp, lptr<
   if (t == 0) {
     Sp->alpha = alpha; Sp->beta = beta; Sp->gamma = gamma; Sp->eta = eta;
     Sp->iters = iters; Sp->inner = inner; Sp->budget = budget; Sp->epoch = bar.epoch; Sp->exit = ex;
+    if (QUAD) {
+      Sp->hs[0] = h0; Sp->hs[1] = h1; Sp->hs[2] = h2; Sp->hs[3] = h3;
+      Sp->hs_sum = hs_sum; Sp->hs_n = hs_n;
+      Sp->est = hs_n >= 4 ? hs_scale * (((h0 + h1) + h2) + h3) : -1.0;
+    }
   }
   __syncthreads();
 }
@@ -762,15 +780,21 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
   SysBar bar{reinterpret_cast<gptr<BarSlot>>(ws + Lay.slots), reinterpret_cast<gptr<BarRel>>(ws + Lay.rel), G, rank, 0u,
              P.spin_limit};
 
-  int32_t phase, iters, outer, inner;
+  int32_t phase, iters, outer, inner, hs_n;
   double bnorm, rnorm, scale, gamma, eta, alpha, beta, itol;
+  double hs[4], hs_sum, jres, est;  // the capacity stop's state (QUAD in cg_loop)
   if (S.start) {
-    phase = PH_INIT; iters = 0; outer = 0; inner = 0;
+    phase = PH_INIT; iters = 0; outer = 0; inner = 0; hs_n = 0;
     bnorm = rnorm = scale = gamma = eta = alpha = beta = itol = 0.0;
+    hs[0] = hs[1] = hs[2] = hs[3] = hs_sum = jres = 0.0;
+    est = -1.0;
   } else {
     phase = ctl->phase; iters = ctl->iters; outer = ctl->outer; inner = ctl->inner; bar.epoch = ctl->epoch;
     bnorm = ctl->bnorm; rnorm = ctl->rnorm; scale = ctl->scale; gamma = ctl->gamma; eta = ctl->eta;
     alpha = ctl->alpha; beta = ctl->beta; itol = ctl->itol;
+    hs_n = ctl->hs_n;
+    for (int q = 0; q < 4; ++q) hs[q] = ctl->hs[q];
+    hs_sum = ctl->hs_sum; jres = ctl->jres; est = ctl->est;
   }
   if (phase == PH_DONE) return;
   int32_t status = BC_OK;
@@ -782,7 +806,6 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
     s_cg.vr = vr; s_cg.vu = vu; s_cg.vp = vp; s_cg.vs = vs; s_cg.vd = vd; s_cg.idg = idg;
     s_cg.rp = rpV; s_cg.cp = cpV;
     s_cg.slots = bar.slots; s_cg.rel = bar.rel;
-    s_cg.b = b;
     s_cg.H = H;
     s_cg.r0 = r0; s_cg.r1 = r1; s_cg.G = G; s_cg.rank = rank;
     s_cg.spin_limit = P.spin_limit;
@@ -820,6 +843,9 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
         if (!sys_sync<1>(bar, none, dummy, l_red, l_flag)) { aborted = true; break; }
         half_gather<double>(HR, r0, r1, rpD, cpD, (lptr<double>)s_part, (lptr<double>)s_band);
       }
+      // sums: ||r||^2, then ||b||^2 at the first step and x^T r after it,
+      // ||x||^2, b^T x
+      const bool first = outer == 0;
       double pr = 0.0, pb = 0.0, pxx = 0.0, pbx = 0.0;
       for (int i = r0 + t; i < r1; i += kSolveWG) {
         double acc = zero_x ? 0.0 : s_band[i - r0];
@@ -829,25 +855,31 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
         const double ri = b[i] - acc, xi = x64[i];
         r64[i] = ri;
         pr = __builtin_fma(ri, ri, pr);
-        pb = __builtin_fma(b[i], b[i], pb);
+        pb = first ? __builtin_fma(b[i], b[i], pb) : __builtin_fma(xi, ri, pb);
         pxx = __builtin_fma(xi, xi, pxx);
         pbx = __builtin_fma(b[i], xi, pbx);
       }
       // the residual norm to reach: rtol ||b||, or with a capacity tolerance
       // the norm at which ||x|| ||r|| / |b^T x|, the first-order bound on
       // Cap's relative error (4pi (Cap* - Cap) = x*^T r), is cap_rtol
-      double target;
+      // and the capacity functional J(x) = 2 b^T x - x^T A x = b^T x + x^T r
+      // (at the first step x = 0, or a caller's guess, for which b^T x
+      // serves as the scale of the capacity stop)
+      double target, jcur;
       {
         const double v[4] = {pr, pb, pxx, pbx};
         double tot[4];
         if (!sys_sync<4>(bar, v, tot, l_red, l_flag)) { aborted = true; break; }
-        if (outer == 0) bnorm = sqrt(tot[1]);
+        if (first) bnorm = sqrt(tot[1]);
         rnorm = sqrt(tot[0]);
+        jcur = tot[3] + (first ? 0.0 : tot[1]);
         target = P.rtol * bnorm;
         if (P.cap_rtol > 0.0 && tot[2] > 0.0) target = fmax(target, P.cap_rtol * fabs(tot[3]) / sqrt(tot[2]));
       }
       outer += 1;
-      if (!(rnorm > target)) { status = BC_OK; phase = PH_DONE; continue; }
+      // the capacity stop: the last inner solve's estimate of J's algebraic error
+      const bool quad_met = P.cap_rtol > 0.0 && est >= 0.0 && est <= P.cap_rtol * fabs(jcur);
+      if (!(rnorm > target) || quad_met) { status = BC_OK; phase = PH_DONE; continue; }
       if (outer > P.max_outer || iters >= P.max_iter) { status = BC_ENOCONV; phase = PH_DONE; continue; }
       scale = 1.0 / rnorm;
       // the inner solve need not go further than the outer target asks
@@ -879,21 +911,28 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       if (!(eta > 0.0)) { status = BC_EBREAKDOWN; phase = PH_DONE; continue; }
       alpha = gamma / eta;
       beta = 0.0;
+      // a new inner solve: its terms alpha_j gamma_j start afresh
+      hs[0] = hs[1] = hs[2] = hs[3] = hs_sum = 0.0;
+      hs_n = 0;
+      jres = jcur;
+      est = -1.0;
       phase = PH_CG;
       continue;
     }
     if (phase == PH_CG) {
-      // the first inner solve from x = 0 also stops on the capacity bound,
-      // when that can come before the residual target (everything here is
-      // kept in the control block, so a resumed launch decides the same)
-      const bool cap_first = outer == 1 && !P.x0_given && P.cap_rtol > 0.0 && 0.3 * P.cap_rtol > itol;
+      // with a capacity tolerance every inner solve also stops on its estimate
+      // of the capacity's algebraic error (everything here is kept in the
+      // control block, so a resumed launch decides the same)
+      const bool quad = P.cap_rtol > 0.0;
       if (t == 0) {
         s_st.alpha = alpha; s_st.beta = beta; s_st.gamma = gamma; s_st.eta = eta; s_st.itol = itol;
-        s_st.capt = cap_first ? 0.3 * P.cap_rtol / rnorm : 0.0;
+        for (int q = 0; q < 4; ++q) s_st.hs[q] = hs[q];
+        s_st.hs_sum = hs_sum; s_st.hs_n = hs_n; s_st.hs_scale = rnorm * rnorm; s_st.jres = jres;
+        s_st.hs_tol = 0.3 * P.cap_rtol; s_st.est = est;
         s_st.iters = iters; s_st.inner = inner; s_st.budget = budget; s_st.epoch = bar.epoch;
       }
       __syncthreads();
-      if (cap_first)
+      if (quad)
         cg_loop<MT, true>((lptr<CGCtx<MT>>)&s_cg, (lptr<CGState>)&s_st, (lptr<VT>)s_buf, (lptr<VT>)s_part,
                           (lptr<VT>)s_band, l_red, l_flag);
       else
@@ -903,11 +942,15 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       eta = uniform_f64(s_st.eta);
       iters = uniform32(s_st.iters); inner = uniform32(s_st.inner); budget = uniform32(s_st.budget);
       bar.epoch = (unsigned)uniform32((int)s_st.epoch);
+      if (quad) {
+        for (int q = 0; q < 4; ++q) hs[q] = uniform_f64(s_st.hs[q]);
+        hs_sum = uniform_f64(s_st.hs_sum); hs_n = uniform32(s_st.hs_n); est = uniform_f64(s_st.est);
+      }
       const int ex = uniform32(s_st.exit);
       __syncthreads();  // the state is read before a later phase writes it again
       if (ex == 0) break;  // this launch's budget is used up; the next one resumes here
       if (ex == 3) { aborted = true; break; }
-      if (ex == 2) { status = BC_EBREAKDOWN; phase = PH_DONE; continue; }
+      if (ex == 2) { status = BC_EBREAKDOWN; est = -1.0; phase = PH_DONE; continue; }
       phase = PH_UPDATE;
       continue;
     }
@@ -918,21 +961,29 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       phase = PH_RESID;
       continue;
     }
-    // PH_DONE: sigma = x, Cap = (1/4pi) sum x_i |T_i|
-    double pc = 0.0, pxx = 0.0;
+    // PH_DONE: sigma = x, Cap = (1/4pi) J(x) with J(x) = b^T x + x^T r
+    // (r = b - A x, the residual of the last step, which is x's), which equals
+    // (1/4pi) sum x_i |T_i| at the exact solution and differs from it by
+    // (1/4pi) ||x* - x||_A^2 >= 0 for every x
+    double pc = 0.0, pxx = 0.0, pxr = 0.0;
     for (int i = r0 + t; i < r1; i += kSolveWG) {
       const double xi = x64[i];
       sigma[i] = xi;
       pc = __builtin_fma(xi, b[i], pc);
       pxx = __builtin_fma(xi, xi, pxx);
+      pxr = __builtin_fma(xi, r64[i], pxr);
     }
     double cap, cap_bound;
     {
-      const double v[2] = {pc, pxx};
-      double tot[2];
-      if (!sys_sync<2>(bar, v, tot, l_red, l_flag)) { aborted = true; break; }
-      cap = tot[0] * kInv4Pi;
-      cap_bound = tot[0] != 0.0 ? sqrt(tot[1]) * rnorm / fabs(tot[0]) : 0.0;
+      const double v[3] = {pc, pxx, pxr};
+      double tot[3];
+      if (!sys_sync<3>(bar, v, tot, l_red, l_flag)) { aborted = true; break; }
+      const double J = tot[0] + tot[2];
+      cap = J * kInv4Pi;
+      if (P.cap_rtol > 0.0 && est >= 0.0)
+        cap_bound = J != 0.0 ? est / fabs(J) : 0.0;  // the capacity stop's estimate
+      else
+        cap_bound = tot[0] != 0.0 ? sqrt(tot[1]) * rnorm / fabs(tot[0]) : 0.0;  // first-order bound
     }
     if (rank == 0 && t == 0) {
       result->cap = cap;
@@ -958,6 +1009,9 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       ctl->phase = phase; ctl->iters = iters; ctl->outer = outer; ctl->inner = inner; ctl->epoch = bar.epoch;
       ctl->bnorm = bnorm; ctl->rnorm = rnorm; ctl->scale = scale; ctl->gamma = gamma; ctl->eta = eta;
       ctl->alpha = alpha; ctl->beta = beta; ctl->itol = itol;
+      ctl->hs_n = hs_n;
+      for (int q = 0; q < 4; ++q) ctl->hs[q] = hs[q];
+      ctl->hs_sum = hs_sum; ctl->jres = jres; ctl->est = est;
       result->iters = iters;
       result->outer = outer;
       result->status = BC_RUNNING;

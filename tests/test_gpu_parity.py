@@ -469,11 +469,16 @@ def test_solve_mixed_capacity(api, name):
 
 @pytest.mark.parametrize("name", ["cube768", "voxel", "hull"])
 def test_capacity_tolerance_stop(api, name):
-    """Stopping on the capacity bound (bc_solve_opts.cap_rtol): for symmetric
-    V, 4pi (Cap* - Cap) = sigma*^T r exactly, so ||sigma|| ||r|| / |b^T sigma|
-    bounds the relative capacity error to first order.  The identity is
-    checked with the oracle's matrix and solution, the bound against the
-    oracle's capacity."""
+    """Stopping on the capacity tolerance (bc_solve_opts.cap_rtol).  The
+    capacity is reported as (1/4pi) J(sigma), J(x) = 2 b^T x - x^T V x, which
+    for symmetric positive definite V falls short of the exact discrete
+    capacity by exactly (1/4pi) ||sigma* - sigma||_V^2 (the algebraic form
+    of Section 2.7's Proposition: the capacity error is the squared energy
+    error).  That identity is checked with the oracle's matrix and solution;
+    the error is non-negative (the capacity is approached from below), below
+    the tolerance, and the solver's own estimate of it (from the terms
+    alpha_j gamma_j of its last CG run) is reported and is below the
+    tolerance too."""
     _flush(f"capacity tolerance stop {name}")
     m = MESHES[name]()
     cap_ref, Vref, b, xref = _oracle_cap(name)
@@ -484,33 +489,31 @@ def test_capacity_tolerance_stop(api, name):
     assert r.ok, r
     assert 0.0 < r.cap_bound <= 1e-6, r
     assert r.iters < tight.iters, (r.iters, tight.iters)
-    # the first inner solve (from x = 0) stops on the bound estimated from
-    # its recurrence, so one FP64 residual after it confirms the stop
+    # the first inner solve (from x = 0) stops on its estimate, and one FP64
+    # residual after it confirms the stop
     assert r.outer == 2, r
     sig = p.sigma.cpu().numpy()
-    resid = b - Vref @ sig
+    e = xref - sig
     lhs = 4 * math.pi * (cap_ref - r.cap)
-    rhs = float(xref @ resid)
-    assert abs(lhs - rhs) <= 1e-3 * abs(rhs) + 1e-13 * cap_ref, (lhs, rhs)
-    bound = np.linalg.norm(sig) * np.linalg.norm(resid) / abs(b @ sig)
-    assert abs(bound - r.cap_bound) <= 1e-6 * bound, (bound, r.cap_bound)
-    err = abs(r.cap - cap_ref) / cap_ref
-    assert err <= 1.001 * r.cap_bound, (err, r.cap_bound)
-    _flush(f"  iters {r.iters} (tight {tight.iters}) err {err:.2e} bound {r.cap_bound:.2e}")
+    rhs = float(e @ (Vref @ e))
+    assert abs(lhs - rhs) <= 1e-3 * rhs + 1e-13 * cap_ref, (lhs, rhs)
+    err = (cap_ref - r.cap) / cap_ref
+    assert -1e-14 <= err <= 1e-6, (err, r.cap_bound)
+    _flush(f"  iters {r.iters} (tight {tight.iters}) err {err:.2e} estimate {r.cap_bound:.2e}")
     # mixed precision at the capacity tolerance of the benchmark
     pm = api.CapacityProblem(m.verts, m.tris, "mixed")
     pm.assemble()
     rm_tight = pm.solve()
     rm = pm.solve(cap_rtol=1e-8)
-    assert rm.ok and rm.cap_bound <= 1e-8 and rm.iters <= rm_tight.iters, (rm, rm_tight)
+    assert rm.ok and rm.cap_bound <= 1e-8 and rm.iters < rm_tight.iters, (rm, rm_tight)
     assert abs(rm.cap - cap_ref) / cap_ref <= 1e-8
-    # mixed precision where the first inner solve's own capacity stop applies
-    # (0.3 cap_rtol above the inner tolerance): the FP32 CG with the bound
-    # estimated from its recurrence stops it, one FP64 residual confirms
+    _flush(f"  mixed: iters {rm.iters} (tight {rm_tight.iters}) err {abs(rm.cap - cap_ref) / cap_ref:.2e}")
+    # mixed with a looser tolerance and a tighter inner floor: the first inner
+    # solve stops on its estimate, one FP64 residual confirms
     re = pm.solve(rtol=0.0, inner_rtol=1e-7, cap_rtol=1e-6)
     assert re.ok and re.outer == 2 and 0.0 < re.cap_bound <= 1e-6, re
-    assert re.iters < rm_tight.iters
-    assert abs(re.cap - cap_ref) / cap_ref <= re.cap_bound + 1e-8, (re, cap_ref)
+    assert re.iters < rm.iters
+    assert abs(re.cap - cap_ref) / cap_ref <= 1e-6 + 1e-8, (re, cap_ref)
 
 
 def test_capacity_reduction(api):
