@@ -5,9 +5,11 @@ pair classification, dense assembly of V, the persistent Krylov solve with
 FP64 refinement, the FP64 capacity reduction, and the ZZ indicators.
 Workload: the sphere of radius r ~ U[0.5, 2] (seed 2) as a level-5
 icosphere, N = 20480 triangles, mixed precision (FP32 V, FP32 CG, FP64
-residual refinement), solved until the first-order bound on the capacity's
-relative algebraic error, ||sigma|| ||r|| / |b^T sigma|, is below 1e-8
-(--cap-rtol); the result is checked against a tight FP64 solve.
+residual refinement), solved until the estimate of the capacity's relative
+algebraic error is below 1e-8 (--cap-rtol; the capacity is reported as
+(b^T sigma + sigma^T r) / 4pi, whose error is the squared energy error of
+sigma); the result is checked against a tight FP64 solve and the stored
+oracle result.
 
     python bench.py [--steps K] [--warmup W] [--precision mixed|fp64]
 
@@ -692,7 +694,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--cap-rtol", type=float, default=1e-8,
-                    help="stop the solve once the first-order bound on Cap's relative error is below this "
+                    help="stop the solve once the estimate of Cap's relative algebraic error is below this "
                          "(bc_solve_opts.cap_rtol; 0: residual tolerance only)")
     ap.add_argument("--level", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
