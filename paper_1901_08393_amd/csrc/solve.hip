@@ -882,8 +882,12 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       if (!(rnorm > target) || quad_met) { status = BC_OK; phase = PH_DONE; continue; }
       if (outer > P.max_outer || iters >= P.max_iter) { status = BC_ENOCONV; phase = PH_DONE; continue; }
       scale = 1.0 / rnorm;
-      // the inner solve need not go further than the outer target asks
-      itol = fmax(P.inner_rtol, 0.3 * target / rnorm);
+      // the inner solve need not go further than the outer target asks; with
+      // a capacity tolerance its own estimate usually stops it first, and the
+      // residual floor is a tenth of inner_rtol, so that a run is not cut
+      // short (and another FP64 residual step taken) just before the estimate
+      // would have stopped it
+      itol = fmax(P.cap_rtol > 0.0 ? 0.1 * P.inner_rtol : P.inner_rtol, 0.3 * target / rnorm);
       // inner start: r = r64 / ||r64||, u = M^-1 r, d = p = s = 0
       double pru = 0.0;
       for (int i = r0 + t; i < r1; i += kSolveWG) {
