@@ -182,6 +182,32 @@ def solver_traffic(products: int):
     return rec.get("hbm_bytes")
 
 
+def assembly_traffic():
+    """HBM bytes of one mixed-precision bc_assemble call on the headline mesh
+    (its kernels' FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy) from
+    the committed counter summary, or None if the assembly sources changed
+    since the counters were taken."""
+    import hashlib
+    import re
+
+    path = os.path.join(ROOT, "profiles", "sphere_L5_mixed_hbm_counters.md")
+    try:
+        m = re.search(r"```json\n(.*?)\n```", open(path).read(), flags=re.S)
+        data = json.loads(m.group(1))
+    except Exception:
+        return None
+    h = hashlib.sha256()
+    for f in ASSEMBLY_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    rec = data.get("bc_assemble_mixed", {})
+    if rec.get("source_sha") != h.hexdigest()[:16]:
+        return None
+    return rec.get("hbm_bytes")
+
+
+ASSEMBLY_SOURCES = ("paper_1901_08393_amd/csrc/assemble.hip", "paper_1901_08393_amd/csrc/geometry.hip",
+                    "paper_1901_08393_amd/csrc/bc_internal.h")
+
 ROW_BLOCK = 128  # rows per block of the solver's symmetric product
 
 
@@ -803,8 +829,9 @@ def main():
                   "kernel": f"k_solve<{'float' if elem == 4 else 'double'}>",
                   "per_launch_bytes": solve_bytes, "products_per_launch": streams,
                   "avg_launch_ms": round(mean("solve_ms"), 4)}
+    asm_traffic = assembly_traffic() if a.precision == "mixed" and N == 20480 else None
     roof_asm = {"bound": "alu", "achieved": round(asm_tflops, 2), "peak": asm_peak, "unit": "TFLOP/s",
-                "frac": round(asm_tflops / asm_peak, 4), "traffic": None,
+                "frac": round(asm_tflops / asm_peak, 4), "traffic": asm_traffic,
                 "kernel": "bc_assemble (k_pattern emit + k_far + k_sparse + k_pad)",
                 "per_launch_flops": point_pairs * FLOPS_PER_POINT_PAIR,
                 "point_pairs_per_pair": round(point_pairs / pairs, 2),
