@@ -325,11 +325,18 @@ __device__ __forceinline__ void far32m_tile(int I, int J, const double4 *__restr
     wt[a] = fw.w[a];
   }
   float S[4] = {0.f, 0.f, 0.f, 0.f};
+  // the column point relative to the column block's box centre, and its
+  // squared norm (tabulated by bc_prepare); the next point's pair is loaded
+  // while this one is used, so that no iteration waits for its own loads
+  auto col_b = [&](int b) { return k < 3 ? qpB[(size_t)(b * 4 + k) * N + jb] : 1.0f; };
+  auto col_n = [&](int b) { return qpB[(size_t)(b * 4 + 3) * N + jb]; };
+  float bv_next = col_b(0), yn_next = col_n(0);
   for (int b = 0; b < QP; ++b) {
-    // the column point relative to the column block's box centre, and its
-    // squared norm (tabulated by bc_prepare)
-    const float bv = k < 3 ? qpB[(size_t)(b * 4 + k) * N + jb] : 1.0f;
-    const float yn = qpB[(size_t)(b * 4 + 3) * N + jb];
+    const float bv = bv_next, yn = yn_next;
+    if (b + 1 < QP) {
+      bv_next = col_b(b + 1);
+      yn_next = col_n(b + 1);
+    }
     const float wb = fw.w[b];
     const v4f C = {-yn, -yn, -yn, -yn};
     float Sb[4] = {0.f, 0.f, 0.f, 0.f};
