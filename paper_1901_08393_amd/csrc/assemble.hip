@@ -285,7 +285,9 @@ struct FarWeights {
 };
 
 // FP32 far field of separated tiles (I < J, at least kSepFar block diameters
-// apart) on the matrix cores.  A wavefront takes 16 x 16 element pairs; for
+// apart) on the matrix cores.  A wavefront takes 16 rows of a tile and its
+// four 16-column sub-blocks in turn (the row operands, which depend on the
+// column block only, are formed once for the four); for each sub-block and
 // each pair of points (a, b) one v_mfma_f32_16x16x4f32 forms
 //   -r^2 = 2 e.y - |e|^2 - |y|^2        for all 16 x 16 element pairs,
 // A[i][k] = (2 e_x, 2 e_y, 2 e_z, -|e|^2) of point a of row element i,
@@ -302,73 +304,84 @@ struct FarWeights {
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <int QP>
-__device__ __forceinline__ void far32m_tile(int I, int J, const double4 *__restrict__ qpA,
+__device__ __forceinline__ void far32m_tile(int I, int J, int rsb, const double4 *__restrict__ qpA,
                                             const float *__restrict__ qpB, const FarWeights &fw,
                                             const double *__restrict__ area, const double *__restrict__ bbox,
                                             const double *__restrict__ rsqb, double scale, int N, int64_t ld,
                                             float *__restrict__ V) {
   static_assert(QP == 16 || QP == kQLow, "far rule of 16 or kQLow points");
   const int lane = (int)__lane_id();
-  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  const int i0 = I * 64 + 16 * (w >> 2), j0 = J * 64 + 16 * (w & 3);
-  if (i0 >= N || j0 >= N) return;  // the wavefront's block lies past the end (wavefront-uniform)
+  const int i0 = I * 64 + 16 * rsb;
+  if (i0 >= N) return;  // the wavefront's rows lie past the end (wavefront-uniform)
   const int k = lane >> 4;
-  const int ia = min(i0 + (lane & 15), N - 1), jb = min(j0 + (lane & 15), N - 1);
+  const int ia = min(i0 + (lane & 15), N - 1);
   const double *bj = bbox + 8 * J;
   const double fx = 0.5 * (bj[0] + bj[3]), fy = 0.5 * (bj[1] + bj[4]), fz = 0.5 * (bj[2] + bj[5]);
-  float av[QP], wt[QP];
+  // the row operands relative to the column block's box centre: the same for
+  // the tile's four column sub-blocks, which this wavefront takes in turn
+  float av[QP];
 #pragma unroll
   for (int a = 0; a < QP; ++a) {
     const double4 p = qpA[(size_t)ia * QP + a];
     const double ex = p.x - fx, ey = p.y - fy, ez = p.z - fz;
     av[a] = (float)(k == 0 ? 2.0 * ex : (k == 1 ? 2.0 * ey : (k == 2 ? 2.0 * ez : -(ex * ex + ey * ey + ez * ez))));
-    wt[a] = fw.w[a];
   }
-  float S[4] = {0.f, 0.f, 0.f, 0.f};
-  // the column point relative to the column block's box centre, and its
-  // squared norm (tabulated by bc_prepare); the next point's pair is loaded
-  // while this one is used, so that no iteration waits for its own loads
-  auto col_b = [&](int b) { return k < 3 ? qpB[(size_t)(b * 4 + k) * N + jb] : 1.0f; };
-  auto col_n = [&](int b) { return qpB[(size_t)(b * 4 + 3) * N + jb]; };
-  float bv_next = col_b(0), yn_next = col_n(0);
-  for (int b = 0; b < QP; ++b) {
-    const float bv = bv_next, yn = yn_next;
-    if (b + 1 < QP) {
-      bv_next = col_b(b + 1);
-      yn_next = col_n(b + 1);
+  const double sb = scale / (1.0 + *rsqb);
+  const int ib = i0 + 4 * k;
+#pragma unroll 1
+  for (int csb = 0; csb < 4; ++csb) {
+    const int j0 = J * 64 + 16 * csb;
+    if (j0 >= N) break;  // wavefront-uniform
+    const int jb = min(j0 + (lane & 15), N - 1);
+    float S[4] = {0.f, 0.f, 0.f, 0.f};
+    // the column point relative to the column block's box centre, and its
+    // squared norm (tabulated by bc_prepare); the next point's pair is loaded
+    // while this one is used, so that no iteration waits for its own loads
+    auto col_b = [&](int b) { return k < 3 ? qpB[(size_t)(b * 4 + k) * N + jb] : 1.0f; };
+    auto col_n = [&](int b) { return qpB[(size_t)(b * 4 + 3) * N + jb]; };
+    float bv_next = col_b(0), yn_next = col_n(0);
+    for (int b = 0; b < QP; ++b) {
+      const float bv = bv_next, yn = yn_next;
+      if (b + 1 < QP) {
+        bv_next = col_b(b + 1);
+        yn_next = col_n(b + 1);
+      }
+      const float wb = fw.w[b];
+      const v4f C = {-yn, -yn, -yn, -yn};
+      float Sb[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int a = 0; a < QP; ++a) {
+        const v4f D = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv, C, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Sb[r] = __builtin_fmaf(fw.w[a], __builtin_amdgcn_rsqf(-D[r]), Sb[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) S[r] = __builtin_fmaf(wb, Sb[r], S[r]);
     }
-    const float wb = fw.w[b];
-    const v4f C = {-yn, -yn, -yn, -yn};
-    float Sb[4] = {0.f, 0.f, 0.f, 0.f};
+    const int j = j0 + (lane & 15);
+    if (j < N) {
+      const double aj = 4.0 * area[j] * sb;
+      float v[4];
 #pragma unroll
-    for (int a = 0; a < QP; ++a) {
-      const v4f D = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv, C, 0, 0, 0);
+      for (int r = 0; r < 4; ++r) v[r] = ib + r < N ? (float)((double)S[r] * (area[ib + r] * aj)) : 0.f;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Sb[r] = __builtin_fmaf(wt[a], __builtin_amdgcn_rsqf(-D[r]), Sb[r]);
+      for (int r = 0; r < 4; ++r)
+        if (ib + r < N) V[(size_t)(ib + r) * ld + j] = v[r];
+      // the mirrored entries (j, ib .. ib + 3) are consecutive in row j
+      if (ib + 3 < N) {
+        *reinterpret_cast<float4 *>(V + (size_t)j * ld + ib) = make_float4(v[0], v[1], v[2], v[3]);
+      } else {
+        for (int r = 0; r < 4; ++r)
+          if (ib + r < N) V[(size_t)j * ld + ib + r] = v[r];
+      }
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) S[r] = __builtin_fmaf(wb, Sb[r], S[r]);
-  }
-  const int j = j0 + (lane & 15), ib = i0 + 4 * k;
-  if (j >= N) return;
-  const double aj = 4.0 * area[j] * (scale / (1.0 + *rsqb));
-  float v[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) v[r] = ib + r < N ? (float)((double)S[r] * (area[ib + r] * aj)) : 0.f;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-    if (ib + r < N) V[(size_t)(ib + r) * ld + j] = v[r];
-  // the mirrored entries (j, ib .. ib + 3) are consecutive in row j
-  if (ib + 3 < N) {
-    *reinterpret_cast<float4 *>(V + (size_t)j * ld + ib) = make_float4(v[0], v[1], v[2], v[3]);
-  } else {
-    for (int r = 0; r < 4; ++r)
-      if (ib + r < N) V[(size_t)j * ld + ib + r] = v[r];
   }
 }
 
-// The tiles of one list, grid-stride (no workgroup barrier: a wavefront
-// that has nothing to do in a tile goes on to the next).
+// The tiles of one list, grid-stride, four at a time per workgroup: its
+// sixteen wavefronts take four tiles, four wavefronts (one per 16-row
+// sub-block) each (no workgroup barrier: a wavefront that has nothing to do
+// in a tile goes on to the next).
 template <int QP>
 __global__ __launch_bounds__(1024) void k_far32m(const double4 *__restrict__ qpA, const float *__restrict__ qpB,
                                                  FarWeights fw, const double *__restrict__ area,
@@ -376,12 +389,13 @@ __global__ __launch_bounds__(1024) void k_far32m(const double4 *__restrict__ qpA
                                                  const int32_t *__restrict__ list, const double *__restrict__ rsqb,
                                                  double scale, int N, int64_t ld, float *__restrict__ V) {
   const int nt = (int)far_tiles(N), n = min(*cnt, nt);
-  for (int q = blockIdx.x; q < n; q += gridDim.x) {
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  for (int q = (int)blockIdx.x * 4 + (w >> 2); q < n; q += (int)gridDim.x * 4) {
     const int t = list[q];
     if (t < 0 || t >= nt) continue;  // lists from another mesh: nothing out of range
     int I, J;
     tile_of(t, I, J);
-    far32m_tile<QP>(I, J, qpA, qpB, fw, area, bbox, rsqb, scale, N, ld, V);
+    far32m_tile<QP>(I, J, w & 3, qpA, qpB, fw, area, bbox, rsqb, scale, N, ld, V);
   }
 }
 
