@@ -146,15 +146,17 @@ struct alignas(64) BarRel {
 
 // Symmetric product.  V is read only on its diagonal blocks and above them:
 // rows are grouped in blocks of kRB, and block b is swept from column kRB*b to
-// ld in chunks of 64*k columns (16 bytes per lane: k = 4 FP32 or 2 FP64
-// entries).  A unit is one (block, chunk) pair; units are numbered block by
-// block and the workgroups of a system take equal contiguous ranges of them.
+// ld.  With several vectors (the dual mesh's products) the sweep is cut into
+// chunks of 64*k columns (k entries per lane); a unit is one (block, chunk)
+// pair, units are numbered block by block and the workgroups of a system take
+// equal contiguous ranges of them.  With one vector it is cut into strips
+// (below).
 constexpr int kRB = 128;        // rows per block of the symmetric product
 constexpr int kMaxBand = 1536;  // rows of the vectors owned by one solver workgroup
 
 // Units of the blocks 0..B-1, m64 = ld / 64.  Block b has
 // ceil((m64 - 2b) / k) units; the sum is written out for k = 1, 2 and 4
-// (pairs of blocks for k = 4).
+// (pairs of blocks for k = 4; only k = 1 is in use).
 __host__ __device__ inline int64_t half_units_before(int64_t B, int64_t m64, int k) {
   if (k == 1) return B * m64 - B * (B - 1);
   if (k == 2) return B * ((m64 + 1) / 2) - B * (B - 1) / 2;
@@ -164,22 +166,46 @@ __host__ __device__ inline int64_t half_units_before(int64_t B, int64_t m64, int
   return s;
 }
 
+// Strip sweep of the symmetric product with one vector: block b is swept
+// from column kRB*b to ld in strips of 256 bytes of each row (64 FP32 or 32
+// FP64 columns, a divisor of 64), and the wavefronts of a system take equal
+// contiguous ranges of the strips, numbered block by block.  Block b has
+// (ld - kRB b) / sw strips.
+constexpr int kStripBytes = 256;
+__host__ __device__ inline int64_t strips_before(int64_t B, int64_t ld, int sw) {
+  return B * (ld / sw) - (kRB / sw) * (B * (B - 1) / 2);
+}
+// Workgroups of one system in the solver: about 80 rows (5 per wavefront)
+// each, at most kGMax.
+__host__ __device__ inline int solve_wg_count(int64_t N) {
+  int64_t g = (N + 79) / 80;
+  if (g < 1) g = 1;
+  if (g > kGMax) g = kGMax;
+  return (int)g;
+}
+// Row-sum slots of a strip sweep: the segment of wavefront g (of GH) in row
+// block B is stored at slot g + B, which no other segment shares (a later
+// wavefront never holds an earlier block).
+__host__ __device__ inline int64_t strip_slots(int64_t N) {
+  return 16 * (int64_t)solve_wg_count(N) + (N + kRB - 1) / kRB;
+}
+
 // Offsets inside one system's solver workspace (256-byte aligned).
 //   ctl    control block, then the solver descriptor of bc_solve
 //   slots  barrier slots, one per workgroup;  rel  release records
 //   x64 r64   FP64 iterate and residual
 //   vec    r u w p s d invdiag in the matrix precision
-//   rpart  row partial sums of the symmetric product, kRB per unit
+//   rpart  row partial sums of the symmetric product, kRB per slot
 //   cpart  column partial sums, ld per row block
 struct SolveLayout {
   size_t ctl, slots, rel, x64, r64, vec, rpart, cpart, total;
   int64_t ld, nB, T;
-  int k;
+  int sw;  // strip width in columns
   __host__ __device__ SolveLayout(int64_t N, int32_t precision) {
     ld = (N + 63) / 64 * 64;
-    k = precision == BC_FP64 ? 2 : 4;
+    sw = kStripBytes / (precision == BC_FP64 ? 8 : 4);
     nB = (N + kRB - 1) / kRB;
-    T = half_units_before(nB, ld / 64, k);
+    T = strips_before(nB, ld, sw);
     size_t o = 0;
     auto take = [&](size_t bytes) {
       size_t r = o;
@@ -192,10 +218,8 @@ struct SolveLayout {
     x64 = take(sizeof(double) * ld);
     r64 = take(sizeof(double) * ld);
     vec = take((precision == BC_FP64 ? 8 : 4) * ld * 7);
-    // FP64 row sums; in mixed precision those of the residual product,
-    // whose units are 128 columns wide (k = 2: two FP32 columns per lane
-    // with the FP64 vector), more than the CG product's
-    rpart = take(sizeof(double) * kRB * (size_t)half_units_before(nB, ld / 64, 2));
+    // FP64 row sums (those of the residual product in mixed precision)
+    rpart = take(sizeof(double) * kRB * (size_t)strip_slots(N));
     cpart = take(sizeof(double) * (size_t)ld * (size_t)nB);
     total = o;
   }
@@ -209,14 +233,18 @@ constexpr int32_t kMatvecF32X64 = BC_F32_F64;
 struct MatvecLayout {
   size_t xpad, rpart, cpart, total;
   int64_t ld, nB, T;
-  int k;
+  int k;   // several vectors: unit width / 64 (one column per lane)
+  int sw;  // one vector: strip width in columns
   // kind: BC_FP64, BC_MIXED (FP32 matrix and vectors) or kMatvecF32X64
-  // (FP32 matrix, FP64 vectors); k = chunk width / 64
+  // (FP32 matrix, FP64 vectors).  One vector: the strip sweep (row sums per
+  // slot); several: units of kRB rows x 64 columns swept by workgroups (row
+  // sums per unit).
   __host__ __device__ MatvecLayout(int64_t N, int32_t kind, int nr = 1) {
     ld = (N + 63) / 64 * 64;
-    k = kind == BC_MIXED ? 4 : (nr > 1 ? 1 : 2);
+    k = 1;
+    sw = kStripBytes / (kind == BC_FP64 ? 8 : 4);
     nB = (N + kRB - 1) / kRB;
-    T = half_units_before(nB, ld / 64, k);
+    T = nr > 1 ? half_units_before(nB, ld / 64, k) : strips_before(nB, ld, sw);
     size_t o = 0;
     auto take = [&](size_t bytes) {
       size_t r = o;
@@ -224,7 +252,7 @@ struct MatvecLayout {
       return r;
     };
     xpad = take(sizeof(double) * (size_t)nr * (size_t)ld);
-    rpart = take(sizeof(double) * (size_t)nr * kRB * (size_t)T);
+    rpart = take(sizeof(double) * (size_t)nr * kRB * (size_t)(nr > 1 ? T : strip_slots(N)));
     cpart = take(sizeof(double) * (size_t)nr * (size_t)ld * (size_t)nB);
     total = o;
   }

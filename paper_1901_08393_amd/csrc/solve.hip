@@ -30,8 +30,8 @@
 //
 // The product streams the diagonal blocks of V and the blocks above them once
 // from HBM (bandwidth-bound: 4 or 8 bytes per entry read, 4 flops) and uses
-// each off-diagonal block for both of its triangles (half_product,
-// half_gather).  At the first step without an initial guess x = 0 and r = b
+// each off-diagonal block for both of its triangles (strip_product,
+// strip_gather).  At the first step without an initial guess x = 0 and r = b
 // needs no product.  Every reduction has a fixed order, so results are
 // bitwise reproducible and do not depend on which other systems share the
 // launch.
@@ -217,20 +217,6 @@ struct LoadD1 {
   __device__ static void vec(gptr<const double> p, double (&v)[1]) { v[0] = *p; }
 };
 
-// two FP32 columns per lane with FP64 vectors: the product of an FP32 matrix
-// with several FP64 vectors (8-byte matrix loads, as LoadD1)
-struct LoadF2D {
-  static constexpr int VEC = 2;
-  __device__ static void mat(gptr<const float> p, float (&v)[2]) {
-    f2 t = __builtin_nontemporal_load(reinterpret_cast<gptr<const f2>>(p));
-    v[0] = t.x; v[1] = t.y;
-  }
-  __device__ static void vec(gptr<const double> p, double (&v)[2]) {
-    d2 t = *reinterpret_cast<gptr<const d2>>(p);
-    v[0] = t.x; v[1] = t.y;
-  }
-};
-
 // one FP32 column per lane with FP64 vectors
 struct LoadF1D {
   static constexpr int VEC = 1;
@@ -239,7 +225,9 @@ struct LoadF1D {
 };
 
 // ------------------------------------------------ symmetric half product
-// y = V x reading V only on its diagonal blocks and above them.  A unit
+// Y = V X for several vectors (the dual mesh's products; one vector takes the
+// strip product below), reading V only on its diagonal blocks and above
+// them.  A unit
 // (block B, chunk c) covers the rows [kRB B, kRB B + kRB) and CW = 64 VEC
 // columns; wavefront w of the workgroup owns 8 of the block's rows and lane l
 // VEC consecutive columns of the chunk.  For its rows a unit adds
@@ -508,6 +496,314 @@ __device__ __noinline__ void half_gather(const HalfPlan &H, int r0, int r1, gptr
   half_gather_body<AT>(H, r0, r1, rpart, cpart, lpart, band);
 }
 
+// ------------------------------------------------- symmetric strip product
+// y = V x for one vector, reading V only on its diagonal blocks and above
+// them, in strips of 256 bytes of each row (SW = 64 FP32 or 32 FP64 columns;
+// strips_before).  The wavefronts of a system ("holders", 16 per workgroup)
+// take equal contiguous ranges of the strips, so each strip belongs to one
+// wavefront and its column sums are complete inside it: no workgroup
+// barrier and no LDS exchange per strip, and the wavefronts of a workgroup
+// run apart.  A 256-byte row piece keeps the HBM pages open as well as the
+// 1 KiB rows of the unit sweep did; 128-byte pieces lost a fifth of the rate.
+//
+// A wavefront reads a strip in four batches of 32 rows; in batch h lane l
+// holds VEC = 16 / sizeof(MT) entries (16 bytes) of the rows
+// l/16 + 32 h + 4 k (k = 0..7), at columns VEC (l % 16) .. +VEC, so that one
+// load instruction covers 4 rows x 256 contiguous bytes.
+//  * Row sums: per batch a lane's 8 row partials are reduced over the 16
+//    lanes of its row group (row16_scatter8), which leaves lane l the row
+//    l/16 + 32 h + 4 ((l >> 1) & 7); the lane adds it to acc[h] across the
+//    strips of one block (a segment) and the segment's 128 sums are stored at
+//    slot (holder + block) of rpart (strip_slots).
+//  * Column sums: a lane's VEC column partials over its 32 rows of the strip
+//    are reduced over the four lanes of its column group (col4_scatter) and
+//    stored per row block (cpart), for the columns right of the diagonal
+//    block (the diagonal block's own columns are covered by its rows).
+//  * The x values of the block's rows sit in the wavefront's 128 LDS entries
+//    (row r at (r % 4) 32 + r / 4, so a lane reads its batch's 8 as a run).
+// With DELTA the product also returns this wavefront's share of x^T V x
+// (from the column partials: weight 1 on the diagonal block, 2 right of it).
+// Every sum has a fixed order: the result depends on N and the workgroup
+// count only.
+struct StripPlan {
+  int64_t ld, T;  // row stride; strips of the sweep
+  int N, nB, GH;  // rows; row blocks; holders (wavefronts of the system)
+  int g0;         // holder of this workgroup's first wavefront
+  int sw;         // strip width in columns
+};
+
+__device__ __forceinline__ StripPlan strip_plan(int64_t N, int64_t ld, int sw, int G, int rank) {
+  StripPlan P;
+  P.ld = ld;
+  P.N = (int)N;
+  P.nB = (int)((N + kRB - 1) / kRB);
+  P.T = strips_before(P.nB, ld, sw);
+  P.GH = 16 * G;
+  P.g0 = 16 * rank;
+  P.sw = sw;
+  return P;
+}
+
+// Reduce-scatter of 8 values over 16 lanes (a group of l/16): lane l keeps
+// the sum over its group of value 4 b3 + 2 b2 + b1 (b: the bits of l),
+// exchanging with the lanes l^8, l^7 and l^3 and finally adding lane l^1's
+// copy.  The exchanges are lane permutes through the LDS crossbar
+// (ds_bpermute); the same exchanges as DPP row operations gave wrong sums in
+// some builds of the solver kernel and were dropped.
+template <typename AT>
+__device__ __forceinline__ AT row16_scatter8(const AT (&v)[8], int lane) {
+  const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
+  AT a[4], b[2];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const AT keep = b3 ? v[j + 4] : v[j], give = b3 ? v[j] : v[j + 4];
+    a[j] = keep + __shfl_xor(give, 8, 64);
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const AT keep = b2 ? a[j + 2] : a[j], give = b2 ? a[j] : a[j + 2];
+    b[j] = keep + __shfl_xor(give, 7, 64);
+  }
+  const AT keep = b1 ? b[1] : b[0], give = b1 ? b[0] : b[1];
+  const AT c = keep + __shfl_xor(give, 3, 64);
+  return c + __shfl_xor(c, 1, 64);
+}
+
+// Column sums over the four lanes l, l^16, l^32, l^48 of a column group:
+// lane l keeps column 2 b4 + b5 of its group's four (VEC = 4), or column b4
+// of two (VEC = 2, where lanes l and l^32 both hold it).
+template <typename AT, int VEC>
+__device__ __forceinline__ AT col4_scatter(const AT (&cs)[VEC], int lane) {
+  const bool b4 = lane & 16, b5 = lane & 32;
+  if constexpr (VEC == 4) {
+    AT a[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const AT keep = b4 ? cs[j + 2] : cs[j], give = b4 ? cs[j] : cs[j + 2];
+      a[j] = keep + __shfl_xor(give, 16, 64);
+    }
+    const AT keep = b5 ? a[1] : a[0], give = b5 ? a[0] : a[1];
+    return keep + __shfl_xor(give, 32, 64);
+  } else {
+    static_assert(VEC == 2, "four or two columns per lane");
+    const AT keep = b4 ? cs[1] : cs[0], give = b4 ? cs[0] : cs[1];
+    const AT c = keep + __shfl_xor(give, 16, 64);
+    return c + __shfl_xor(c, 32, 64);
+  }
+}
+
+template <typename MT, typename XT, typename AT, bool DELTA>
+__device__ __forceinline__ void strip_product(gptr<const MT> V, gptr<const XT> x, const StripPlan &H,
+                                              gptr<AT> rpart, gptr<AT> cpart, lptr<AT> lxall, double &delta) {
+  using L = Load16<MT, XT>;
+  constexpr int VEC = L::VEC;
+  constexpr int SW = 16 * VEC;
+  constexpr int NDIAG = kRB / SW;  // strips of the diagonal block
+  static_assert(SW * (int)sizeof(MT) == kStripBytes, "a strip is 256 bytes of a row");
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int hold = H.g0 + w;
+  int64_t u = H.T * hold / H.GH;
+  const int64_t u1 = H.T * (hold + 1) / H.GH;
+  if (u >= u1) return;
+  const int lane = (int)__lane_id();
+  const int rq = lane >> 4, cq = lane & 15;
+  const int N = H.N;
+  const int64_t ld = H.ld;
+  lptr<AT> lx = lxall + w * kRB;
+  // block of the first strip
+  int B;
+  {
+    int lo = 0, hi = H.nB - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (strips_before(mid, ld, SW) <= u) lo = mid; else hi = mid - 1;
+    }
+    B = lo;
+  }
+  int64_t SE = strips_before(B + 1, ld, SW);
+  int c = (int)(u - strips_before(B, ld, SW));
+
+  // the block's x values: lane l brings rows l and l + 64, stored at the
+  // start of the block's first strip
+  AT xn0, xn1;
+  auto x_rows = [&](int Bl) {
+    const int i0 = kRB * Bl + lane, i1 = i0 + 64;
+    xn0 = i0 < N ? (AT)x[i0] : AT(0);
+    xn1 = i1 < N ? (AT)x[i1] : AT(0);
+  };
+  bool fresh = true;
+  x_rows(B);
+  MT va[8][VEC];
+  XT xa[VEC];
+  auto load = [&](int Bl, int cl, int h, bool with_x) {
+    const int64_t col = (int64_t)kRB * Bl + (int64_t)SW * cl + VEC * cq;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int row = min(kRB * Bl + rq + 32 * h + 4 * k, N - 1);
+      L::mat(V + (size_t)row * (size_t)ld + col, va[k]);
+    }
+    if (with_x) L::vec(x + col, xa);
+  };
+  // acc[0] always takes the current batch: the four are rotated after each
+  // batch, so that the batch loop needs no register indexing
+  AT acc[4], cs[VEC];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) acc[h] = AT(0);
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) cs[q] = AT(0);
+  int h = 0;
+  load(B, c, 0, true);
+  while (true) {
+    if (h == 0 && fresh) {
+      lx[(lane & 3) * 32 + (lane >> 2)] = xn0;       // row lane
+      lx[(lane & 3) * 32 + 16 + (lane >> 2)] = xn1;  // row lane + 64
+      fresh = false;
+    }
+    AT xq[VEC], xb[8], rp[8];
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) xq[q] = (AT)xa[q];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) xb[k] = lx[rq * 32 + 8 * h + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      AT r = (AT)va[k][0] * xq[0];
+#pragma unroll
+      for (int q = 1; q < VEC; ++q) r = fma_t((AT)va[k][q], xq[q], r);
+      rp[k] = r;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) cs[q] = fma_t((AT)va[k][q], xb[k], cs[q]);
+    {
+      const AT a0 = acc[0] + row16_scatter8<AT>(rp, lane);
+      acc[0] = acc[1]; acc[1] = acc[2]; acc[2] = acc[3]; acc[3] = a0;
+    }
+    if (h < 3) {
+      ++h;
+      load(B, c, h, false);
+      continue;
+    }
+    // end of the strip
+    const bool more = u + 1 < u1, same = u + 1 < SE;
+    const int Bn = same ? B : B + 1, cn = same ? c + 1 : 0;
+    if (DELTA) {
+      double d = 0.0;
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) d = __builtin_fma((double)xq[q], (double)cs[q], d);
+      delta = __builtin_fma(c < NDIAG ? 1.0 : 2.0, d, delta);
+    }
+    if (more) {
+      load(Bn, cn, 0, true);
+      if (!same) {
+        x_rows(Bn);
+        fresh = true;
+      }
+    }
+    // the strip's column sums (right of the diagonal block)
+    {
+      const AT sum = col4_scatter<AT, VEC>(cs, lane);
+      const int q = VEC == 4 ? 2 * ((lane >> 4) & 1) + ((lane >> 5) & 1) : (lane >> 4) & 1;
+      if (c >= NDIAG && (VEC == 4 || lane < 32))
+        cpart[(size_t)B * (size_t)ld + (size_t)(kRB * B + SW * c + VEC * cq + q)] = sum;
+#pragma unroll
+      for (int j = 0; j < VEC; ++j) cs[j] = AT(0);
+    }
+    if (!more || !same) {
+      // end of a segment: its row sums at slot (holder + block); after the
+      // four rotations acc[h] holds batch h
+      const int rk = 4 * ((lane >> 1) & 7) + rq;
+#pragma unroll
+      for (int hh = 0; hh < 4; ++hh) {
+        const int row = 32 * hh + rk;
+        if (!(lane & 1) && kRB * B + row < N) rpart[(size_t)(hold + B) * kRB + row] = acc[hh];
+        acc[hh] = AT(0);
+      }
+    }
+    if (!more) break;
+    ++u;
+    h = 0;
+    B = Bn;
+    c = cn;
+    if (!same) SE = strips_before(B + 1, ld, SW);
+  }
+}
+
+// y_i for the rows [r0, r1) of this workgroup into band[i - r0] after a
+// strip product: the row sums of the segments of i's block (one per
+// wavefront that holds strips of it, in wavefront order) and then the
+// column sums of the row blocks 0 .. B(i)-1.  The band is cut into groups of
+// 64 rows (a lane per row); the sixteen wavefronts are shared out over up to
+// sixteen groups at a time, S per group, and the S wavefronts of a group take
+// every S-th term.  A wavefront issues the loads of sixteen of its terms
+// before adding any, keeps one partial sum per load slot and adds them in a
+// fixed tree, and the S wavefront sums of a row are added in wavefront order.
+template <typename AT>
+__device__ __forceinline__ void strip_gather_body(const StripPlan &H, int r0, int r1, gptr<const AT> rpart,
+                                                  gptr<const AT> cpart, lptr<AT> lpart, lptr<AT> band) {
+  constexpr int NB = 16;  // loads in flight per wavefront
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ngr = (r1 - r0 + 63) >> 6;  // groups of 64 rows
+  const int gpp = ngr < 16 ? ngr : 16;  // groups per pass
+  const int S = 16 / (gpp > 0 ? gpp : 1);  // wavefronts per group
+  const int64_t T = H.T, GH = H.GH;
+  for (int p0 = 0; p0 < ngr; p0 += gpp) {
+    const int g = p0 + w / S, sl = w % S;
+    const int i = r0 + 64 * g + lane;
+    AT s[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) s[k] = AT(0);
+    if (w < S * gpp && g < ngr && i < r1) {
+      const int B = i / kRB;
+      const int64_t SB = strips_before(B, H.ld, H.sw), SE = strips_before(B + 1, H.ld, H.sw);
+      // holders of the strips SB and SE - 1 (ranges [T g / GH, T (g+1) / GH))
+      const int glo = (int)(((SB + 1) * GH + T - 1) / T) - 1;
+      const int ghi = (int)((SE * GH + T - 1) / T) - 1;
+      const int nseg = ghi - glo + 1;
+      const int nterm = nseg + B;
+      const int ii = i - kRB * B;
+      int q = sl;
+      for (; q < nseg && q < nterm; q += S) {  // segment row sums
+        const int64_t gq = glo + q;
+        if (T * (gq + 1) / GH != T * gq / GH)  // a holder without strips has no segment
+          s[0] += rpart[(size_t)(gq + B) * kRB + ii];
+      }
+      // column sums of the blocks above, NB loads issued before any add
+      for (; q < nterm; q += NB * S) {
+        AT v[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const int qk = q + k * S;
+          v[k] = qk < nterm ? cpart[(size_t)(qk - nseg) * (size_t)H.ld + i] : AT(0);
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) s[k] += v[k];
+      }
+    }
+#pragma unroll
+    for (int h = NB / 2; h > 0; h >>= 1)
+#pragma unroll
+      for (int k = 0; k < h; ++k) s[k] += s[k + h];
+    lpart[w * 64 + lane] = s[0];
+    __syncthreads();
+    if (w < gpp) {
+      const int gg = p0 + w, iw = r0 + 64 * gg + lane;
+      if (gg < ngr && iw < r1) {
+        AT tot = AT(0);
+        for (int q = 0; q < S; ++q) tot += lpart[(w * S + q) * 64 + lane];
+        band[iw - r0] = tot;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename AT>
+__device__ __noinline__ void strip_gather(const StripPlan &H, int r0, int r1, gptr<const AT> rpart,
+                                          gptr<const AT> cpart, lptr<AT> lpart, lptr<AT> band) {
+  strip_gather_body<AT>(H, r0, r1, rpart, cpart, lpart, band);
+}
+
 // The solver's products as a call of their own.  Inlined into k_solve, the
 // product loop shares the kernel's 128 registers with the state of the
 // whole state machine and spills inside the loop; as a call it has the
@@ -532,50 +828,35 @@ template <typename T>
 __device__ __forceinline__ lptr<T> uniform_lptr(lptr<T> p) {
   return (lptr<T>)(uintptr_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(uintptr_t)p);
 }
-template <typename HP>
-__device__ __forceinline__ HalfPlan uniform_plan(const HP &H) {
-  HalfPlan U;
+template <typename SP>
+__device__ __forceinline__ StripPlan uniform_strip(const SP &H) {
+  StripPlan U;
   U.ld = uniform64(H.ld);
-  U.m64 = uniform64(H.m64);
   U.T = uniform64(H.T);
   U.N = uniform32(H.N);
   U.nB = uniform32(H.nB);
-  U.k = uniform32(H.k);
-  U.G = uniform32(H.G);
-  U.u0 = uniform64(H.u0);
-  U.u1 = uniform64(H.u1);
+  U.GH = uniform32(H.GH);
+  U.g0 = uniform32(H.g0);
+  U.sw = uniform32(H.sw);
   return U;
 }
 
-template <typename MT, typename XT, typename AT, bool DELTA, bool LDS2, typename L = Load16<MT, XT>>
-__device__ __noinline__ double solver_product(gptr<const MT> V, gptr<const XT> x, HalfPlan H, gptr<AT> rpart,
-                                              gptr<AT> cpart, lptr<AT> lbuf) {
+// Its operands are read from an LDS record written by the caller, as the CG
+// phase reads its own (with them passed as call arguments the FP64 solver
+// gave wrong products in some builds).
+struct ProdArgs {
+  gptr<const void> V, x;
+  gptr<void> rp, cp;
+  StripPlan H;
+};
+template <typename MT, typename XT, typename AT, bool DELTA>
+__device__ __noinline__ double solver_product(lptr<ProdArgs> P, lptr<AT> lx) {
+  P = uniform_lptr(P);
   double delta = 0.0;
-  half_product<MT, XT, AT, DELTA, LDS2, 1, L>(uniform_ptr(V), uniform_ptr(x), uniform_plan(H), uniform_ptr(rpart),
-                                              uniform_ptr(cpart), uniform_lptr(lbuf), delta);
+  strip_product<MT, XT, AT, DELTA>(uniform_ptr((gptr<const MT>)P->V), uniform_ptr((gptr<const XT>)P->x),
+                                   uniform_strip(P->H), uniform_ptr((gptr<AT>)P->rp), uniform_ptr((gptr<AT>)P->cp),
+                                   uniform_lptr(lx), delta);
   return delta;
-}
-
-// Residual products: the FP64 iterate with the stored matrix.  An FP32
-// matrix is read two columns per lane (units of 128 columns, k = 2), which
-// leaves the FP64 row and column sums their registers; with the CG
-// product's 16-byte loads they spilled and the product took twice as long.
-template <typename MT>
-struct ResidLoad {
-  using type = Load16<MT, double>;
-};
-template <>
-struct ResidLoad<float> {
-  using type = LoadF2D;
-};
-__device__ __forceinline__ HalfPlan resid_plan(const HalfPlan &H, bool mixed, int rank) {
-  if (!mixed) return H;
-  HalfPlan R = H;
-  R.k = 2;
-  R.T = half_units_before(H.nB, H.m64, 2);
-  R.u0 = R.T * rank / H.G;
-  R.u1 = R.T * (rank + 1) / H.G;
-  return R;
 }
 
 // ---------------------------------------------------------- CG iterations
@@ -593,7 +874,7 @@ struct CGCtx {
   gptr<MT> vr, vu, vp, vs, vd, idg, rp, cp;
   gptr<BarSlot> slots;
   gptr<BarRel> rel;
-  HalfPlan H;
+  StripPlan H;
   int r0, r1, G, rank;
   uint32_t spin_limit;
   int32_t max_iter;
@@ -635,7 +916,7 @@ __device__ __noinline__ void cg_loop(lptr<CGCtx<MT>> Cp, lptr<CGState> Sp, lptr<
   const gptr<VT> vr = uniform_ptr(Cp->vr), vu = uniform_ptr(Cp->vu), vp = uniform_ptr(Cp->vp);
   const gptr<VT> vs = uniform_ptr(Cp->vs), vd = uniform_ptr(Cp->vd), idg = uniform_ptr(Cp->idg);
   const gptr<VT> rp = uniform_ptr(Cp->rp), cp = uniform_ptr(Cp->cp);
-  const HalfPlan H = uniform_plan(Cp->H);
+  const StripPlan H = uniform_strip(Cp->H);
   const int r0 = uniform32(Cp->r0), r1 = uniform32(Cp->r1), max_iter = uniform32(Cp->max_iter);
   SysBar bar{uniform_ptr(Cp->slots), uniform_ptr(Cp->rel), uniform32(Cp->G), uniform32(Cp->rank),
              (unsigned)uniform32((int)Sp->epoch), (uint32_t)uniform32((int)Cp->spin_limit)};
@@ -656,7 +937,7 @@ __device__ __noinline__ void cg_loop(lptr<CGCtx<MT>> Cp, lptr<CGState> Sp, lptr<
     if (budget <= 0) { ex = 0; break; }
     budget -= 1;
     // w = V u of the last product
-    half_gather_body<VT>(H, r0, r1, rp, cp, lpart, band);
+    strip_gather_body<VT>(H, r0, r1, rp, cp, lpart, band);
     const VT a = (VT)alpha, bt = (VT)beta;
     double pru = 0.0, prr = 0.0;
     // the lane's first row, formed anew in every iteration: kept across the
@@ -697,7 +978,7 @@ __device__ __noinline__ void cg_loop(lptr<CGCtx<MT>> Cp, lptr<CGState> Sp, lptr<
     }
     if (!(sqrt(rr) > itol) || cap_met || iters >= max_iter) { ex = 1; break; }
     double pwu = 0.0;
-    half_product<MT, VT, VT, true, true>(V, vu, H, rp, cp, lbuf, pwu);
+    strip_product<MT, VT, VT, true>(V, vu, H, rp, cp, lbuf, pwu);
     double delta;
     {
       const double v[1] = {pwu};
@@ -733,11 +1014,12 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
   constexpr bool MIXED = sizeof(MT) == 4;
   __shared__ double s_red[80];
   __shared__ int s_flag;
-  __shared__ double s_buf[4096];       // column sums of the symmetric product (32 KB)
+  __shared__ double s_buf[16 * kRB];   // x of the product's row blocks, per wavefront (16 KB)
   __shared__ double s_part[16 * 64];   // per-wavefront sums of half_gather
   __shared__ double s_band[kMaxBand];  // V x on this workgroup's rows
   __shared__ CGCtx<MT> s_cg;
   __shared__ CGState s_st;
+  __shared__ ProdArgs s_prod;
   const lptr<double> l_red = (lptr<double>)s_red;
   const lptr<int> l_flag = (lptr<int>)&s_flag;
 
@@ -756,9 +1038,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
   const int r0 = (int)((int64_t)N * rank / G), r1 = (int)((int64_t)N * (rank + 1) / G);
   const SolveLayout Lay(S.N, MIXED ? BC_MIXED : BC_FP64);
   const int64_t ld = Lay.ld;
-  HalfPlan H;
-  H.ld = ld; H.m64 = ld / 64; H.T = Lay.T; H.N = N; H.nB = (int)Lay.nB; H.k = Lay.k; H.G = G;
-  H.u0 = Lay.T * rank / G; H.u1 = Lay.T * (rank + 1) / G;
+  const StripPlan H = strip_plan(N, ld, Lay.sw, G, rank);
   gptr<char> ws = as_global(S.ws);
   gptr<SolveCtl> ctl = reinterpret_cast<gptr<SolveCtl>>(ws + Lay.ctl);
   gptr<double> x64 = reinterpret_cast<gptr<double>>(ws + Lay.x64);
@@ -837,11 +1117,14 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       const bool zero_x = outer == 0 && !P.x0_given;
       if (!zero_x) {
         double unused = 0.0, dummy[1];
-        const HalfPlan HR = resid_plan(H, MIXED, rank);
-        unused = solver_product<MT, double, double, false, false, typename ResidLoad<MT>::type>(V, x64, HR, rpD, cpD,
-                                                                                              (lptr<double>)s_buf);
+        if (t == 0) {
+          s_prod.V = (gptr<const void>)V; s_prod.x = (gptr<const void>)x64;
+          s_prod.rp = (gptr<void>)rpD; s_prod.cp = (gptr<void>)cpD; s_prod.H = H;
+        }
+        __syncthreads();
+        unused = solver_product<MT, double, double, false>((lptr<ProdArgs>)&s_prod, (lptr<double>)s_buf);
         if (!sys_sync<1>(bar, none, dummy, l_red, l_flag)) { aborted = true; break; }
-        half_gather<double>(HR, r0, r1, rpD, cpD, (lptr<double>)s_part, (lptr<double>)s_band);
+        strip_gather<double>(H, r0, r1, rpD, cpD, (lptr<double>)s_part, (lptr<double>)s_band);
       }
       // sums: ||r||^2, then ||b||^2 at the first step and x^T r after it,
       // ||x||^2, b^T x
@@ -903,7 +1186,12 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
         gamma = tot[0];
       }
       double pwu = 0.0;
-      pwu = solver_product<MT, VT, VT, true, true>(V, vu, H, rpV, cpV, (lptr<VT>)s_buf);
+      if (t == 0) {
+        s_prod.V = (gptr<const void>)V; s_prod.x = (gptr<const void>)vu;
+        s_prod.rp = (gptr<void>)rpV; s_prod.cp = (gptr<void>)cpV; s_prod.H = H;
+      }
+      __syncthreads();
+      pwu = solver_product<MT, VT, VT, true>((lptr<ProdArgs>)&s_prod, (lptr<VT>)s_buf);
       {
         const double v[1] = {pwu};
         double tot[1];
@@ -1072,13 +1360,7 @@ int launch_set_desc(const SysDesc *h, int n, SysDesc *d, hipStream_t s) {
   return BC_OK;
 }
 
-// About 80 rows (5 per wavefront) per workgroup, at most kGMax workgroups.
-int solve_workgroups(int64_t N) {
-  int64_t g = (N + 79) / 80;
-  if (g < 1) g = 1;
-  if (g > kGMax) g = kGMax;
-  return (int)g;
-}
+int solve_workgroups(int64_t N) { return solve_wg_count(N); }
 
 int solve_capacity(int32_t precision) {
   int dev = 0, cus = 0, nb = 0;
@@ -1139,27 +1421,34 @@ __device__ __forceinline__ HalfPlan matvec_plan(const MatvecLayout &Lay, int64_t
   return H;
 }
 
-// LDS: two buffers of NR x 16 wavefronts x CW column sums, and for NR > 1
-// the 16 x 8 x NR row x values.  One vector: 16-byte matrix loads; several:
-// 8-byte matrix loads (one FP64 or two FP32 columns per lane), so that the
-// NR x 8 row sums stay in registers.
+// One vector: the strip product (LDS: the x values of each wavefront's row
+// block).  Several: the unit sweep with 8-byte matrix loads (one FP64 or FP32
+// column per lane), so that the NR x 8 row sums stay in registers; LDS: two
+// buffers of NR x 16 wavefronts x CW column sums and the 16 x 8 x NR row x
+// values.
 template <typename MT, typename XT, int NR>
 __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) void k_matvec_part(
     const MT *__restrict__ V, int64_t N, char *ws, const int32_t *__restrict__ skip) {
   if (skip && *skip) return;
   static_assert(NR == 1 || sizeof(XT) == 8, "several vectors: FP64 vectors only");
-  using L = typename std::conditional<
-      sizeof(MT) == sizeof(XT), typename std::conditional<NR == 1, Load16<MT, XT>, LoadD1>::type,
-      typename std::conditional<NR == 1, LoadF2D, LoadF1D>::type>::type;
-  constexpr int CW = 64 * L::VEC;
-  __shared__ XT s_buf[2 * NR * 16 * CW + (NR > 1 ? 16 * 8 * NR : 0)];
   const MatvecLayout Lay(N, matvec_kind<MT, XT>(), NR);
-  const HalfPlan H = matvec_plan(Lay, N, (int)gridDim.x, (int)blockIdx.x);
   gptr<char> w = as_global(ws);
   double unused = 0.0;
-  half_product<MT, XT, XT, false, true, NR, L>(as_global(V), reinterpret_cast<gptr<const XT>>(w + Lay.xpad), H,
-                                               reinterpret_cast<gptr<XT>>(w + Lay.rpart),
-                                               reinterpret_cast<gptr<XT>>(w + Lay.cpart), (lptr<XT>)s_buf, unused);
+  if constexpr (NR == 1) {
+    __shared__ XT s_x[16 * kRB];
+    const StripPlan H = strip_plan(N, Lay.ld, Lay.sw, (int)gridDim.x, (int)blockIdx.x);
+    strip_product<MT, XT, XT, false>(as_global(V), reinterpret_cast<gptr<const XT>>(w + Lay.xpad), H,
+                                     reinterpret_cast<gptr<XT>>(w + Lay.rpart),
+                                     reinterpret_cast<gptr<XT>>(w + Lay.cpart), (lptr<XT>)s_x, unused);
+  } else {
+    using L = typename std::conditional<sizeof(MT) == sizeof(XT), LoadD1, LoadF1D>::type;
+    constexpr int CW = 64 * L::VEC;
+    __shared__ XT s_buf[2 * NR * 16 * CW + 16 * 8 * NR];
+    const HalfPlan H = matvec_plan(Lay, N, (int)gridDim.x, (int)blockIdx.x);
+    half_product<MT, XT, XT, false, true, NR, L>(as_global(V), reinterpret_cast<gptr<const XT>>(w + Lay.xpad), H,
+                                                 reinterpret_cast<gptr<XT>>(w + Lay.rpart),
+                                                 reinterpret_cast<gptr<XT>>(w + Lay.cpart), (lptr<XT>)s_buf, unused);
+  }
 }
 
 template <typename MT, typename XT, int NR>
@@ -1170,16 +1459,23 @@ __global__ __launch_bounds__(kSolveWG) void k_matvec_gather(int64_t N, const cha
   __shared__ double s_band[kMaxBand];
   const MatvecLayout Lay(N, matvec_kind<MT, XT>(), NR);
   const int G = (int)gridDim.x, rank = (int)blockIdx.x;
-  const HalfPlan H = matvec_plan(Lay, N, G, rank);
   const int r0 = (int)(N * rank / G), r1 = (int)(N * (rank + 1) / G);
   gptr<const char> w = as_global(ws);
   XT *band = reinterpret_cast<XT *>(s_band);
-  for (int m = 0; m < NR; ++m) {
-    half_gather<XT>(H, r0, r1, reinterpret_cast<gptr<const XT>>(w + Lay.rpart) + (size_t)m * kRB * Lay.T,
-                    reinterpret_cast<gptr<const XT>>(w + Lay.cpart) + (size_t)m * Lay.nB * Lay.ld,
-                    (lptr<XT>)s_part, (lptr<XT>)s_band);
-    for (int i = r0 + (int)threadIdx.x; i < r1; i += kSolveWG) y[m * N + i] = band[i - r0];
-    __syncthreads();  // band is rewritten by the next vector's gather
+  if constexpr (NR == 1) {
+    const StripPlan H = strip_plan(N, Lay.ld, Lay.sw, G, rank);
+    strip_gather<XT>(H, r0, r1, reinterpret_cast<gptr<const XT>>(w + Lay.rpart),
+                     reinterpret_cast<gptr<const XT>>(w + Lay.cpart), (lptr<XT>)s_part, (lptr<XT>)s_band);
+    for (int i = r0 + (int)threadIdx.x; i < r1; i += kSolveWG) y[i] = band[i - r0];
+  } else {
+    const HalfPlan H = matvec_plan(Lay, N, G, rank);
+    for (int m = 0; m < NR; ++m) {
+      half_gather<XT>(H, r0, r1, reinterpret_cast<gptr<const XT>>(w + Lay.rpart) + (size_t)m * kRB * Lay.T,
+                      reinterpret_cast<gptr<const XT>>(w + Lay.cpart) + (size_t)m * Lay.nB * Lay.ld,
+                      (lptr<XT>)s_part, (lptr<XT>)s_band);
+      for (int i = r0 + (int)threadIdx.x; i < r1; i += kSolveWG) y[m * N + i] = band[i - r0];
+      __syncthreads();  // band is rewritten by the next vector's gather
+    }
   }
 }
 
