@@ -675,13 +675,15 @@ __device__ __forceinline__ void strip_product(gptr<const MT> V, gptr<const XT> x
     for (int k = 0; k < 8; ++k)
 #pragma unroll
       for (int q = 0; q < VEC; ++q) cs[q] = fma_t((AT)va[k][q], xb[k], cs[q]);
-    {
+    // the next loads go out before the lane exchanges of the row sums
+    auto rows_done = [&]() {
       const AT a0 = acc[0] + row16_scatter8<AT>(rp, lane);
       acc[0] = acc[1]; acc[1] = acc[2]; acc[2] = acc[3]; acc[3] = a0;
-    }
+    };
     if (h < 3) {
       ++h;
       load(B, c, h, false);
+      rows_done();
       continue;
     }
     // end of the strip
@@ -700,6 +702,7 @@ __device__ __forceinline__ void strip_product(gptr<const MT> V, gptr<const XT> x
         fresh = true;
       }
     }
+    rows_done();
     // the strip's column sums (right of the diagonal block)
     {
       const AT sum = col4_scatter<AT, VEC>(cs, lane);
