@@ -378,19 +378,23 @@ __device__ __forceinline__ void far32m_tile(int I, int J, int rsb, const double4
   }
 }
 
-// The tiles of one list, grid-stride, four at a time per workgroup: its
-// sixteen wavefronts take four tiles, four wavefronts (one per 16-row
-// sub-block) each (no workgroup barrier: a wavefront that has nothing to do
-// in a tile goes on to the next).
+// The tiles of one list, grid-stride, one tile per four wavefronts (one per
+// 16-row sub-block; no workgroup barrier: a wavefront that has nothing to do
+// in a tile goes on to the next).  Workgroups of kFarMWG threads, kFarMGrid
+// per CU in the grid (L5 sphere, mixed assembly: 3.49 ms with 512 x 4, 3.53
+// with 1024 x 2, 3.77 with 256 x 8; 72 registers allow 7 wavefronts per SIMD).
+constexpr int kFarMWG = 512;
+constexpr int kFarMGrid = 4;
 template <int QP>
-__global__ __launch_bounds__(1024) void k_far32m(const double4 *__restrict__ qpA, const float *__restrict__ qpB,
-                                                 FarWeights fw, const double *__restrict__ area,
-                                                 const double *__restrict__ bbox, const int32_t *__restrict__ cnt,
-                                                 const int32_t *__restrict__ list, const double *__restrict__ rsqb,
-                                                 double scale, int N, int64_t ld, float *__restrict__ V) {
+__global__ __launch_bounds__(kFarMWG) void k_far32m(const double4 *__restrict__ qpA, const float *__restrict__ qpB,
+                                                    FarWeights fw, const double *__restrict__ area,
+                                                    const double *__restrict__ bbox, const int32_t *__restrict__ cnt,
+                                                    const int32_t *__restrict__ list, const double *__restrict__ rsqb,
+                                                    double scale, int N, int64_t ld, float *__restrict__ V) {
+  constexpr int TPW = kFarMWG / 256;  // tiles per workgroup pass
   const int nt = (int)far_tiles(N), n = min(*cnt, nt);
   const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  for (int q = (int)blockIdx.x * 4 + (w >> 2); q < n; q += (int)gridDim.x * 4) {
+  for (int q = (int)blockIdx.x * TPW + (w >> 2); q < n; q += (int)gridDim.x * TPW) {
     const int t = list[q];
     if (t < 0 || t >= nt) continue;  // lists from another mesh: nothing out of range
     int I, J;
@@ -531,8 +535,8 @@ static void far_launch(bool mixed, bool low_order, const MeshView &m, int N, int
     // Each tile class on its own kernel, over the tile lists of bc_prepare:
     // near and diagonal tiles on the vector ALU, separated ones on the
     // matrix cores (those at least kSepFarLow apart with Radon's rule when
-    // low_order).  The matrix-core kernels run as many workgroups as fit on
-    // the chip at once (two per CU) and take the tiles grid-stride.
+    // low_order).  The matrix-core kernels run about as many workgroups as fit
+    // on the chip at once and take the tiles grid-stride.
     const int cus = device_cus();
     const int nt = (int)far_tiles(N);
     const int32_t *cnt = m.tile_cnt, *list = m.tile_list;
@@ -544,17 +548,17 @@ static void far_launch(bool mixed, bool low_order, const MeshView &m, int N, int
     double rs[kQLow], rt[kQLow], rw[kQLow];
     radon7(rs, rt, rw);
     for (int a = 0; a < kQLow; ++a) wL.w[a] = (float)rw[a];
-    const int gv = std::min(nt, 4 * cus), gm = std::min(nt, 2 * cus);
+    const int gv = std::min(nt, 4 * cus), gm = std::min(nt, kFarMGrid * cus);
     hipLaunchKernelGGL((k_far32<Q, true>), dim3(gv), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox, cnt,
                        list, m.rsq_bias, scale, N, ld, static_cast<float *>(V));
-    hipLaunchKernelGGL(k_far32m<16>, dim3(gm), dim3(1024), 0, s, m.qpA64, m.qpB16, w16, m.area, m.bbox, cnt + 1,
+    hipLaunchKernelGGL(k_far32m<16>, dim3(gm), dim3(kFarMWG), 0, s, m.qpA64, m.qpB16, w16, m.area, m.bbox, cnt + 1,
                        list + (size_t)nt, m.rsq_bias, scale, N, ld, static_cast<float *>(V));
     if (low_order)
-      hipLaunchKernelGGL(k_far32m<kQLow>, dim3(gm), dim3(1024), 0, s, m.qpLA64, m.qpBL, wL, m.area, m.bbox,
+      hipLaunchKernelGGL(k_far32m<kQLow>, dim3(gm), dim3(kFarMWG), 0, s, m.qpLA64, m.qpBL, wL, m.area, m.bbox,
                          cnt + 2, list + 2 * (size_t)nt, m.rsq_bias, far32_scale_w(rw, kQLow), N, ld,
                          static_cast<float *>(V));
     else
-      hipLaunchKernelGGL(k_far32m<16>, dim3(gm), dim3(1024), 0, s, m.qpA64, m.qpB16, w16, m.area, m.bbox, cnt + 2,
+      hipLaunchKernelGGL(k_far32m<16>, dim3(gm), dim3(kFarMWG), 0, s, m.qpA64, m.qpB16, w16, m.area, m.bbox, cnt + 2,
                          list + 2 * (size_t)nt, m.rsq_bias, scale, N, ld, static_cast<float *>(V));
   } else {
     hipLaunchKernelGGL((k_far32<Q, false>), dim3(tiles), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox,
