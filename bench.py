@@ -34,8 +34,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-FP32_VECTOR_PEAK = 157.3  # TFLOP/s, published (counts packed FP32)
-FP32_UNPACKED_PEAK = 78.6  # TFLOP/s = 256 CU x 64 lanes x 2 flops x 2.4 GHz
+FP32_VECTOR_PEAK = 157.3  # TFLOP/s, published: 128 FP32 FMA lanes per CU per clock
+# Issue costs on one SIMD measured by throughput probes (independent chains, 6
+# wavefronts per SIMD): a wave64 FP32 VALU instruction (fma, fmac, mul, sub)
+# 2.8-3.25 cycles, v_rsq_f32 8.2, v_mfma_f32_16x16x4f32 35.5; a mix of MFMA and
+# VALU instructions takes the sum of their times (no overlap).
+CYC_VALU_F32 = 2.9
+CYC_RSQ_F32 = 8.2
+CYC_MFMA_F32 = 35.5
+SIMDS, CLOCK_HZ = 1024, 2.4e9
 FP64_VECTOR_PEAK = 78.6  # TFLOP/s
 FLOPS_PER_POINT_PAIR = 11  # 3 sub, 5 for r^2, 1 inverse sqrt, 2 for the weighted sums
 POINT_PAIRS_PER_PAIR = 256  # 16 x 16 collapsed Gauss points
@@ -837,8 +844,6 @@ def main():
                 "point_pairs_per_pair": round(point_pairs / pairs, 2),
                 "avg_launch_ms": round(mean("assemble_ms"), 4)}
     if a.precision == "mixed":
-        roof_asm["peak_unpacked"] = FP32_UNPACKED_PEAK
-        roof_asm["frac_unpacked"] = round(asm_tflops / FP32_UNPACKED_PEAK, 4)
         # on separated tiles the 8 flops of -r^2 (3 differences, 5 for the
         # square) are one matrix-core product per point pair
         # (v_mfma_f32_16x16x4f32: 16 x 16 x 4 x 2 flops for 256 point pairs);
@@ -856,6 +861,19 @@ def main():
             "matrix_core_tflops": round(mm_flops / sec / 1e12, 2),
             "matrix_core_frac_of_157.3": round(mm_flops / sec / 1e12 / FP32_VECTOR_PEAK, 4),
             "note": "flops by the 11-per-point-pair convention; on matrix-core tiles 8 of them are MFMA flops",
+        }
+        # issue time of the far field's instruction mix at the probed costs:
+        # vector tiles 7 VALU (differences, r^2, accumulation) and one v_rsq_f32
+        # per 64 point pairs; matrix-core tiles one MFMA, 4 v_rsq_f32 and 4 FMA
+        # per 256 point pairs
+        cyc = (pp_vec / 64 * (7 * CYC_VALU_F32 + CYC_RSQ_F32)
+               + pp_mm / 256 * (CYC_MFMA_F32 + 4 * CYC_RSQ_F32 + 4 * CYC_VALU_F32))
+        issue_ms = cyc / (SIMDS * CLOCK_HZ) * 1e3
+        roof_asm["issue_bound"] = {
+            "far_field_issue_ms": round(issue_ms, 4),
+            "frac_of_call": round(issue_ms / mean("assemble_ms"), 4),
+            "basis": "probed wave64 costs: FP32 VALU 2.9 cycles, v_rsq_f32 8.2, v_mfma_f32_16x16x4f32 35.5, "
+                     "MFMA and VALU times adding up; 1024 SIMDs at 2.4 GHz",
         }
     dominant = roof_solve if mean("solve_ms") >= mean("assemble_ms") else roof_asm
     other = roof_asm if dominant is roof_solve else roof_solve
