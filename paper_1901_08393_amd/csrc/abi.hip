@@ -196,7 +196,7 @@ int32_t bc_prepare(const double *d_verts, int64_t M, const int32_t *d_tris, int6
   MeshLayout L(N);
   if (mesh_ws_bytes < L.total) return BC_ENOMEM;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  int st = launch_geometry(d_verts, M, d_tris, N, opts->far_order, d_mesh_ws, s);
+  int st = launch_geometry(d_verts, d_tris, N, opts->far_order, d_mesh_ws, s);
   if (st != BC_OK) return st;
   st = launch_pattern(d_verts, d_tris, N, opts->near_factor, d_mesh_ws, nullptr, 0, opts->precision, false, s);
   if (st != BC_OK) return st;

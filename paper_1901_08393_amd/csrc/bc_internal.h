@@ -598,8 +598,8 @@ __device__ __forceinline__ T wave_sum_full(T v) {
 
 // Host-side launchers (each returns a bc_status).
 namespace bc {
-int launch_geometry(const double *verts, int64_t M, const int32_t *tris, int64_t N,
-                    int far_order, void *mesh_ws, hipStream_t s);
+int launch_geometry(const double *verts, const int32_t *tris, int64_t N, int far_order, void *mesh_ws,
+                    hipStream_t s);
 // the mean error of the FP32 hardware inverse square root into the mesh
 // workspace (MeshLayout::rsqb)
 int launch_rsq_bias(void *mesh_ws, int64_t N, hipStream_t s);

@@ -24,7 +24,7 @@ struct FarRule {
   double s[kQMax], t[kQMax], w[kQMax];
 };
 
-__global__ __launch_bounds__(kWG) void k_geometry(const double *__restrict__ verts, int64_t M,
+__global__ __launch_bounds__(kWG) void k_geometry(const double *__restrict__ verts,
                                                   const int32_t *__restrict__ tris, int N, FarRule rule,
                                                   FarRule ruleL, int4 *tri4, double4 *cen4, double *area,
                                                   double4 *qpA64, double *qpS64, float4 *qpA32, float *qpS32,
@@ -403,7 +403,7 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ rowcn
   if (t == 1023) rowptr[N] = (int32_t)acc;
 }
 
-int launch_geometry(const double *verts, int64_t M, const int32_t *tris, int64_t N, int far_order,
+int launch_geometry(const double *verts, const int32_t *tris, int64_t N, int far_order,
                     void *mesh_ws, hipStream_t s) {
   FarRule r{};
   double x[8], w[8];
@@ -422,7 +422,7 @@ int launch_geometry(const double *verts, int64_t M, const int32_t *tris, int64_t
   MeshLayout L(N);
   char *base = static_cast<char *>(mesh_ws);
   int grid = (int)((N + kWG - 1) / kWG);
-  hipLaunchKernelGGL(k_geometry, dim3(grid), dim3(kWG), 0, s, verts, M, tris, (int)N, r, rL,
+  hipLaunchKernelGGL(k_geometry, dim3(grid), dim3(kWG), 0, s, verts, tris, (int)N, r, rL,
                      reinterpret_cast<int4 *>(base + L.tri4), reinterpret_cast<double4 *>(base + L.cen4),
                      reinterpret_cast<double *>(base + L.area), reinterpret_cast<double4 *>(base + L.qpA64),
                      reinterpret_cast<double *>(base + L.qpS64), reinterpret_cast<float4 *>(base + L.qpA32),

@@ -1037,7 +1037,7 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
   if (rank < 0 || rank >= S.wg_count) return;
   const int G = S.wg_count;
   const int N = (int)S.N;
-  const int t = threadIdx.x, w = t >> 6;
+  const int t = threadIdx.x;
   const int r0 = (int)((int64_t)N * rank / G), r1 = (int)((int64_t)N * (rank + 1) / G);
   const SolveLayout Lay(S.N, MIXED ? BC_MIXED : BC_FP64);
   const int64_t ld = Lay.ld;
@@ -1052,7 +1052,6 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
   gptr<double> cpD = reinterpret_cast<gptr<double>>(ws + Lay.cpart);
   gptr<VT> rpV = reinterpret_cast<gptr<VT>>(ws + Lay.rpart);
   gptr<VT> cpV = reinterpret_cast<gptr<VT>>(ws + Lay.cpart);
-  VT *bandV = reinterpret_cast<VT *>(s_band);
   gptr<const MT> V = as_global(static_cast<const MT *>(S.V));
   gptr<const double> b = as_global(S.area);
   gptr<double> sigma = as_global(S.sigma);
@@ -1119,13 +1118,13 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
       // r = b - A x in FP64 (x = 0 at the first step without an initial guess)
       const bool zero_x = outer == 0 && !P.x0_given;
       if (!zero_x) {
-        double unused = 0.0, dummy[1];
+        double dummy[1];
         if (t == 0) {
           s_prod.V = (gptr<const void>)V; s_prod.x = (gptr<const void>)x64;
           s_prod.rp = (gptr<void>)rpD; s_prod.cp = (gptr<void>)cpD; s_prod.H = H;
         }
         __syncthreads();
-        unused = solver_product<MT, double, double, false>((lptr<ProdArgs>)&s_prod, (lptr<double>)s_buf);
+        (void)solver_product<MT, double, double, false>((lptr<ProdArgs>)&s_prod, (lptr<double>)s_buf);
         if (!sys_sync<1>(bar, none, dummy, l_red, l_flag)) { aborted = true; break; }
         strip_gather<double>(H, r0, r1, rpD, cpD, (lptr<double>)s_part, (lptr<double>)s_band);
       }
