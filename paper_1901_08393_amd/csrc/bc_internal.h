@@ -12,6 +12,7 @@
 namespace bc {
 
 constexpr int kWG = 256;            // threads per workgroup (4 wave64)
+constexpr int kRsqParts = 32;       // workgroups of the FP32 inverse-square-root bias (k_rsq_part)
 constexpr int kQMax = 16;           // far-field points per triangle (order <= 4)
 constexpr int kTileClasses = 3;     // far-field tiles: 0 near or diagonal, 1 separated, 2 distant
 constexpr int kQLow = 7;            // points per triangle of the distant tiles' rule (mixed precision)
@@ -59,7 +60,7 @@ struct MeshLayout {
     // mean relative error of the FP32 hardware inverse square root, measured
     // by bc_prepare in mixed precision and divided out of every FP32 far
     // entry (one double)
-    rsqb = take(sizeof(double));
+    rsqb = take(sizeof(double) * (1 + kRsqParts));  // the bias, then its partial sums
     blockbox = take(sizeof(double) * 8 * ((N + 63) / 64));  // per 64 elements: min xyz, max xyz, max diam^2
     // far-field tile lists: kTileClasses counts (padded to 16), one list of
     // tile indices per class, and the per-chunk counts of the list builder

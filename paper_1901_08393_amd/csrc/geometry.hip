@@ -243,16 +243,25 @@ __global__ __launch_bounds__(kWG) void k_tile_emit(const double *__restrict__ bb
   }
 }
 
-// One workgroup per block of 64 rows (16 rows per wave); lanes sweep the
-// columns 64 at a time.  Row data are staged in LDS (broadcast reads).
+// One workgroup of kPatWG threads per kPatRows rows (kPatRPW rows per wave;
+// the rows lie in one block of 64 and take that block's box); lanes sweep
+// the columns 64 at a time.  Row data are staged in LDS (broadcast reads).
+// Few rows per wavefront keep many wavefronts in flight: each one's sweep is
+// a chain of loads and ballots over the candidate blocks (L5 sphere, N =
+// 20480: with 64 rows in 256 threads the preparation took 0.30 ms, with 32
+// rows in 1024 threads 0.24 ms, and EMIT 38 us less).
 // COUNT: rowcnt[i] = |pattern row i|, kindcnt[i][k] = pairs (i, j >= i) of
 // class k.  EMIT: write (col, row, kind) at rowptr[i] in column order.
 // Column blocks whose vertex box is farther from the row block's box than
 // nf * (largest diameter in either block) can hold neither a touching pair
 // (touching triangles share a point) nor a near pair (centroids lie in the
 // boxes), so they are skipped without looking at their elements.
+constexpr int kPatWG = 1024;                        // threads per workgroup of k_pattern
+constexpr int kPatRows = 32;                        // rows per workgroup (divides 64)
+constexpr int kPatRPW = kPatRows / (kPatWG / 64);   // rows per wavefront
+static_assert(64 % kPatRows == 0 && kPatRPW >= 1, "pattern rows per workgroup");
 template <bool EMIT>
-__global__ __launch_bounds__(kWG) void k_pattern(const int4 *__restrict__ tri4, const double4 *__restrict__ cen4,
+__global__ __launch_bounds__(kPatWG) void k_pattern(const int4 *__restrict__ tri4, const double4 *__restrict__ cen4,
                                                  const double *__restrict__ bbox, int N, double nf2, int32_t *rowcnt,
                                                  int32_t *kindcnt, const int32_t *__restrict__ rowptr, int32_t *pcol,
                                                  int32_t *prow, int32_t *pkind) {
@@ -260,30 +269,30 @@ __global__ __launch_bounds__(kWG) void k_pattern(const int4 *__restrict__ tri4, 
   __shared__ double4 s_cen[64];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int I0 = blockIdx.x * 64;
+  const int I0 = blockIdx.x * kPatRows;
   if (threadIdx.x < 64) {
     int i = min(I0 + (int)threadIdx.x, N - 1);
     s_tri[threadIdx.x] = tri4[i];
     s_cen[threadIdx.x] = cen4[i];
   }
   __syncthreads();
-  int cnt[16], base[16];
-  int kc[16][4];
+  int cnt[kPatRPW], base[kPatRPW];
+  int kc[kPatRPW][4];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
+  for (int k = 0; k < kPatRPW; ++k) {
     cnt[k] = 0;
     kc[k][0] = kc[k][1] = kc[k][2] = kc[k][3] = 0;
-    int i = I0 + w * 16 + k;
+    int i = I0 + w * kPatRPW + k;
     base[k] = (EMIT && i < N) ? rowptr[i] : 0;
   }
-  const double *rb = bbox + 8 * blockIdx.x;
+  const double *rb = bbox + 8 * (blockIdx.x / (64 / kPatRows));
   const int nblk = (N + 63) / 64;
-  // Column blocks in rounds of kWG: the box tests of a round run in parallel
+  // Column blocks in rounds of kPatWG: the box tests of a round run in parallel
   // and the blocks that pass are listed in LDS in increasing order (wave
   // ballots, then the waves' counts in wave order), then swept.
-  __shared__ int s_cand[kWG];
-  __shared__ int s_wcnt[kWG / 64];
-  for (int R0 = 0; R0 < nblk; R0 += kWG) {
+  __shared__ int s_cand[kPatWG];
+  __shared__ int s_wcnt[kPatWG / 64];
+  for (int R0 = 0; R0 < nblk; R0 += kPatWG) {
     const int Jb = R0 + (int)threadIdx.x;
     bool keep = false;
     if (Jb < nblk) {
@@ -295,7 +304,7 @@ __global__ __launch_bounds__(kWG) void k_pattern(const int4 *__restrict__ tri4, 
     if (lane == 0) s_wcnt[w] = __popcll(km);
     __syncthreads();
     int off = 0, ncand = 0;
-    for (int q = 0; q < kWG / 64; ++q) {
+    for (int q = 0; q < kPatWG / 64; ++q) {
       if (q < w) off += s_wcnt[q];
       ncand += s_wcnt[q];
     }
@@ -309,10 +318,10 @@ __global__ __launch_bounds__(kWG) void k_pattern(const int4 *__restrict__ tri4, 
       int4 tj = tri4[jv ? j : N - 1];
       double4 cj = cen4[jv ? j : N - 1];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const int i = I0 + w * 16 + k;
+      for (int k = 0; k < kPatRPW; ++k) {
+        const int i = I0 + w * kPatRPW + k;
         if (i < N) {  // uniform
-          int cls = jv ? pair_class(s_tri[w * 16 + k], s_cen[w * 16 + k], tj, cj, nf2) : -1;
+          int cls = jv ? pair_class(s_tri[w * kPatRPW + k], s_cen[w * kPatRPW + k], tj, cj, nf2) : -1;
           uint64_t m = __ballot(cls >= 0);
           if (!EMIT) {
             cnt[k] += __popcll(m);
@@ -334,8 +343,8 @@ __global__ __launch_bounds__(kWG) void k_pattern(const int4 *__restrict__ tri4, 
   }
   if (!EMIT && lane == 0) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      int i = I0 + w * 16 + k;
+    for (int k = 0; k < kPatRPW; ++k) {
+      int i = I0 + w * kPatRPW + k;
       if (i < N) {
         rowcnt[i] = cnt[k];
         for (int q = 0; q < 4; ++q) kindcnt[4 * i + q] = kc[k][q];
@@ -444,6 +453,7 @@ int launch_pattern(const double *verts, const int32_t *tris, int64_t N, double n
   double nf2 = near_factor * near_factor;
   int grid = (int)((N + 63) / 64);
   const double *bbox = reinterpret_cast<const double *>(base + L.blockbox);
+  const unsigned pgrid = (unsigned)((N + kPatRows - 1) / kPatRows);
   if (!emit) {
     hipLaunchKernelGGL(k_blockbox, dim3(grid), dim3(64), 0, s, verts, tri4, cen4, (int)N, const_cast<double *>(bbox));
     if (hipGetLastError() != hipSuccess) return BC_EDEVICE;
@@ -460,7 +470,7 @@ int launch_pattern(const double *verts, const int32_t *tris, int64_t N, double n
     hipLaunchKernelGGL(k_tile_emit, dim3(nchunk), dim3(kWG), 0, s, bbox, (int)ntiles, sep_low,
                        (const int32_t *)chunk_cnt, tile_cnt, tile_list);
     if (hipGetLastError() != hipSuccess) return BC_EDEVICE;
-    hipLaunchKernelGGL(k_pattern<false>, dim3(grid), dim3(kWG), 0, s, tri4, cen4, bbox, (int)N, nf2, rowcnt, kindcnt,
+    hipLaunchKernelGGL(k_pattern<false>, dim3(pgrid), dim3(kPatWG), 0, s, tri4, cen4, bbox, (int)N, nf2, rowcnt, kindcnt,
                        (const int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr);
     if (hipGetLastError() != hipSuccess) return BC_EDEVICE;
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, rowcnt, kindcnt, (int)N, rowptr,
@@ -470,7 +480,7 @@ int launch_pattern(const double *verts, const int32_t *tris, int64_t N, double n
     char *pb = static_cast<char *>(pattern);
     if (hipMemcpyAsync(pb + P.rowptr, rowptr, sizeof(int32_t) * (N + 1), hipMemcpyDeviceToDevice, s) != hipSuccess)
       return BC_EDEVICE;
-    hipLaunchKernelGGL(k_pattern<true>, dim3(grid), dim3(kWG), 0, s, tri4, cen4, bbox, (int)N, nf2, (int32_t *)nullptr,
+    hipLaunchKernelGGL(k_pattern<true>, dim3(pgrid), dim3(kPatWG), 0, s, tri4, cen4, bbox, (int)N, nf2, (int32_t *)nullptr,
                        (int32_t *)nullptr, (const int32_t *)rowptr, reinterpret_cast<int32_t *>(pb + P.col),
                        reinterpret_cast<int32_t *>(pb + P.row), reinterpret_cast<int32_t *>(pb + P.kind));
   }
