@@ -1127,16 +1127,27 @@ __global__ __launch_bounds__(kSolveWG) __attribute__((amdgpu_waves_per_eu(4))) v
         (void)solver_product<MT, double, double, false>((lptr<ProdArgs>)&s_prod, (lptr<double>)s_buf);
         if (!sys_sync<1>(bar, none, dummy, l_red, l_flag)) { aborted = true; break; }
         strip_gather<double>(H, r0, r1, rpD, cpD, (lptr<double>)s_part, (lptr<double>)s_band);
+        if (MIXED && S.pcorr != nullptr) {
+          // the FP64 near-field correction of the mixed matrix: one wavefront
+          // per row, its lanes over the row's pattern entries (gathers in
+          // parallel), summed in a fixed order and added to the product
+          const int lane = t & 63;
+          for (int i = r0 + (t >> 6); i < r1; i += kSolveWG / 64) {
+            const int e0 = prowptr[i], e1 = prowptr[i + 1];
+            double c = 0.0;
+            for (int e = e0 + lane; e < e1; e += 64) c = __builtin_fma(pcorr[e], x64[pcol[e]], c);
+            c = wave_sum(c);
+            if (lane == 0) s_band[i - r0] += c;
+          }
+          __syncthreads();
+        }
       }
       // sums: ||r||^2, then ||b||^2 at the first step and x^T r after it,
       // ||x||^2, b^T x
       const bool first = outer == 0;
       double pr = 0.0, pb = 0.0, pxx = 0.0, pbx = 0.0;
       for (int i = r0 + t; i < r1; i += kSolveWG) {
-        double acc = zero_x ? 0.0 : s_band[i - r0];
-        if (MIXED && S.pcorr != nullptr && !zero_x) {
-          for (int e = prowptr[i]; e < prowptr[i + 1]; ++e) acc = __builtin_fma(pcorr[e], x64[pcol[e]], acc);
-        }
+        const double acc = zero_x ? 0.0 : s_band[i - r0];
         const double ri = b[i] - acc, xi = x64[i];
         r64[i] = ri;
         pr = __builtin_fma(ri, ri, pr);
