@@ -15,6 +15,13 @@
 
 namespace bc {
 
+// One wavefront per element i: its lanes load the entries of row i once
+// (class, column, the column element's vertices, area and sigma), and for each
+// vertex z of T_i a ballot selects the elements containing z; lane order is
+// column order, so adding the selected lanes in increasing order gives the
+// sums of the plain row loop, term by term.
+constexpr int kZZRows = kWG / 64;  // elements per workgroup
+
 __global__ __launch_bounds__(kWG) void k_zz(const int4 *__restrict__ tri4, const double4 *__restrict__ cen4,
                                             const double *__restrict__ area, const int32_t *__restrict__ prowptr,
                                             const int32_t *__restrict__ pcol, const int32_t *__restrict__ pkind,
@@ -22,26 +29,38 @@ __global__ __launch_bounds__(kWG) void k_zz(const int4 *__restrict__ tri4, const
                                             double *__restrict__ eta2) {
   // no contraction: the sums round like the plain expressions
 #pragma clang fp contract(off)
-  const int i = blockIdx.x * kWG + threadIdx.x;
-  if (i >= N) return;
+  const int lane = (int)threadIdx.x & 63;
+  const int i = (int)blockIdx.x * kZZRows + ((int)threadIdx.x >> 6);
+  if (i >= N) return;  // wavefront-uniform
   const int4 ti = tri4[i];
   const int zs[3] = {ti.x, ti.y, ti.z};
-  double d[3];
-  const double si = sigma[i];
-  for (int k = 0; k < 3; ++k) {
-    const int z = zs[k];
-    double num = 0.0, den = 0.0;
-    for (int e = prowptr[i]; e < prowptr[i + 1]; ++e) {
-      if (pkind[e] == kNear) continue;
+  double num[3] = {0.0, 0.0, 0.0}, den[3] = {0.0, 0.0, 0.0};
+  const int e0 = prowptr[i], e1 = prowptr[i + 1];
+  for (int c = e0; c < e1; c += 64) {
+    const int e = c + lane;
+    bool has[3] = {false, false, false};
+    double aj = 0.0, asj = 0.0;
+    if (e < e1 && pkind[e] != kNear) {
       const int j = pcol[e];
       const int4 tj = tri4[j];
-      if (tj.x == z || tj.y == z || tj.z == z) {
-        num += area[j] * sigma[j];
-        den += area[j];
+      aj = area[j];
+      asj = aj * sigma[j];
+      for (int k = 0; k < 3; ++k) has[k] = tj.x == zs[k] || tj.y == zs[k] || tj.z == zs[k];
+    }
+    for (int k = 0; k < 3; ++k) {
+      uint64_t m = __ballot(has[k]);
+      while (m) {  // increasing lanes: increasing columns
+        const int l = __builtin_ctzll(m);
+        m &= m - 1;
+        num[k] += lane_f(asj, l);
+        den[k] += lane_f(aj, l);
       }
     }
-    d[k] = num / den - si;
   }
+  if (lane != 0) return;
+  const double si = sigma[i];
+  double d[3];
+  for (int k = 0; k < 3; ++k) d[k] = num[k] / den[k] - si;
   const double s = d[0] + d[1] + d[2];
   const double l2 = area[i] / 12.0 * (s * s + d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
   const double h = h_mode == 0 ? sqrt(cen4[i].w) : sqrt(area[i]);
@@ -54,7 +73,7 @@ int launch_zz(const int32_t *tris, int64_t N, const void *mesh_ws, const void *p
   const MeshView m = mesh_view(mesh_ws, N);
   PatternLayout P(N, nnz, BC_FP64);  // offsets of rowptr/col/kind do not depend on precision
   const char *pb = static_cast<const char *>(pattern);
-  hipLaunchKernelGGL(k_zz, dim3((int)((N + kWG - 1) / kWG)), dim3(kWG), 0, s, m.tri4, m.cen4, m.area,
+  hipLaunchKernelGGL(k_zz, dim3((unsigned)((N + kZZRows - 1) / kZZRows)), dim3(kWG), 0, s, m.tri4, m.cen4, m.area,
                      reinterpret_cast<const int32_t *>(pb + P.rowptr), reinterpret_cast<const int32_t *>(pb + P.col),
                      reinterpret_cast<const int32_t *>(pb + P.kind), sigma, (int)N, h_mode, eta2);
   return hipGetLastError() == hipSuccess ? BC_OK : BC_EDEVICE;
