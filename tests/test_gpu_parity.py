@@ -539,6 +539,23 @@ def test_zz_indicators(api, name):
         assert np.allclose(eta2, ref, rtol=1e-12, atol=1e-12 * ref.max())
 
 
+
+def test_zz_indicators_long_pattern_rows(api):
+    """ZZ on a mixed-precision pattern whose rows hold near pairs and exceed
+    64 entries: the kernel skips the near entries and takes a row 64 entries
+    at a time, and must still give the indicators of the touching pairs."""
+    _flush("zz cube768 mixed, near factor 6")
+    m = MESHES["cube768"]()
+    cap_ref, V, b, x = _oracle_cap("cube768")
+    p = api.CapacityProblem(m.verts, m.tris, "mixed", near_factor=6.0)
+    p.assemble()
+    rowptr = p.pattern_arrays()[0].cpu().numpy()
+    assert np.diff(rowptr).max() > 128  # three or more chunks of 64 in the longest rows
+    for h_mode, hname in ((0, "diam"), (1, "area")):
+        eta2 = p.zz(torch.from_numpy(x).cuda(), h_mode).cpu().numpy()
+        ref = oracle.zz_indicators(m.verts, m.tris, x, hname)
+        assert np.allclose(eta2, ref, rtol=1e-12, atol=1e-12 * ref.max())
+
 # ---------------------------------------------------------------- batching
 
 @pytest.mark.parametrize("cap_rtol", [0.0, 1e-8])
