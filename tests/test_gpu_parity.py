@@ -556,6 +556,23 @@ def test_zz_indicators_long_pattern_rows(api):
         ref = oracle.zz_indicators(m.verts, m.tris, x, hname)
         assert np.allclose(eta2, ref, rtol=1e-12, atol=1e-12 * ref.max())
 
+
+def test_solve_mixed_long_pattern_rows(api):
+    """The mixed solve with near pairs filling pattern rows beyond 64 entries:
+    the residual phase adds each row's FP64 corrections 64 entries at a time."""
+    _flush("solve mixed cube768, near factor 6")
+    m = MESHES["cube768"]()
+    cap_ref, *_ = _oracle_cap("cube768")
+    p = api.CapacityProblem(m.verts, m.tris, "mixed", near_factor=6.0)
+    p.assemble()
+    assert np.diff(p.pattern_arrays()[0].cpu().numpy()).max() > 128
+    for kw in ({}, {"cap_rtol": 1e-8}):
+        r = p.solve(**kw)
+        assert r.ok, r
+        err = abs(r.cap - cap_ref) / cap_ref
+        _flush(f"  {kw} cap rel err {err:.3e} iters {r.iters} outer {r.outer}")
+        assert err <= 1e-8, (kw, err)
+
 # ---------------------------------------------------------------- batching
 
 @pytest.mark.parametrize("cap_rtol", [0.0, 1e-8])
