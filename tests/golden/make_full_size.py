@@ -14,6 +14,10 @@ can tell whether ``synth`` still builds the same mesh):
 * ``voxel_60k``: the voxel union of 26 unit voxels in a 4^3 lattice
   (seed 4), NVB-refined uniformly and then by bisection of the largest
   elements until N >= 60000 (``synth.refine_to_size``), N = 60000.
+* ``serve_voxel``, ``serve_hull``, ``serve_box``: the largest request of each
+  kind in the serving stream (``synth.request_stream(512, seed=5)``: requests
+  2, 151 and 307, N = 29900, 29442 and 29800 or near), at the top of the
+  serving workload's size range.
 
 For each: the capacity of the FP64 Galerkin solution (eq. "cap:ell"; 4 x 4
 regular rule, order-4 singular rules; dense Cholesky, or for more than 2^31
@@ -65,7 +69,28 @@ def voxel_60k():
                   "voxels": int(m.meta["voxels"])}
 
 
-WORKLOADS = {"sphere_L5": sphere_L5, "voxel_60k": voxel_60k}
+def _serving_request(rid: int):
+    reqs = {q.rid: q for q in synth.request_stream(512, seed=5)}
+    r = reqs[rid]
+    m = r.build_mesh()
+    return m.verts, m.tris, {"recipe": f"synth.request_stream(512, seed=5), request {rid}: {r.kind} {r.params}",
+                             "kind": r.kind}
+
+
+def serve_voxel():
+    return _serving_request(2)
+
+
+def serve_hull():
+    return _serving_request(151)
+
+
+def serve_box():
+    return _serving_request(307)
+
+
+WORKLOADS = {"sphere_L5": sphere_L5, "voxel_60k": voxel_60k, "serve_voxel": serve_voxel, "serve_hull": serve_hull,
+             "serve_box": serve_box}
 
 
 def run(name: str) -> dict:

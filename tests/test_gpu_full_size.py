@@ -1,11 +1,12 @@
 """The benchmark's full-size workloads against the FP64 oracle.
 
 The oracle's results for the level-5 sphere (N = 20480, the headline
-workload) and for a voxel union refined to N = 60000 (28.8 GB in FP64) take
-minutes to half an hour on the CPU, so they are stored in
-tests/golden/full_size.json by tests/golden/make_full_size.py, which calls
-only the oracle and the mesh generators.  At these sizes every solver
-launch has 256 workgroups and bands of more than 80 rows.
+workload), for a voxel union refined to N = 60000 (28.8 GB in FP64) and for
+the largest request of each kind in the serving stream (voxel union, convex
+hull, box; N near 30000) take minutes to an hour on the CPU, so they are
+stored in tests/golden/full_size.json by tests/golden/make_full_size.py,
+which calls only the oracle and the mesh generators.  At these sizes every
+solver launch has 256 workgroups and bands of more than 80 rows.
 
 Bars: the FP64 capacity within a relative 1e-12 of the oracle's and the
 mixed one within 1e-8 (the two forms' stated accuracies); the FP64 product
@@ -81,7 +82,7 @@ def host_product(V, N, x, rows=4096):
     return y, a
 
 
-@pytest.mark.parametrize("name", ["sphere_L5", "voxel_60k"])
+@pytest.mark.parametrize("name", ["sphere_L5", "voxel_60k", "serve_voxel", "serve_hull", "serve_box"])
 def test_full_size_capacity_vs_oracle(api, name):
     """Cap of the FP64 and of the mixed GPU forms (the benchmark's options:
     Radon's rule on distant tiles, stop on the capacity bound 1e-8) against
