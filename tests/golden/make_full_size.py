@@ -18,6 +18,10 @@ can tell whether ``synth`` still builds the same mesh):
   kind in the serving stream (``synth.request_stream(512, seed=5)``: requests
   2, 151 and 307, N = 29900, 29442 and 29800 or near), at the top of the
   serving workload's size range.
+* ``dual_cube``: Algorithm 1's dual system (Section 2.6) on the 12-triangle
+  cube of Table 1 refined uniformly four times (N = 3072, N_bary = 18432):
+  the dual capacity, the dual solution at 64 seeded vertices and the ZZ
+  indicators (|T|^(1/2)) at 64 seeded elements and in total.
 
 For each: the capacity of the FP64 Galerkin solution (eq. "cap:ell"; 4 x 4
 regular rule, order-4 singular rules; dense Cholesky, or for more than 2^31
@@ -93,6 +97,42 @@ WORKLOADS = {"sphere_L5": sphere_L5, "voxel_60k": voxel_60k, "serve_voxel": serv
              "serve_box": serve_box}
 
 
+def dual_cube():
+    m = synth.cube12()
+    v, t, _ = synth.refine_uniform(m.verts, m.tris, 4)
+    return v, t, {"recipe": "refine_uniform(cube12, 4): the 12-triangle cube of Table 1 refined uniformly four times"}
+
+
+DUAL_WORKLOADS = {"dual_cube": dual_cube}
+
+
+def run_dual(name: str) -> dict:
+    """Algorithm 1's dual system on the barycentric refinement (Section 2.6):
+    V_bary assembled densely, the dual matrix P^T V_bary P solved by Cholesky,
+    the capacity and the ZZ indicators of the dual solution."""
+    verts, tris, meta = DUAL_WORKLOADS[name]()
+    N = len(tris)
+    t0 = time.perf_counter()
+    Vb, P, bv, bt = oracle.dual.assemble_dual(verts, tris)
+    t_asm = time.perf_counter() - t0
+    f = oracle.dual.dual_load(verts, tris)
+    t0 = time.perf_counter()
+    x, _ = oracle.dual.solve_dual(Vb, P, f)
+    t_solve = time.perf_counter() - t0
+    del Vb
+    cap = oracle.dual.capacity_dual(x, f)
+    eta2 = oracle.dual.zz_dual(verts, tris, x, "area")
+    M = np.asarray(verts).shape[0]
+    vrows = np.sort(np.random.default_rng(7).choice(M, size=64, replace=False))
+    erows = np.sort(np.random.default_rng(8).choice(N, size=64, replace=False))
+    print(f"{name}: N={N} N_bary={len(bt)} cap={cap!r} assemble {t_asm:.0f} s solve {t_solve:.0f} s", flush=True)
+    return dict(meta, N=N, N_bary=len(bt), M=int(M), mesh_sha=mesh_sha(verts, tris), far_order=4, ss_order=4,
+                cap=cap, x_rows=vrows.tolist(), x=[float(x[i]) for i in vrows.tolist()],
+                eta2_rows=erows.tolist(), eta2=[float(eta2[i]) for i in erows.tolist()],
+                eta2_sum=math.fsum(eta2.tolist()), solver="cholesky",
+                oracle_seconds={"assemble": round(t_asm, 1), "solve": round(t_solve, 1)}, cores=os.cpu_count())
+
+
 def run(name: str) -> dict:
     verts, tris, meta = WORKLOADS[name]()
     N = len(tris)
@@ -127,11 +167,11 @@ def run(name: str) -> dict:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--only", choices=sorted(WORKLOADS), default=None)
+    ap.add_argument("--only", choices=sorted(WORKLOADS) + sorted(DUAL_WORKLOADS), default=None)
     a = ap.parse_args()
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
-    for name in ([a.only] if a.only else sorted(WORKLOADS)):
-        data[name] = run(name)
+    for name in ([a.only] if a.only else sorted(WORKLOADS) + sorted(DUAL_WORKLOADS)):
+        data[name] = run_dual(name) if name in DUAL_WORKLOADS else run(name)
         data["_about"] = ("FP64 oracle results (tests/golden/make_full_size.py; oracle/ and synth/ only): "
                           "Cap, 1^T V 1 and sampled row sums of V")
         with open(OUT, "w") as f:

@@ -3,8 +3,9 @@
 The oracle's results for the level-5 sphere (N = 20480, the headline
 workload), for a voxel union refined to N = 60000 (28.8 GB in FP64) and for
 the largest request of each kind in the serving stream (voxel union, convex
-hull, box; N near 30000) take minutes to an hour on the CPU, so they are
-stored in tests/golden/full_size.json by tests/golden/make_full_size.py,
+hull, box; N near 30000), and for Algorithm 1's dual system on the refined
+cube of Table 1 (N_bary = 18432) take minutes to an hour on the CPU, so they
+are stored in tests/golden/full_size.json by tests/golden/make_full_size.py,
 which calls only the oracle and the mesh generators.  At these sizes every
 solver launch has 256 workgroups and bands of more than 80 rows.
 
@@ -53,7 +54,8 @@ _MESH = {}
 
 def workload(name):
     if name not in _MESH:
-        v, t, _ = MAKER.WORKLOADS[name]()
+        make = MAKER.WORKLOADS.get(name) or MAKER.DUAL_WORKLOADS[name]
+        v, t, _ = make()
         assert MAKER.mesh_sha(v, t) == gold()[name]["mesh_sha"], "synth no longer builds the stored mesh"
         _MESH[name] = (np.asarray(v), np.asarray(t, dtype=np.int32))
     return _MESH[name]
@@ -123,6 +125,35 @@ def test_full_size_capacity_vs_oracle(api, name):
     del q
     torch.cuda.empty_cache()
 
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_size_dual_vs_oracle(api, precision):
+    """Algorithm 1's dual system (Section 2.6) on the 12-triangle cube refined
+    uniformly four times (N = 3072, N_bary = 18432; 2.7 GB V_bary in FP64)
+    against the oracle's Cholesky solution: Cap within 1e-12 (FP64) and 1e-8
+    (mixed: FP32 V_bary with the FP64 correction), the dual solution at 64
+    seeded vertices within 1e-10 and 1e-6 of max |x|, and in FP64 the ZZ
+    indicators (|T|^(1/2)) within 1e-9."""
+    g = gold()["dual_cube"]
+    v, t = workload("dual_cube")
+    _flush(f"full size dual cube N={len(t)} N_bary={g['N_bary']} {precision}")
+    p = api.DualProblem(v, t, restart=100, precision=precision)
+    p.assemble()
+    r = p.solve(rtol=1e-13)
+    assert r.ok, r
+    err = abs(r.cap - g["cap"]) / g["cap"]
+    _flush(f"  cap {r.cap!r} oracle {g['cap']!r} rel {err:.2e} GMRES steps {r.iters}")
+    assert err <= (1e-12 if precision == "fp64" else 1e-8)
+    x = p.x.cpu().numpy()
+    dx = np.abs(x[g["x_rows"]] - np.asarray(g["x"])).max() / np.abs(x).max()
+    assert dx <= (1e-10 if precision == "fp64" else 1e-6), dx
+    if precision == "fp64":
+        eta2 = p.zz(1).cpu().numpy()
+        assert np.allclose(eta2[g["eta2_rows"]], g["eta2"], rtol=1e-9)
+        assert abs(float(np.sum(eta2)) - g["eta2_sum"]) <= 1e-9 * g["eta2_sum"]
+    del p
+    torch.cuda.empty_cache()
 
 def test_product_60k_against_host(api):
     """bc_matvec with the FP64 and the FP32 matrix of N = 60000 against a
