@@ -22,6 +22,10 @@ can tell whether ``synth`` still builds the same mesh):
   cube of Table 1 refined uniformly four times (N = 3072, N_bary = 18432):
   the dual capacity, the dual solution at 64 seeded vertices and the ZZ
   indicators (|T|^(1/2)) at 64 seeded elements and in total.
+* ``adaptive_voxel``: configuration 3 run by the oracle (five steps of
+  solve, ZZ, Doerfler with theta = 1/2 and NVB from about 2.5k to about 28k
+  triangles): per step the mesh's hash, Cap, the sum of eta^2 and the number
+  of marked elements.
 
 For each: the capacity of the FP64 Galerkin solution (eq. "cap:ell"; 4 x 4
 regular rule, order-4 singular rules; dense Cholesky, or for more than 2^31
@@ -106,6 +110,48 @@ def dual_cube():
 DUAL_WORKLOADS = {"dual_cube": dual_cube}
 
 
+def adaptive_voxel_start():
+    """Configuration 3's start: the voxel union of 26 unit voxels (4^3
+    lattice, seed 3), uniformly refined to about 2.5k triangles."""
+    m = synth.voxel_union(4, 0.4, 3)
+    v, t = m.verts, synth.init_reference_edges(m.verts, m.tris)
+    while len(t) * 4 <= 2600:
+        v, t, _ = synth.refine_uniform(v, t, 1)
+    return v, t
+
+
+def run_adaptive(name: str) -> dict:
+    """Configuration 3 run by the oracle: five steps of the FP64 Galerkin
+    solution, ZZ indicators (eq. "zz:T", diameter weights), Doerfler marking
+    (theta = 1/2) and NVB with the marked elements split into four, then the
+    last mesh's solution; per step the mesh's hash, Cap, the sum of eta^2 and
+    the number of marked elements."""
+    v, t = adaptive_voxel_start()
+    steps = []
+    t_all = time.perf_counter()
+    for level in range(6):
+        V = oracle.assemble(v, t, 4, 4)
+        b = oracle.rhs(v, t)
+        x = oracle.solve_direct(V, b, overwrite=True)
+        del V
+        cap = oracle.capacity(x, b)
+        eta2 = oracle.zz_indicators(v, t, x, "diam")
+        rec = {"level": level, "N": int(len(t)), "mesh_sha": mesh_sha(v, t), "cap": cap,
+               "eta2_sum": math.fsum(eta2.tolist())}
+        if level < 5:
+            mk = oracle.doerfler(eta2, 0.5)
+            rec["marked"] = int(len(mk))
+            v, t, _ = synth.refine_nvb(v, t, mk, "bisec3")
+        steps.append(rec)
+        print(f"{name} level {level}: N={rec['N']} cap={cap!r} marked={rec.get('marked')}", flush=True)
+    return {"recipe": "voxel_union(4, 0.4, 3), uniform NVB to ~2.5k, then 5 x (solve, ZZ diam, Doerfler 1/2, "
+                      "NVB bisec3)", "steps": steps, "far_order": 4, "ss_order": 4,
+            "oracle_seconds": round(time.perf_counter() - t_all, 1), "cores": os.cpu_count()}
+
+
+ADAPTIVE_WORKLOADS = {"adaptive_voxel": run_adaptive}
+
+
 def run_dual(name: str) -> dict:
     """Algorithm 1's dual system on the barycentric refinement (Section 2.6):
     V_bary assembled densely, the dual matrix P^T V_bary P solved by Cholesky,
@@ -167,11 +213,15 @@ def run(name: str) -> dict:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--only", choices=sorted(WORKLOADS) + sorted(DUAL_WORKLOADS), default=None)
+    names = sorted(WORKLOADS) + sorted(DUAL_WORKLOADS) + sorted(ADAPTIVE_WORKLOADS)
+    ap.add_argument("--only", choices=names, default=None)
     a = ap.parse_args()
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
-    for name in ([a.only] if a.only else sorted(WORKLOADS) + sorted(DUAL_WORKLOADS)):
-        data[name] = run_dual(name) if name in DUAL_WORKLOADS else run(name)
+    for name in ([a.only] if a.only else names):
+        if name in ADAPTIVE_WORKLOADS:
+            data[name] = ADAPTIVE_WORKLOADS[name](name)
+        else:
+            data[name] = run_dual(name) if name in DUAL_WORKLOADS else run(name)
         data["_about"] = ("FP64 oracle results (tests/golden/make_full_size.py; oracle/ and synth/ only): "
                           "Cap, 1^T V 1 and sampled row sums of V")
         with open(OUT, "w") as f:

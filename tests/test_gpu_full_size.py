@@ -3,8 +3,9 @@
 The oracle's results for the level-5 sphere (N = 20480, the headline
 workload), for a voxel union refined to N = 60000 (28.8 GB in FP64) and for
 the largest request of each kind in the serving stream (voxel union, convex
-hull, box; N near 30000), and for Algorithm 1's dual system on the refined
-cube of Table 1 (N_bary = 18432) take minutes to an hour on the CPU, so they
+hull, box; N near 30000), for Algorithm 1's dual system on the refined cube
+of Table 1 (N_bary = 18432) and for configuration 3's adaptive loop (five
+steps to about 28k triangles) take minutes to an hour on the CPU, so they
 are stored in tests/golden/full_size.json by tests/golden/make_full_size.py,
 which calls only the oracle and the mesh generators.  At these sizes every
 solver launch has 256 workgroups and bands of more than 80 rows.
@@ -153,6 +154,28 @@ def test_full_size_dual_vs_oracle(api, precision):
         assert np.allclose(eta2[g["eta2_rows"]], g["eta2"], rtol=1e-9)
         assert abs(float(np.sum(eta2)) - g["eta2_sum"]) <= 1e-9 * g["eta2_sum"]
     del p
+    torch.cuda.empty_cache()
+
+
+def test_full_size_adaptive_vs_oracle():
+    """Configuration 3 on the GPU (the benchmark's five steps, FP64: solve,
+    ZZ, Doerfler with theta = 1/2, NVB with marked elements split into four,
+    about 2.5k to 28k triangles) against the same loop run by the oracle:
+    every step's mesh the oracle's (the same elements marked), Cap within
+    1e-12 and the sum of eta^2 within 1e-9."""
+    from paper_1901_08393_amd.adaptive import adaptive_capacity
+
+    g = gold()["adaptive_voxel"]["steps"]
+    v, t = MAKER.adaptive_voxel_start()
+    _flush(f"full size adaptive voxel union from N={len(t)}")
+    steps = adaptive_capacity(v, t, steps=5, theta=0.5, precision="fp64", refine="bisec3", keep=True)
+    assert len(steps) == len(g)
+    for s, r in zip(steps, g):
+        _flush(f"  level {s.level} N={s.N} cap {s.cap!r} oracle {r['cap']!r} marked {s.n_marked}")
+        assert s.N == r["N"] and MAKER.mesh_sha(s.verts, s.tris) == r["mesh_sha"], s.level
+        assert abs(s.cap - r["cap"]) <= 1e-12 * r["cap"]
+        assert abs(s.eta2 - r["eta2_sum"]) <= 1e-9 * r["eta2_sum"]
+        assert s.n_marked == r.get("marked", 0)
     torch.cuda.empty_cache()
 
 def test_product_60k_against_host(api):
