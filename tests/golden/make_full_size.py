@@ -11,6 +11,8 @@ can tell whether ``synth`` still builds the same mesh):
 
 * ``sphere_L5``: the sphere of radius r ~ U[0.5, 2] (numpy default_rng(2)) as
   a level-5 icosphere, N = 20480 (the headline workload);
+* ``sphere_L4``: the same sphere as a level-4 icosphere, N = 5120 (the
+  configuration's smaller mesh);
 * ``voxel_60k``: the voxel union of 26 unit voxels in a 4^3 lattice
   (seed 4), NVB-refined uniformly and then by bisection of the largest
   elements until N >= 60000 (``synth.refine_to_size``), N = 60000.
@@ -69,6 +71,12 @@ def sphere_L5():
     return m.verts, m.tris, {"recipe": "icosphere(5, r), r = default_rng(2).uniform(0.5, 2)", "r": r}
 
 
+def sphere_L4():
+    r = float(np.random.default_rng(2).uniform(0.5, 2.0))
+    m = synth.icosphere(4, r)
+    return m.verts, m.tris, {"recipe": "icosphere(4, r), r = default_rng(2).uniform(0.5, 2)", "r": r}
+
+
 def voxel_60k():
     m = synth.voxel_union(4, 0.4, 4)
     t0 = synth.init_reference_edges(m.verts, m.tris)
@@ -97,7 +105,7 @@ def serve_box():
     return _serving_request(307)
 
 
-WORKLOADS = {"sphere_L5": sphere_L5, "voxel_60k": voxel_60k, "serve_voxel": serve_voxel, "serve_hull": serve_hull,
+WORKLOADS = {"sphere_L4": sphere_L4, "sphere_L5": sphere_L5, "voxel_60k": voxel_60k, "serve_voxel": serve_voxel, "serve_hull": serve_hull,
              "serve_box": serve_box}
 
 

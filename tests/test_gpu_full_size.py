@@ -85,7 +85,7 @@ def host_product(V, N, x, rows=4096):
     return y, a
 
 
-@pytest.mark.parametrize("name", ["sphere_L5", "voxel_60k", "serve_voxel", "serve_hull", "serve_box"])
+@pytest.mark.parametrize("name", ["sphere_L4", "sphere_L5", "voxel_60k", "serve_voxel", "serve_hull", "serve_box"])
 def test_full_size_capacity_vs_oracle(api, name):
     """Cap of the FP64 and of the mixed GPU forms (the benchmark's options:
     Radon's rule on distant tiles, stop on the capacity bound 1e-8) against
