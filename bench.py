@@ -303,6 +303,15 @@ def serving_leg(n_requests: int, precisions=("mixed", "fp64"), cap_rtol: float =
     out = {"requests": len(reqs), "seed": 5, "policy": policy, "chunks_in_flight": pipeline,
            "N_range": [min(m.N for m in meshes), max(m.N for m in meshes)]}
     caps = {}
+    # the requests whose FP64 oracle capacity is stored (the largest of each
+    # kind in the stream; tests/golden/make_full_size.py), if this run has them
+    stored = {}
+    for gname, rid in (("serve_voxel", 2), ("serve_hull", 151), ("serve_box", 307)):
+        g = golden(gname)
+        idx = next((i for i, q in enumerate(reqs) if q.rid == rid), None)
+        if g and idx is not None and mesh_sha(meshes[idx].verts, meshes[idx].tris) == g["mesh_sha"]:
+            stored[rid] = g
+    vs_oracle = {}
     for prec in precisions:
         # the mixed form at the capacity tolerance; the FP64 form at its tight default, the reference
         srv = CapacityServer(prec, solve_opts={"cap_rtol": cap_rtol} if prec == "mixed" else None, policy=policy,
@@ -320,6 +329,11 @@ def serving_leg(n_requests: int, precisions=("mixed", "fp64"), cap_rtol: float =
             out[prec][key] = dict(poi, rate=rate, load=load)
             if load == loads[0]:
                 caps[prec] = np.array([r.cap for r in precs])
+                for r in precs:
+                    if r.rid in stored:
+                        g = stored[r.rid]
+                        vs_oracle.setdefault(prec, {})[f"request {r.rid} ({r.kind}, N={r.N})"] = \
+                            abs(r.cap - g["cap"]) / g["cap"]
             if log_fn:
                 log_fn(f"{prec}: saturated {sat['solves_per_s']:.1f} solves/s; poisson at {load:g} x: p50 "
                        f"{poi['p50_ms']:.1f} ms p99 {poi['p99_ms']:.1f} ms")
@@ -328,6 +342,8 @@ def serving_leg(n_requests: int, precisions=("mixed", "fp64"), cap_rtol: float =
     if "mixed" in caps and "fp64" in caps:
         rel = np.abs(caps["mixed"] - caps["fp64"]) / caps["fp64"]
         out["cap_rel_err_mixed_vs_fp64"] = {"max": float(rel.max()), "median": float(np.median(rel))}
+    if vs_oracle:
+        out["cap_rel_err_vs_oracle"] = vs_oracle
     return out
 
 

@@ -47,6 +47,9 @@ class Request:
 def request_stream(n: int = 512, seed: int = 5, rate: float = math.inf,
                    n_min: int = 500, n_max: int = 30000):
     rng = np.random.default_rng(seed)
+    # arrival times from a generator of their own, so that the requests
+    # themselves (kind, parameters, size, mesh seed) do not depend on the rate
+    arrivals = np.random.default_rng([seed, 1])
     out = []
     t = 0.0
     for rid in range(n):
@@ -60,6 +63,6 @@ def request_stream(n: int = 512, seed: int = 5, rate: float = math.inf,
         n_target = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
         sub_seed = int(rng.integers(0, 2 ** 31 - 1))
         if math.isfinite(rate):
-            t += float(rng.exponential(1.0 / rate))
+            t += float(arrivals.exponential(1.0 / rate))
         out.append(Request(rid, t if math.isfinite(rate) else 0.0, kind, params, n_target, sub_seed))
     return out

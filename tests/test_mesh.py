@@ -102,6 +102,11 @@ def test_refine_to_size_and_requests():
     assert all(reqs[k].arrival < reqs[k + 1].arrival for k in range(5))
     again = synth.request_stream(6, seed=5, rate=10.0)
     assert [(r.kind, r.n_target, r.seed) for r in reqs] == [(r.kind, r.n_target, r.seed) for r in again]
+    # the requests do not depend on the arrival rate (a Poisson run serves the
+    # same meshes as the saturated one)
+    sat = synth.request_stream(6, seed=5)
+    assert all(r.arrival == 0.0 for r in sat)
+    assert [(r.kind, r.params, r.n_target, r.seed) for r in reqs] == [(r.kind, r.params, r.n_target, r.seed) for r in sat]
     small = [r for r in reqs if r.n_target < 4000][:2]
     for r in small:
         mesh = r.build_mesh()
