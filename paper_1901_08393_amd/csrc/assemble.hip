@@ -32,7 +32,7 @@ namespace bc {
 // tensor rule's points (absolute coordinates, FP64), the inverse square root
 // refined by one Newton step (rsqrt64_far2).  Tiles at least kSepFar block
 // diameters apart expand -r^2 = -|x|^2 - |y|^2 + 2 x.y about the column
-// element's centroid (as in the FP32 kernel); closer tiles form differences.
+// element's centroid; closer tiles form differences.
 // Inverse square root for the FP64 far field: the hardware estimate y and one
 // Newton step, y (3 - x y^2) / 2, returned without the factor 1/2, which the
 // column weights carry: two multiplications and one FMA.  Measured over
@@ -146,12 +146,15 @@ __global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, 
 // amount).  What remains per point pair is rounding of either sign, about one
 // FP32 ulp, which the 256-term sums and the FP32 storage of V dominate.
 //
-// The kernel forms c = -r^2.  For tiles whose bounding boxes are at least
-// kSepFar block diameters apart it expands c = -|e|^2 - |y|^2 + 2 e.y with
-// e = c_i - c_j + x_a and y the offset of y_b from c_j, so that a point pair
-// costs one add and three FMAs; closer tiles form the differences.  At that
-// separation the expansion loses at most a few roundings of |e|^2 over
-// r^2 <= (1 + 1/kSepFar)^2 + 1/kSepFar^2.
+// The vector kernel (k_far32) forms r^2 from the differences e - y, e =
+// c_i - c_j + x_a and y the offset of y_b from c_j: three subtractions and
+// three multiply-adds per point pair.  Its tiles are the near and diagonal
+// ones and the separated tiles whose column block is not compact; separated
+// compact tiles go to the matrix cores (k_far32m).  (Expanding -r^2 =
+// -|e|^2 - |y|^2 + 2 e.y on the separated tiles here would save two
+// operations per point pair, but the kernel with both forms behind a branch
+// per tile was slower on every tile: L5 sphere assembly 3.45 against 3.31 ms
+// with differences alone.)
 
 // Mean relative error of v_rsq_f32 over inputs spread log-uniformly over
 // [1, 4) (the error depends only on the mantissa and the exponent's parity,
@@ -204,28 +207,25 @@ int launch_rsq_bias(void *mesh_ws, int64_t N, hipStream_t s) {
 template <int Q>
 __device__ __forceinline__ void far32_tile(int I, int J, const float4 *__restrict__ qpA,
                                            const float *__restrict__ qpS, const double4 *__restrict__ cen4,
-                                           const double *__restrict__ area, const double *__restrict__ bbox,
-                                           const double *__restrict__ rsqb, double scale, int N, int64_t ld,
-                                           float *__restrict__ V) {
+                                           const double *__restrict__ area, const double *__restrict__ rsqb,
+                                           double scale, int N, int64_t ld, float *__restrict__ V) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int j = J * 64 + lane;
   const bool jv = j < N;
   const int jj = jv ? j : N - 1;
-  float vx[Q], vy[Q], vz[Q], vw[Q], vn[Q];
+  float vx[Q], vy[Q], vz[Q], vw[Q];
 #pragma unroll
   for (int b = 0; b < Q; ++b) {
     vx[b] = qpS[(size_t)(b * 4 + 0) * N + jj];
     vy[b] = qpS[(size_t)(b * 4 + 1) * N + jj];
     vz[b] = qpS[(size_t)(b * 4 + 2) * N + jj];
     vw[b] = qpS[(size_t)(b * 4 + 3) * N + jj];
-    vn[b] = -(vx[b] * vx[b] + vy[b] * vy[b] + vz[b] * vz[b]);
   }
-  const bool sep = far_separated(bbox, I, J);
   const double4 cj = cen4[jj];
   const double aj = 4.0 * area[jj] * (scale / (1.0 + *rsqb));
   const int i0 = I * 64 + w * 16;
-  auto row = [&](auto SEP, int i) {
+  auto row = [&](int i) {
     const double4 ci = cen4[i];
     // centroid difference formed in FP64 and kept as hi + lo floats, so that
     // each point offset e = D_hi + (x_a + D_lo) is one rounding of D + x_a.
@@ -241,19 +241,11 @@ __device__ __forceinline__ void far32_tile(int I, int J, const float4 *__restric
     for (int a = 0; a < Q; ++a) {
       const float4 p = ua[a];
       const float ex = Dx + (p.x + Lx), ey = Dy + (p.y + Ly), ez = Dz + (p.z + Lz);
-      const float ne = -(ex * ex + ey * ey + ez * ez);
-      const float tx = 2.0f * ex, ty = 2.0f * ey, tz = 2.0f * ez;
       float s = 0.f;
 #pragma unroll
       for (int b = 0; b < Q; ++b) {
-        float c;  // -r^2
-        if constexpr (decltype(SEP)::value) {
-          c = __builtin_fmaf(tz, vz[b], __builtin_fmaf(ty, vy[b], __builtin_fmaf(tx, vx[b], ne + vn[b])));
-        } else {
-          const float dx = ex - vx[b], dy = ey - vy[b], dz = ez - vz[b];
-          c = -(dx * dx + dy * dy + dz * dz);
-        }
-        s = __builtin_fmaf(vw[b], __builtin_amdgcn_rsqf(-c), s);
+        const float dx = ex - vx[b], dy = ey - vy[b], dz = ez - vz[b];
+        s = __builtin_fmaf(vw[b], __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz), s);
       }
       acc = __builtin_fmaf(p.w, s, acc);
     }
@@ -266,7 +258,7 @@ __device__ __forceinline__ void far32_tile(int I, int J, const float4 *__restric
   for (int k = 0; k < 16; ++k) {
     const int i = i0 + k;
     if (i >= N) break;
-    if (sep) row(std::true_type{}, i); else row(std::false_type{}, i);
+    row(i);
   }
 }
 
@@ -275,13 +267,13 @@ __device__ __forceinline__ void far32_tile(int I, int J, const float4 *__restric
 template <int Q, bool LIST>
 __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, const float *__restrict__ qpS,
                                                const double4 *__restrict__ cen4, const double *__restrict__ area,
-                                               const double *__restrict__ bbox, const int32_t *__restrict__ cnt,
-                                               const int32_t *__restrict__ list, const double *__restrict__ rsqb,
-                                               double scale, int N, int64_t ld, float *__restrict__ V) {
+                                               const int32_t *__restrict__ cnt, const int32_t *__restrict__ list,
+                                               const double *__restrict__ rsqb, double scale, int N, int64_t ld,
+                                               float *__restrict__ V) {
   int I, J;
   if (!LIST) {
     tile_of(blockIdx.x, I, J);
-    far32_tile<Q>(I, J, qpA, qpS, cen4, area, bbox, rsqb, scale, N, ld, V);
+    far32_tile<Q>(I, J, qpA, qpS, cen4, area, rsqb, scale, N, ld, V);
     return;
   }
   const int nt = (int)far_tiles(N), n = min(*cnt, nt);
@@ -289,7 +281,7 @@ __global__ __launch_bounds__(kWG) void k_far32(const float4 *__restrict__ qpA, c
     const int t = list[q];
     if (t < 0 || t >= nt) continue;  // lists from another mesh: nothing out of range
     tile_of(t, I, J);
-    far32_tile<Q>(I, J, qpA, qpS, cen4, area, bbox, rsqb, scale, N, ld, V);
+    far32_tile<Q>(I, J, qpA, qpS, cen4, area, rsqb, scale, N, ld, V);
   }
 }
 
@@ -563,8 +555,8 @@ static void far_launch(bool mixed, bool low_order, const MeshView &m, int N, int
     radon7(rs, rt, rw);
     for (int a = 0; a < kQLow; ++a) wL.w[a] = (float)rw[a];
     const int gv = std::min(nt, 4 * cus), gm = std::min(nt, kFarMGrid * cus);
-    hipLaunchKernelGGL((k_far32<Q, true>), dim3(gv), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox, cnt,
-                       list, m.rsq_bias, scale, N, ld, static_cast<float *>(V));
+    hipLaunchKernelGGL((k_far32<Q, true>), dim3(gv), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, cnt, list,
+                       m.rsq_bias, scale, N, ld, static_cast<float *>(V));
     hipLaunchKernelGGL(k_far32m<16>, dim3(gm), dim3(kFarMWG), 0, s, m.qpA64, m.qpB16, w16, m.area, m.bbox, cnt + 1,
                        list + (size_t)nt, m.rsq_bias, scale, N, ld, static_cast<float *>(V));
     if (low_order)
@@ -575,7 +567,7 @@ static void far_launch(bool mixed, bool low_order, const MeshView &m, int N, int
       hipLaunchKernelGGL(k_far32m<16>, dim3(gm), dim3(kFarMWG), 0, s, m.qpA64, m.qpB16, w16, m.area, m.bbox, cnt + 2,
                          list + 2 * (size_t)nt, m.rsq_bias, scale, N, ld, static_cast<float *>(V));
   } else {
-    hipLaunchKernelGGL((k_far32<Q, false>), dim3(tiles), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area, m.bbox,
+    hipLaunchKernelGGL((k_far32<Q, false>), dim3(tiles), dim3(kWG), 0, s, m.qpA32, m.qpS32, m.cen4, m.area,
                        (const int32_t *)nullptr, (const int32_t *)nullptr, m.rsq_bias, scale, N, ld,
                        static_cast<float *>(V));
   }
