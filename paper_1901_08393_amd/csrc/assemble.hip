@@ -51,8 +51,11 @@ __device__ __forceinline__ double rsqrt64_far2(double x) {
 
 // One 64 x 64 tile (I, J), I <= J, with the Q-point rule whose points sit
 // STRIDE apart per element in the row table qpA ([N][STRIDE]) and in the
-// column table qpS ([(b*4+c)][N]).
-template <int Q, int STRIDE>
+// column table qpS ([(b*4+c)][N]).  FORM: 0 the form chosen per tile
+// (expansion on separated tiles), 1 differences, 2 the expansion (tiles known
+// to be separated).  A kernel with one form schedules better than one that
+// branches between them per tile.
+template <int Q, int STRIDE, int FORM>
 __device__ __forceinline__ void far64_tile(int I, int J, const double4 *__restrict__ qpA,
                                            const double *__restrict__ qpS, const double4 *__restrict__ cen4,
                                            const double *__restrict__ bbox, int N, int64_t ld, double *__restrict__ V) {
@@ -61,7 +64,7 @@ __device__ __forceinline__ void far64_tile(int I, int J, const double4 *__restri
   const int j = J * 64 + lane;
   const bool jv = j < N;
   const int jj = jv ? j : N - 1;
-  const bool sep = far_separated(bbox, I, J);
+  const bool sep = FORM == 0 ? far_separated(bbox, I, J) : FORM == 2;
   // column element's points relative to its centroid (separated tiles) or
   // absolute (close tiles)
   const double4 cj = cen4[jj];
@@ -108,13 +111,19 @@ __device__ __forceinline__ void far64_tile(int I, int J, const double4 *__restri
   for (int k = 0; k < 16; ++k) {
     const int i = i0 + k;
     if (i >= N) break;
-    if (sep) row(std::true_type{}, i); else row(std::false_type{}, i);
+    if constexpr (FORM == 1) {
+      row(std::false_type{}, i);
+    } else if constexpr (FORM == 2) {
+      row(std::true_type{}, i);
+    } else {
+      if (sep) row(std::true_type{}, i); else row(std::false_type{}, i);
+    }
   }
 }
 
 // One workgroup per tile of the upper block triangle, or (LIST) the tiles of
 // one list from bc_prepare, visited grid-stride.
-template <int Q, int STRIDE, bool LIST>
+template <int Q, int STRIDE, bool LIST, int FORM>
 __global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, const double *__restrict__ qpS,
                                                const double4 *__restrict__ cen4, const double *__restrict__ bbox,
                                                const int32_t *__restrict__ cnt, const int32_t *__restrict__ list,
@@ -122,7 +131,7 @@ __global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, 
   int I, J;
   if (!LIST) {
     tile_of(blockIdx.x, I, J);
-    far64_tile<Q, STRIDE>(I, J, qpA, qpS, cen4, bbox, N, ld, V);
+    far64_tile<Q, STRIDE, FORM>(I, J, qpA, qpS, cen4, bbox, N, ld, V);
     return;
   }
   const int nt = (int)far_tiles(N), n = min(*cnt, nt);
@@ -130,7 +139,7 @@ __global__ __launch_bounds__(kWG) void k_far64(const double4 *__restrict__ qpA, 
     const int t = list[q];
     if (t < 0 || t >= nt) continue;  // lists from another mesh: nothing out of range
     tile_of(t, I, J);
-    far64_tile<Q, STRIDE>(I, J, qpA, qpS, cen4, bbox, N, ld, V);
+    far64_tile<Q, STRIDE, FORM>(I, J, qpA, qpS, cen4, bbox, N, ld, V);
   }
 }
 
@@ -525,17 +534,20 @@ template <int Q>
 static void far_launch(bool mixed, bool low_order, const MeshView &m, int N, int64_t ld, void *V, int tiles,
                        double scale, hipStream_t s) {
   if (!mixed && !(low_order && Q == 16)) {
-    hipLaunchKernelGGL((k_far64<Q, kQMax, false>), dim3(tiles), dim3(kWG), 0, s, m.qpA64, m.qpS64, m.cen4, m.bbox,
+    hipLaunchKernelGGL((k_far64<Q, kQMax, false, 0>), dim3(tiles), dim3(kWG), 0, s, m.qpA64, m.qpS64, m.cen4, m.bbox,
                        (const int32_t *)nullptr, (const int32_t *)nullptr, N, ld, static_cast<double *>(V));
   } else if (!mixed) {
     // FP64 with Radon's rule on the tiles at least kSepFarLow64 diameters
     // apart (class 2 of bc_prepare's lists); the 4 x 4 rule on the others
     const int nt = (int)far_tiles(N);
     const int g = std::min(nt, 4 * device_cus());
-    for (int c = 0; c < 2; ++c)
-      hipLaunchKernelGGL((k_far64<16, kQMax, true>), dim3(g), dim3(kWG), 0, s, m.qpA64, m.qpS64, m.cen4, m.bbox,
-                         m.tile_cnt + c, m.tile_list + (size_t)c * nt, N, ld, static_cast<double *>(V));
-    hipLaunchKernelGGL((k_far64<kQLow, kQLow, true>), dim3(g), dim3(kWG), 0, s, m.qpLA64, m.qpLS64, m.cen4, m.bbox,
+    // (class 0: near, diagonal and separated non-compact tiles, differences;
+    // classes 1 and 2 are separated, the expansion)
+    hipLaunchKernelGGL((k_far64<16, kQMax, true, 1>), dim3(g), dim3(kWG), 0, s, m.qpA64, m.qpS64, m.cen4, m.bbox,
+                       m.tile_cnt, m.tile_list, N, ld, static_cast<double *>(V));
+    hipLaunchKernelGGL((k_far64<16, kQMax, true, 2>), dim3(g), dim3(kWG), 0, s, m.qpA64, m.qpS64, m.cen4, m.bbox,
+                       m.tile_cnt + 1, m.tile_list + (size_t)nt, N, ld, static_cast<double *>(V));
+    hipLaunchKernelGGL((k_far64<kQLow, kQLow, true, 2>), dim3(g), dim3(kWG), 0, s, m.qpLA64, m.qpLS64, m.cen4, m.bbox,
                        m.tile_cnt + 2, m.tile_list + 2 * (size_t)nt, N, ld, static_cast<double *>(V));
   } else if (Q == 16) {
     // Each tile class on its own kernel, over the tile lists of bc_prepare:
